@@ -1,0 +1,109 @@
+"""ctypes front end of the C oracle (``synth.c``).
+
+TEST INFRASTRUCTURE (see the package docstring). ``build()`` compiles synth.c
+with gcc into ``oracle/_synth.so``; ``synth()`` packs a ``words.Plan`` into the
+C records and runs the FP64 direct sum with OpenMP.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import words
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "synth.c")
+_LIB = os.path.join(_HERE, "_synth.so")
+
+
+class _Ramp(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("p_line", ctypes.c_uint64), ("f_line", ctypes.c_uint64),
+                ("p_after", ctypes.c_uint64), ("f_after", ctypes.c_uint64),
+                ("coef", ctypes.c_int64), ("table", ctypes.c_void_p),
+                ("shape", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class _Tone(ctypes.Structure):
+    _fields_ = [("p0", ctypes.c_uint64), ("f0", ctypes.c_uint64), ("amp", ctypes.c_double),
+                ("first_ramp", ctypes.c_int32), ("n_ramps", ctypes.c_int32)]
+
+
+def build(force=True):
+    """Compile synth.c (gcc, C99, OpenMP, no FMA contraction)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-std=c99", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                           "-shared", "-Wall", _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_synth.argtypes = [ctypes.POINTER(_Tone), ctypes.c_int32, ctypes.POINTER(_Ramp),
+                                     ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int32]
+        lib.oracle_synth.restype = None
+        lib.oracle_phases.argtypes = [ctypes.POINTER(_Tone), ctypes.POINTER(_Ramp), ctypes.c_uint64,
+                                      ctypes.c_int64, ctypes.c_void_p]
+        lib.oracle_phases.restype = None
+        _lib = lib
+    return _lib
+
+
+class Packed:
+    """A Plan flattened into C records; keeps the tables alive."""
+
+    def __init__(self, plan):
+        n_ramps = sum(len(t.ramps) for t in plan.tones)
+        self.tones = (_Tone * max(1, len(plan.tones)))()
+        self.ramps = (_Ramp * max(1, n_ramps))()
+        self.keep = []
+        j = 0
+        for k, t in enumerate(plan.tones):
+            ct = self.tones[k]
+            ct.p0, ct.f0, ct.amp = t.p0, t.f0, t.amp
+            ct.first_ramp, ct.n_ramps = j, len(t.ramps)
+            for r in t.ramps:
+                cr = self.ramps[j]
+                cr.a, cr.n = r.a, r.N
+                cr.p_line, cr.f_line = r.p_line, r.f_line
+                cr.p_after, cr.f_after = r.p_after, r.f_after
+                cr.coef, cr.shape = r.coef, r.shape
+                if r.shape in words.SMOOTH_SHAPES:
+                    tab = r.table if r.table is not None else words.ramp_table(r.shape, r.N)
+                    tab = np.ascontiguousarray(tab, dtype=np.uint64)
+                    self.keep.append(tab)
+                    cr.table = tab.ctypes.data
+                j += 1
+        self.n_tones = len(plan.tones)
+
+
+def synth(plan, n0, count, threads=0, packed=None):
+    """(q int16[count], y float64[count]) for samples n0 .. n0+count-1."""
+    lib = _load()
+    pk = packed if packed is not None else Packed(plan)
+    q = np.empty(int(count), dtype=np.int16)
+    y = np.empty(int(count), dtype=np.float64)
+    lib.oracle_synth(pk.tones, pk.n_tones, pk.ramps, int(n0), int(count),
+                     q.ctypes.data, y.ctypes.data, int(threads))
+    return q, y
+
+
+def phases(plan, k, n0, count, packed=None):
+    """Exact phase words of tone k for samples n0 .. n0+count-1 (uint64)."""
+    lib = _load()
+    pk = packed if packed is not None else Packed(plan)
+    out = np.empty(int(count), dtype=np.uint64)
+    tone = ctypes.pointer(pk.tones[k])
+    lib.oracle_phases(tone, pk.ramps, int(n0), int(count), out.ctypes.data)
+    return out
