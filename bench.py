@@ -1,0 +1,183 @@
+"""Benchmark of the synthesis hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--method auto|direct|mfma-f16|mfma-bf16]
+
+Workload (the configuration the headline metric is quoted on): one period of a
+static 1000-tone buffer, L = 2^24 samples at fs = 280 MS/s, bins in 60-140 MHz,
+amplitudes U[0.5, 1], Schroeder phases, default gain (seeded, synthetic). A step
+is one awg_synth_static call over the whole buffer into a resident int16 buffer
+(exact phase words, sinusoids, weighted sum, int16 epilogue). The timed region
+is K steps between device synchronisations; value = tones * samples / time.
+
+Also reported:
+  roofline      the dominant kernel's algorithmic rate against the MI355X peak
+  cpu_baseline  the CPU oracle (FP64 direct sum) on a bounded contiguous sample of
+                the same buffer, on this host's cores; its outputs also give the
+                int16 error of the GPU result on that sample
+  streaming     a chirped stream (1000 tones, 35 ms linear/cosine ramps, 2^20-sample
+                chunks): per-chunk latency p50/p99 and real-time factor
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tone-samples/s + real-time factor at 280 MS/s (int16, <=1 LSB); p99 chunk latency"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP16_TFLOPS = 2500.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--method", default="auto", choices=["auto", "direct", "mfma-f16", "mfma-bf16"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    return ap.parse_args()
+
+
+def timed_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(w, q_gpu, seconds):
+    """Oracle FP64 direct sum on a contiguous sample of the buffer (CPU, all cores)."""
+    from oracle import words, csynth
+    op = words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones)
+    pk = csynth.Packed(op)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    probe = 4096
+    t0 = time.perf_counter()
+    csynth.synth(op, 0, probe, threads=threads, packed=pk)
+    dt = time.perf_counter() - t0
+    count = int(min(w.count, max(probe, probe * seconds / max(dt, 1e-6))))
+    start = int(np.random.default_rng(99).integers(0, w.count - count + 1))
+    t0 = time.perf_counter()
+    qo, yo = csynth.synth(op, start, count, threads=threads, packed=pk)
+    dt = time.perf_counter() - t0
+    ts = len(w.tones) * count
+    dq = int(np.max(np.abs(q_gpu[start:start + count].astype(np.int32) - qo.astype(np.int32))))
+    return {"value": ts / dt, "unit": "tone-samples/s", "cores": threads, "kind": "oracle",
+            "sample": "samples [%d, %d) of the %d-sample buffer, all %d tones (%.1f s)"
+                      % (start, start + count, w.count, len(w.tones), dt),
+            "max_dq_lsb_vs_gpu": dq}
+
+
+def streaming_leg(torch, awg, W):
+    """Config-3 style chirped stream: per-chunk latency and real-time factor."""
+    w = W.config3(shape="mixed")
+    plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2)
+    s = torch.cuda.current_stream()
+    n_chunks = w.count // w.chunk
+    buf = [torch.empty(w.chunk, dtype=torch.int16, device="cuda") for _ in range(2)]
+    for c in range(2):                       # warm-up
+        plan.stream_next(w.chunk, out=buf[c % 2])
+    plan.seek(0)
+    lat = []
+    for rep in range(3):
+        plan.seek(0)
+        evs = []
+        for c in range(n_chunks):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            plan.stream_next(w.chunk, out=buf[c % 2])
+            e1.record(s)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        lat += [a.elapsed_time(b) for a, b in evs]
+    lat = np.array(lat)
+    chunk_s = w.chunk / w.fs_hz
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+    plan.close()
+    return {"workload": w.name, "tones": len(w.tones), "chunk": w.chunk, "chunks": int(len(lat)),
+            "p50_chunk_ms": p50, "p99_chunk_ms": p99,
+            "tone_samples_per_s": len(w.tones) * w.chunk / (float(np.mean(lat)) * 1e-3),
+            "rtf_p99": chunk_s / (p99 * 1e-3), "rtf_mean": chunk_s / (float(np.mean(lat)) * 1e-3),
+            "latency_note": "device time per 2^20-sample chunk (hipEvents on the launch stream)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the synthesis on a single "
+              "MI355X (see the sharding notes in DESIGN.md); --gpus %d is not supported" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2403_15582_amd as awg
+    from paper_2403_15582_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    w = W.config2()
+    K, L = len(w.tones), w.count
+    methods = {"direct": awg.AWG_F_METHOD_DIRECT, "mfma-f16": awg.AWG_F_METHOD_MFMA_F16X3,
+               "mfma-bf16": awg.AWG_F_METHOD_MFMA_BF16X3}
+    method = "direct" if a.method == "auto" else a.method
+    log("workload", w.name, "method", method)
+    plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, methods[method])
+    out = torch.empty(L, dtype=torch.int16, device="cuda")
+
+    def step():
+        plan.synth_static(0, L, out=out)
+
+    ms, wall = timed_steps(torch, step, a.steps, a.warmup)
+    value = K * L / (ms * 1e-3)
+    log("ms/step %.3f  tone-samples/s %.3e  (wall %.2f s)" % (ms, value, wall))
+
+    # dominant kernel: the direct kernel is the whole step (one launch)
+    kernel_ms = ms
+    alg_flop = 2.0 * K * L                  # one FMA per tone-sample
+    achieved = alg_flop / (kernel_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "direct_kernel", "achieved": achieved,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": None,
+                "note": "2 algorithmic flop per tone-sample (the weighting FMA) over the FP32 vector "
+                        "peak; the kernel is bound by VALU issue incl. one v_sin_f32 per tone-sample"}
+
+    q_gpu = out.cpu().numpy()
+    res = {"metric": METRIC, "value": value, "unit": "tone-samples/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "tones": K, "samples": L, "fs_hz": w.fs_hz,
+                      "method": method, "output": "int16"},
+           "rtf": (L / w.fs_hz) / (ms * 1e-3),
+           "roofline": roofline}
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        res["cpu_baseline"] = cpu_baseline(w, q_gpu, a.cpu_seconds)
+    if not a.no_stream:
+        log("streaming leg ...")
+        res["streaming"] = streaming_leg(torch, awg, W)
+    plan.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

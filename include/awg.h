@@ -1,0 +1,213 @@
+/*
+ * awg.h -- C ABI of the MI355X multi-tone additive-synthesis library.
+ *
+ * The library computes the discretised multi-tone waveform of the paper's
+ * Theory section,
+ *
+ *     V[n] = Q( sum_k A_k sin(phi_k(n)) ),                     Eqs. (2), (5)-(7)
+ *
+ * for static tones (phi_k(n) = theta_k + 2 pi f_k n / fs, frequencies snapped to
+ * the bins of a period L when one is given, Eq. (4)) and for chirped tones whose
+ * frequency follows a linear, raised-cosine or minimum-jerk trajectory inside a
+ * ramp window and is constant outside it (Eq. (8)). Q scales by a gain G (LSB
+ * per unit amplitude), rounds half-to-even and saturates to int16 DAC codes.
+ *
+ * Phases are exact 64-bit fixed-point words (one turn = 2^64); the sinusoid and
+ * the sum over tones run in FP32 on the GPU (or FP16 split operands with FP32
+ * accumulation on the matrix cores for static tones).
+ *
+ * Conventions for every call:
+ *  - All functions return an awg_status; none aborts and no C++ exception
+ *    crosses this boundary.
+ *  - "d_" pointers are device pointers on the context's device, owned by the
+ *    caller; all other pointers are host pointers, owned by the caller.
+ *  - hip_stream is a hipStream_t (NULL = the legacy default stream). Synthesis
+ *    calls only enqueue work; results are valid once the stream has synchronised.
+ *  - A plan may be used from several threads for awg_synth_* calls (they only
+ *    read it); awg_stream_* and awg_plan_retune need one caller at a time.
+ */
+#ifndef AWG_H
+#define AWG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct awg_ctx awg_ctx;     /* one HIP device */
+typedef struct awg_plan awg_plan;   /* one tone set with its device tables */
+
+typedef enum {
+    AWG_OK = 0,
+    AWG_E_INVALID = -1,      /* bad argument (null pointer, NaN, f outside (0, fs/2), ...) */
+    AWG_E_NOMEM = -2,        /* host or device allocation failed */
+    AWG_E_HIP = -3,          /* a HIP runtime call failed (also: no device) */
+    AWG_E_RANGE = -4,        /* sample range overflow, bin on 0 or L/2, ramp too long */
+    AWG_E_UNSUPPORTED = -5,  /* valid request the chosen call does not handle */
+    AWG_E_BUSY = -6          /* resource temporarily exhausted (server admission) */
+} awg_status;
+
+/* Frequency trajectory inside a ramp window of N samples, tau = d / N in [0, 1]:
+ *   LINEAR  f = f0 + df * tau
+ *   COSINE  f = f0 + df * (1 - cos(pi tau)) / 2
+ *   MINJERK f = f0 + df * (10 tau^3 - 15 tau^4 + 6 tau^5)          (Eq. (8)) */
+typedef enum {
+    AWG_RAMP_NONE = 0,
+    AWG_RAMP_LINEAR = 1,
+    AWG_RAMP_COSINE = 2,
+    AWG_RAMP_MINJERK = 3
+} awg_ramp;
+
+/* One tone (56 bytes). Static tones use f_start_hz only. A ramped tone is static
+ * at f_start_hz before sample ramp_start, sweeps to f_end_hz over the window
+ * [ramp_start, ramp_start + ramp_len], and holds f_end_hz afterwards with the
+ * phase it reached (Eq. (8) cases 1-3). phase_turns is theta in turns. */
+typedef struct {
+    double f_start_hz;
+    double f_end_hz;
+    double amplitude;        /* A_k >= 0, in units of the gain */
+    double phase_turns;      /* theta_k / (2 pi) */
+    uint64_t ramp_start;     /* absolute sample index a */
+    uint64_t ramp_len;       /* N, 1 <= N < 2^31 for ramped tones */
+    int32_t ramp;            /* awg_ramp */
+    int32_t reserved;        /* must be 0 */
+} awg_tone;
+
+/* Static-synthesis method, flags bits 0-1. */
+#define AWG_F_METHOD_DIRECT      0u   /* VALU: exact phase word, v_sin, FP32 FMA sum */
+#define AWG_F_METHOD_MFMA_F16X3  1u   /* matrix cores: angle addition, FP16 hi/lo x3 */
+#define AWG_F_METHOD_MFMA_BF16X3 2u   /* matrix cores: angle addition, BF16 hi/lo x3 */
+#define AWG_F_METHOD_MASK        3u
+
+typedef struct {
+    double fs_hz;            /* sample rate, > 0 */
+    double gain_lsb;         /* G in LSB per unit amplitude; 0 = 32767 / sum A_k (never clips) */
+    uint32_t period_log2;    /* p > 0: snap every frequency to a bin of L = 2^p (Eq. (4)); 0: none */
+    uint32_t flags;          /* AWG_F_METHOD_* */
+} awg_plan_params;
+
+typedef struct {
+    int32_t n_tones;
+    int32_t n_ramped;        /* tones with a ramp window */
+    double gain_lsb;         /* the gain in use */
+    uint32_t flags;
+    uint32_t period_log2;
+    uint64_t cursor;         /* next sample of awg_stream_next */
+    uint64_t device_bytes;   /* device memory held by the plan (tables, workspaces) */
+} awg_plan_info;
+
+/* A new chirp appended to one tone of a plan (retuning a running stream). The
+ * tone leaves the line it is on at sample ramp_start (which must not precede
+ * the end of its previous window) and sweeps to f_end_hz over ramp_len samples. */
+typedef struct {
+    int32_t tone;
+    int32_t ramp;            /* AWG_RAMP_LINEAR / COSINE / MINJERK */
+    uint64_t ramp_start;
+    uint64_t ramp_len;
+    double f_end_hz;
+} awg_retune;
+
+/* ---------------------------------------------------------------- context */
+
+/* Binds HIP device `device`. Fails with AWG_E_HIP when there is no such device. */
+awg_status awg_ctx_create(int device, awg_ctx **out);
+void awg_ctx_destroy(awg_ctx *ctx);
+
+/* ------------------------------------------------------------------- plan */
+
+/* Plan a tone set (initialisation state of the Software section: all
+ * parameters are converted and uploaded once, no per-call host traffic).
+ *
+ * Per tone: frequency words F = nint(f 2^64 / fs), or with period_log2 = p the
+ * bin j = nint(f L / fs) (Eq. (4)) and F = j 2^(64-p); phase word
+ * P = nint(theta 2^64) mod 2^64; for ramps the chirp coefficient (linear:
+ * R = nint((F1-F0)/N); smooth: dF = F1-F0 and the shared table
+ * H_N[d] = nint(2^16 N Psi(d/N))) and the line after the window. All rounding
+ * is half-to-even and exact (no floating-point shortcuts).
+ *
+ * ctx may be NULL: the plan is then host-only (words and tables only, for
+ * inspection with awg_plan_words); synthesis calls on it return AWG_E_INVALID.
+ * f_quantised_hz (nullable, n_tones entries) receives F * fs / 2^64 per tone.
+ * Errors: AWG_E_INVALID for null tones/out/params, n_tones <= 0, fs not finite
+ * and > 0, gain < 0 or not finite, non-finite tone fields, amplitude < 0,
+ * unknown ramp, reserved != 0, period_log2 == 1 or > 63, f not in (0, fs/2),
+ * all amplitudes 0 with gain 0; AWG_E_RANGE for a bin on 0 or L/2, ramp_len 0 or
+ * >= 2^31, ramp_start + ramp_len >= 2^63; AWG_E_NOMEM / AWG_E_HIP on upload. */
+awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg_tone *tones,
+                          int32_t n_tones, awg_plan **out, double *f_quantised_hz);
+void awg_plan_destroy(awg_plan *plan);
+awg_status awg_plan_info_get(const awg_plan *plan, awg_plan_info *info);
+
+/* Words of every tone (host arrays of n_tones entries, each nullable): initial
+ * phase P0, start and end frequency words F0, F1, and the chirp coefficient (R
+ * for linear ramps, dF for smooth ones, 0 for static tones). After retuning
+ * these describe the most recent ramp of each tone (P0 = line before it). */
+awg_status awg_plan_words(const awg_plan *plan, uint64_t *p0, uint64_t *f0, uint64_t *f1,
+                          int64_t *coef);
+
+/* H_N[0..N] of a smooth ramp shape into out (host, N+1 entries): minimum jerk
+ * exactly nint(2^15 d^4 (5N^2 - 6dN + 2d^2) / N^5); raised cosine
+ * 2^15 d - nint(((32768 N) / pi) * sin((pi d) / N)) in FP64 in that order.
+ * AWG_E_INVALID for other shapes, AWG_E_RANGE for N = 0 or N >= 2^31. */
+awg_status awg_ramp_table(int32_t shape, uint64_t n, uint64_t *out);
+
+/* Append chirps to tones of a planned stream (Streaming pathway with groups of
+ * tones chirped in turn). The device tables are updated in stream order on
+ * hip_stream: synthesis enqueued earlier on that stream sees the old tones,
+ * synthesis enqueued later the new ones. A tone keeps one window on the device,
+ * so after a retune its samples are exact from the end of its previous window
+ * on (the new window must not start earlier); samples before that end are no
+ * longer reproducible from this plan. At most one event per tone per call.
+ * AWG_E_INVALID for a bad tone index or shape, AWG_E_RANGE for a window that
+ * starts before the tone's previous window ends or is too long,
+ * AWG_E_UNSUPPORTED for two events on one tone or more than 16384 events. */
+awg_status awg_plan_retune(awg_plan *plan, const awg_retune *events, int32_t n_events,
+                           void *hip_stream);
+
+/* -------------------------------------------------------------- synthesis */
+
+/* Static pathway: samples n0 .. n0+count-1 of a plan without ramp windows into
+ * d_out (int16, count entries). The method comes from the plan's flags.
+ * AWG_E_UNSUPPORTED if the plan has ramps; AWG_E_RANGE if n0 + count >= 2^63. */
+awg_status awg_synth_static(awg_plan *plan, uint64_t n0, uint64_t count, int16_t *d_out,
+                            void *hip_stream);
+
+/* Playback pathway: any sample range of any plan (static or chirped) with the
+ * direct method. count = 0 is a no-op. */
+awg_status awg_synth_chirp(awg_plan *plan, uint64_t n0, uint64_t count, int16_t *d_out,
+                           void *hip_stream);
+
+/* Streaming pathway: the next count samples after the plan's cursor into d_out,
+ * then advance the cursor. *n0_out (nullable) receives the first sample index.
+ * Results are bit-identical to awg_synth_chirp over the same range: the phase is
+ * a closed form in the absolute sample index and the sum order depends on the
+ * plan only. */
+awg_status awg_stream_next(awg_plan *plan, uint64_t count, int16_t *d_out, void *hip_stream,
+                           uint64_t *n0_out);
+/* Cursor access for checkpoint / resume: (plan inputs, cursor) restore a stream. */
+awg_status awg_stream_seek(awg_plan *plan, uint64_t n0);
+awg_status awg_stream_tell(const awg_plan *plan, uint64_t *n0);
+
+/* Unquantised sum y[n] (FP32, LSB units) for error reporting: the same kernels
+ * as the int16 calls with the rounding left out. method: AWG_F_METHOD_* (MFMA
+ * methods only for static plans). */
+awg_status awg_synth_f32(awg_plan *plan, uint32_t method, uint64_t n0, uint64_t count,
+                         float *d_y, void *hip_stream);
+
+/* Phase words of one tone as the direct kernel generates them (same code path,
+ * same sample-to-lane mapping), for exact comparison: d_words[i] = phi(n0 + i). */
+awg_status awg_phase_dump(awg_plan *plan, int32_t tone, uint64_t n0, uint64_t count,
+                          uint64_t *d_words, void *hip_stream);
+
+/* ------------------------------------------------------------------- misc */
+
+const char *awg_strerror(awg_status status);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t awg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AWG_H */

@@ -56,6 +56,10 @@ def _load():
         lib.oracle_phases.argtypes = [ctypes.POINTER(_Tone), ctypes.POINTER(_Ramp), ctypes.c_uint64,
                                       ctypes.c_int64, ctypes.c_void_p]
         lib.oracle_phases.restype = None
+        lib.oracle_synth_at.argtypes = [ctypes.POINTER(_Tone), ctypes.c_int32, ctypes.POINTER(_Ramp),
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int32]
+        lib.oracle_synth_at.restype = None
         _lib = lib
     return _lib
 
@@ -97,6 +101,44 @@ def synth(plan, n0, count, threads=0, packed=None):
     lib.oracle_synth(pk.tones, pk.n_tones, pk.ramps, int(n0), int(count),
                      q.ctypes.data, y.ctypes.data, int(threads))
     return q, y
+
+
+def synth_at(plan, ns, threads=0, packed=None):
+    """(q, y) at the absolute sample indices ``ns``."""
+    lib = _load()
+    pk = packed if packed is not None else Packed(plan)
+    ns = np.ascontiguousarray(ns, dtype=np.uint64)
+    q = np.empty(len(ns), dtype=np.int16)
+    y = np.empty(len(ns), dtype=np.float64)
+    lib.oracle_synth_at(pk.tones, pk.n_tones, pk.ramps, ns.ctypes.data, len(ns),
+                        q.ctypes.data, y.ctypes.data, int(threads))
+    return q, y
+
+
+def sparse_tables(plan, ns):
+    """Give every smooth ramp without a table one that holds only the entries
+    the samples ``ns`` read (computed exactly by words.ramp_table_entries);
+    lets the C sum run at sampled points of very long ramps."""
+    ns = np.asarray(ns, dtype=np.int64)
+    for tw in plan.tones:
+        for r in tw.ramps:
+            if r.shape not in words.SMOOTH_SHAPES:
+                continue
+            if r.table is not None and not getattr(r, "sparse", False):
+                continue
+            ds = ns - r.a
+            ds = np.unique(ds[(ds >= 0) & (ds <= r.N)])
+            key = (r.shape, r.N)
+            cache = plan.__dict__.setdefault("_sparse", {})
+            if key not in cache:
+                cache[key] = (np.zeros(r.N + 1, dtype=np.uint64), set())
+            tab, have = cache[key]
+            need = [int(d) for d in ds if int(d) not in have]
+            if need:
+                tab[need] = words.ramp_table_entries(r.shape, r.N, need)
+                have.update(need)
+            r.table = tab
+            r.sparse = True
 
 
 def phases(plan, k, n0, count, packed=None):

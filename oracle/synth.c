@@ -93,3 +93,26 @@ void oracle_phases(const oracle_tone *t, const oracle_ramp *ramps, uint64_t n0, 
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < count; ++i) out[i] = oracle_phase_at(t, ramps, n0 + (uint64_t)i);
 }
+
+/* Same as oracle_synth at an arbitrary list of absolute sample indices. */
+void oracle_synth_at(const oracle_tone *tones, int32_t n_tones, const oracle_ramp *ramps,
+                     const uint64_t *ns, int64_t count, int16_t *q, double *y, int32_t threads)
+{
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < count; ++i) {
+        const uint64_t n = ns[i];
+        double acc = 0.0;
+        for (int32_t k = 0; k < n_tones; ++k) {
+            uint64_t w = oracle_phase_at(&tones[k], ramps, n);
+            double turns = (double)(int64_t)w * 0x1p-64;
+            acc += tones[k].amp * sin(two_pi * turns);
+        }
+        double r = nearbyint(acc);
+        if (r > 32767.0) r = 32767.0;
+        if (r < -32768.0) r = -32768.0;
+        y[i] = acc;
+        q[i] = (int16_t)r;
+    }
+}

@@ -1,1 +1,308 @@
-"""MI355X-native multi-tone additive synthesis (placeholder, binding added below)."""
+"""MI355X-native multi-tone additive synthesis (arXiv 2403.15582 hot path).
+
+Python binding of ``libawg.so`` (declared in ``include/awg.h``). The functions
+named ``awg_*`` mirror the C entry points one to one and only marshal
+arguments: every step of the synthesis runs in the library's HIP kernels.
+Device buffers are passed as integer device pointers (e.g. a torch tensor's
+``data_ptr()``) and streams as ``hipStream_t`` integers (``torch.cuda.Stream
+.cuda_stream``); ``Plan`` adds a little convenience on top for callers that use
+torch for device memory.
+
+The library must have been built (``python -m paper_2403_15582_amd.build``);
+importing a function when it is missing raises ``ImportError`` -- there is no
+fallback implementation.
+"""
+import atexit
+import ctypes
+import os
+
+import numpy as np
+
+from .abi_types import (AWG_OK, AWG_E_INVALID, AWG_E_NOMEM, AWG_E_HIP, AWG_E_RANGE,  # noqa: F401
+                        AWG_E_UNSUPPORTED, AWG_E_BUSY, RAMP_NONE, RAMP_LINEAR, RAMP_COSINE,
+                        RAMP_MINJERK, AWG_F_METHOD_DIRECT, AWG_F_METHOD_MFMA_F16X3,
+                        AWG_F_METHOD_MFMA_BF16X3, TONE_DTYPE, make_tones)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libawg.so")
+
+EXPORTED = [
+    "awg_ctx_create", "awg_ctx_destroy", "awg_plan_tones", "awg_plan_destroy",
+    "awg_plan_info_get", "awg_plan_words", "awg_ramp_table", "awg_plan_retune",
+    "awg_synth_static", "awg_synth_chirp", "awg_stream_next", "awg_stream_seek",
+    "awg_stream_tell", "awg_synth_f32", "awg_phase_dump", "awg_strerror", "awg_version",
+]
+
+
+class AwgError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, awg_strerror(status), status))
+
+
+class awg_plan_params(ctypes.Structure):
+    _fields_ = [("fs_hz", ctypes.c_double), ("gain_lsb", ctypes.c_double),
+                ("period_log2", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class awg_plan_info(ctypes.Structure):
+    _fields_ = [("n_tones", ctypes.c_int32), ("n_ramped", ctypes.c_int32),
+                ("gain_lsb", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("period_log2", ctypes.c_uint32), ("cursor", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+class awg_retune(ctypes.Structure):
+    _fields_ = [("tone", ctypes.c_int32), ("ramp", ctypes.c_int32),
+                ("ramp_start", ctypes.c_uint64), ("ramp_len", ctypes.c_uint64),
+                ("f_end_hz", ctypes.c_double)]
+
+
+_lib = None
+_exiting = False
+_VP = ctypes.c_void_p
+
+
+@atexit.register
+def _mark_exit():
+    # plans still alive at interpreter exit are left to the OS: the HIP runtime
+    # may already be tearing down when their finalizers would run
+    global _exiting
+    _exiting = True
+
+_U64 = ctypes.c_uint64
+_I32 = ctypes.c_int32
+
+
+def lib():
+    """The loaded libawg (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libawg.so is not built; run python -m paper_2403_15582_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "awg_ctx_create": ([ctypes.c_int, ctypes.POINTER(_VP)], _I32),
+        "awg_ctx_destroy": ([_VP], None),
+        "awg_plan_tones": ([_VP, ctypes.POINTER(awg_plan_params), _VP, _I32, ctypes.POINTER(_VP), _VP], _I32),
+        "awg_plan_destroy": ([_VP], None),
+        "awg_plan_info_get": ([_VP, ctypes.POINTER(awg_plan_info)], _I32),
+        "awg_plan_words": ([_VP, _VP, _VP, _VP, _VP], _I32),
+        "awg_ramp_table": ([_I32, _U64, _VP], _I32),
+        "awg_plan_retune": ([_VP, ctypes.POINTER(awg_retune), _I32, _VP], _I32),
+        "awg_synth_static": ([_VP, _U64, _U64, _VP, _VP], _I32),
+        "awg_synth_chirp": ([_VP, _U64, _U64, _VP, _VP], _I32),
+        "awg_stream_next": ([_VP, _U64, _VP, _VP, ctypes.POINTER(_U64)], _I32),
+        "awg_stream_seek": ([_VP, _U64], _I32),
+        "awg_stream_tell": ([_VP, ctypes.POINTER(_U64)], _I32),
+        "awg_synth_f32": ([_VP, ctypes.c_uint32, _U64, _U64, _VP, _VP], _I32),
+        "awg_phase_dump": ([_VP, _I32, _U64, _U64, _VP, _VP], _I32),
+        "awg_strerror": ([_I32], ctypes.c_char_p),
+        "awg_version": ([], _I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(status, what):
+    if status != AWG_OK:
+        raise AwgError(status, what)
+
+
+def awg_strerror(status):
+    return lib().awg_strerror(int(status)).decode()
+
+
+def awg_version():
+    return int(lib().awg_version())
+
+
+def awg_ctx_create(device=0):
+    h = _VP()
+    _check(lib().awg_ctx_create(int(device), ctypes.byref(h)), "awg_ctx_create")
+    return h.value
+
+
+def awg_ctx_destroy(ctx):
+    if ctx:
+        lib().awg_ctx_destroy(ctx)
+
+
+def awg_plan_tones(ctx, fs_hz, gain_lsb, period_log2, flags, tones):
+    """Plan ``tones`` (TONE_DTYPE array). Returns (plan handle, quantised Hz)."""
+    t = np.ascontiguousarray(tones, dtype=TONE_DTYPE)
+    p = awg_plan_params(float(fs_hz), float(gain_lsb), int(period_log2), int(flags))
+    fq = np.empty(len(t), dtype=np.float64)
+    h = _VP()
+    _check(lib().awg_plan_tones(ctx, ctypes.byref(p), t.ctypes.data, len(t), ctypes.byref(h),
+                                fq.ctypes.data), "awg_plan_tones")
+    return h.value, fq
+
+
+def awg_plan_destroy(plan):
+    if plan:
+        lib().awg_plan_destroy(plan)
+
+
+def awg_plan_info_get(plan):
+    info = awg_plan_info()
+    _check(lib().awg_plan_info_get(plan, ctypes.byref(info)), "awg_plan_info_get")
+    return {f: getattr(info, f) for f, _ in awg_plan_info._fields_}
+
+
+def awg_plan_words(plan, n_tones):
+    out = {k: np.empty(n_tones, dtype=np.uint64) for k in ("p0", "f0", "f1")}
+    out["coef"] = np.empty(n_tones, dtype=np.int64)
+    _check(lib().awg_plan_words(plan, out["p0"].ctypes.data, out["f0"].ctypes.data,
+                                out["f1"].ctypes.data, out["coef"].ctypes.data), "awg_plan_words")
+    return out
+
+
+def awg_ramp_table(shape, n):
+    out = np.empty(int(n) + 1, dtype=np.uint64)
+    _check(lib().awg_ramp_table(int(shape), int(n), out.ctypes.data), "awg_ramp_table")
+    return out
+
+
+def awg_plan_retune(plan, events, stream=0):
+    """events: iterable of (tone, ramp, ramp_start, ramp_len, f_end_hz)."""
+    ev = list(events)
+    arr = (awg_retune * max(1, len(ev)))()
+    for i, (k, shape, a, n, f) in enumerate(ev):
+        arr[i] = awg_retune(int(k), int(shape), int(a), int(n), float(f))
+    _check(lib().awg_plan_retune(plan, arr, len(ev), stream or None), "awg_plan_retune")
+
+
+def awg_synth_static(plan, n0, count, d_out, stream=0):
+    _check(lib().awg_synth_static(plan, int(n0), int(count), d_out, stream or None), "awg_synth_static")
+
+
+def awg_synth_chirp(plan, n0, count, d_out, stream=0):
+    _check(lib().awg_synth_chirp(plan, int(n0), int(count), d_out, stream or None), "awg_synth_chirp")
+
+
+def awg_stream_next(plan, count, d_out, stream=0):
+    n0 = _U64()
+    _check(lib().awg_stream_next(plan, int(count), d_out, stream or None, ctypes.byref(n0)),
+           "awg_stream_next")
+    return n0.value
+
+
+def awg_stream_seek(plan, n0):
+    _check(lib().awg_stream_seek(plan, int(n0)), "awg_stream_seek")
+
+
+def awg_stream_tell(plan):
+    n0 = _U64()
+    _check(lib().awg_stream_tell(plan, ctypes.byref(n0)), "awg_stream_tell")
+    return n0.value
+
+
+def awg_synth_f32(plan, method, n0, count, d_y, stream=0):
+    _check(lib().awg_synth_f32(plan, int(method), int(n0), int(count), d_y, stream or None),
+           "awg_synth_f32")
+
+
+def awg_phase_dump(plan, tone, n0, count, d_words, stream=0):
+    _check(lib().awg_phase_dump(plan, int(tone), int(n0), int(count), d_words, stream or None),
+           "awg_phase_dump")
+
+
+# ------------------------------------------------------------ convenience
+
+_ctx_cache = {}
+
+
+def context(device=0):
+    """A process-wide context per device (created on first use)."""
+    if device not in _ctx_cache:
+        _ctx_cache[device] = awg_ctx_create(device)
+    return _ctx_cache[device]
+
+
+class Plan:
+    """Owns a plan handle; outputs are torch tensors on the plan's device."""
+
+    def __init__(self, tones, fs_hz, gain_lsb=0.0, period_log2=0, method=AWG_F_METHOD_DIRECT,
+                 device=0, host_only=False):
+        self.device = device
+        ctx = None if host_only else context(device)
+        self.tones = np.ascontiguousarray(tones, dtype=TONE_DTYPE)
+        self.handle, self.f_quantised_hz = awg_plan_tones(ctx, fs_hz, gain_lsb, period_log2, method,
+                                                          self.tones)
+        self.n_tones = len(self.tones)
+
+    def close(self):
+        if self.handle:
+            awg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if _exiting:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self):
+        return awg_plan_info_get(self.handle)
+
+    def words(self):
+        return awg_plan_words(self.handle, self.n_tones)
+
+    def _out(self, count, dtype, out):
+        import torch
+        if out is None:
+            out = torch.empty(int(count), dtype=dtype, device="cuda:%d" % self.device)
+        assert out.dtype == dtype and out.is_contiguous() and out.numel() >= count
+        return out
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        return (stream or torch.cuda.current_stream()).cuda_stream
+
+    def synth_static(self, n0, count, out=None, stream=None):
+        import torch
+        out = self._out(count, torch.int16, out)
+        awg_synth_static(self.handle, n0, count, out.data_ptr(), self._stream(stream))
+        return out
+
+    def synth_chirp(self, n0, count, out=None, stream=None):
+        import torch
+        out = self._out(count, torch.int16, out)
+        awg_synth_chirp(self.handle, n0, count, out.data_ptr(), self._stream(stream))
+        return out
+
+    def stream_next(self, count, out=None, stream=None):
+        import torch
+        out = self._out(count, torch.int16, out)
+        n0 = awg_stream_next(self.handle, count, out.data_ptr(), self._stream(stream))
+        return n0, out
+
+    def synth_f32(self, n0, count, method=AWG_F_METHOD_DIRECT, out=None, stream=None):
+        import torch
+        out = self._out(count, torch.float32, out)
+        awg_synth_f32(self.handle, method, n0, count, out.data_ptr(), self._stream(stream))
+        return out
+
+    def phase_dump(self, tone, n0, count, stream=None):
+        import torch
+        out = self._out(count, torch.int64, None)
+        awg_phase_dump(self.handle, tone, n0, count, out.data_ptr(), self._stream(stream))
+        return out
+
+    def retune(self, events, stream=None):
+        awg_plan_retune(self.handle, events, self._stream(stream))
+
+    def seek(self, n0):
+        awg_stream_seek(self.handle, n0)
+
+    def tell(self):
+        return awg_stream_tell(self.handle)

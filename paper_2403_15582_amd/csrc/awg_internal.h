@@ -1,0 +1,117 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "awg.h"
+
+namespace awg {
+
+// Device phase words carry this constant offset: half a step of the 23-bit turn
+// fraction handed to v_sin_f32, so that truncating to 23 bits rounds to nearest.
+constexpr uint64_t kPhaseBias = 1ull << 40;
+
+// Ramp tables hold 2^16 * N * Psi(d / N).
+constexpr int kTableShift = 16;
+
+// Direct kernel geometry: a workgroup is 4 waves; each wave sums one fixed slice
+// of the tones for the same 64 * S samples, and the 4 slice sums are added in a
+// fixed order. Inside a slice tones are summed in blocks of kBlock.
+constexpr int kWaves = 4;
+constexpr int kLanes = 64;
+constexpr int kBlock = 32;
+
+// One tone as the kernels read it (64 bytes, read with scalar loads).
+// Static tones have a = UINT64_MAX, n = 0 (their window never opens).
+struct ToneDev {
+    uint64_t p0, f0;     // line before the window: phi = p0 + f0 * n (p0 includes kPhaseBias)
+    uint64_t p1, f1;     // line after the window (p1 includes kPhaseBias)
+    uint64_t a, n;       // window [a, a + n]
+    int64_t coef;        // linear: R; smooth: dF
+    float amp;           // A_k * G
+    uint16_t shape;      // awg_ramp
+    uint16_t table;      // index into the plan's table pointer array (smooth shapes)
+};
+static_assert(sizeof(ToneDev) == 64, "ToneDev must be 64 bytes");
+
+// Host copy of a tone's state (exact words without the device bias).
+struct ToneHost {
+    uint64_t p0, f0, p1, f1, a, n;
+    int64_t coef;
+    int32_t shape;
+    double amp;          // A_k * G in FP64
+};
+
+struct Table {
+    int32_t shape;
+    uint64_t n;
+    uint64_t *d_data;    // device, n + 1 entries
+};
+
+}  // namespace awg
+
+struct awg_ctx {
+    int device;
+    std::mutex mu;
+    // smooth-ramp tables shared by all plans of the context, keyed by (shape, N)
+    std::map<std::pair<int32_t, uint64_t>, awg::Table> tables;
+    hipStream_t upload_stream;
+};
+
+struct awg_plan {
+    awg_ctx *ctx;                      // NULL for host-only plans
+    awg_plan_params params;
+    double gain;
+    int32_t n_tones;
+    int32_t n_ramped;
+    std::vector<awg::ToneHost> host;   // authoritative tone state
+    std::vector<awg::ToneDev> dev_mirror;
+    std::vector<const uint64_t *> table_ptrs;   // device pointers, indexed by ToneDev::table
+    std::map<std::pair<int32_t, uint64_t>, uint16_t> table_index;
+    awg::ToneDev *d_tones;             // device copy of dev_mirror
+    const uint64_t **d_table_ptrs;     // device copy of table_ptrs
+    size_t d_table_ptrs_cap;
+    uint64_t cursor;
+    uint64_t device_bytes;
+    // retune staging: pinned host slots and their completion events
+    struct Slot { void *host; hipEvent_t done; bool used; };
+    std::vector<Slot> slots;
+    size_t next_slot;
+    void *d_scratch;                   // device staging for retune records
+    size_t d_scratch_bytes;
+    // MFMA workspace (operands), grown on demand
+    void *d_work;
+    size_t d_work_bytes;
+};
+
+namespace awg {
+
+// Exact word arithmetic (plan.cpp)
+bool rne_ratio_shift(double num, double den, int shift, uint64_t *out);
+uint64_t phase_word(double turns);
+int64_t rne_div(int64_t num, uint64_t den);
+int64_t minjerk_entry(uint64_t n, uint64_t d);
+int64_t cosine_entry(uint64_t n, uint64_t d);
+uint64_t chirp_end_term(int32_t shape, int64_t coef, int64_t dF, uint64_t n);
+ToneDev to_device(const ToneHost &t, uint16_t table);
+
+// Kernel launchers (direct.hip, mfma.hip). Return a HIP error code.
+hipError_t launch_direct_i16(const awg_plan *p, uint64_t n0, uint64_t count, int16_t *out,
+                             hipStream_t s);
+hipError_t launch_direct_f32(const awg_plan *p, uint64_t n0, uint64_t count, float *out,
+                             hipStream_t s);
+hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint64_t count,
+                             uint64_t *out, hipStream_t s);
+hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n,
+                                hipStream_t s);
+// MFMA static synthesis; out_i16 or out_f32 (exactly one non-null).
+awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count,
+                       int16_t *out_i16, float *out_f32, hipStream_t s);
+
+}  // namespace awg

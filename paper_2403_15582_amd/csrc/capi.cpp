@@ -1,0 +1,521 @@
+// extern "C" entry points of libawg: context, plan, synthesis, streaming.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "awg_internal.h"
+
+using namespace awg;
+
+namespace {
+
+constexpr uint64_t kMaxSample = 1ull << 63;          // n0 + count must stay below
+constexpr size_t kTablePtrCap = 1024;                 // distinct smooth tables per plan
+constexpr size_t kSlots = 16;                         // retune staging slots
+constexpr size_t kSlotRecords = 16384;                // records per slot
+
+struct ScatterRecord { uint32_t index; uint32_t pad; ToneDev tone; };
+
+awg_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return AWG_OK;
+    if (e == hipErrorOutOfMemory) return AWG_E_NOMEM;
+    return AWG_E_HIP;
+}
+
+// Frequency word of f at fs (Eq. (4) when period_log2 > 0).
+awg_status freq_word(double f, double fs, uint32_t p, uint64_t *out)
+{
+    if (!std::isfinite(f) || !(f > 0.0) || !(f < fs * 0.5)) return AWG_E_INVALID;
+    uint64_t w;
+    if (p > 0) {
+        if (!rne_ratio_shift(f, fs, (int)p, &w)) return AWG_E_RANGE;
+        if (w < 1 || w >= (1ull << (p - 1))) return AWG_E_RANGE;
+        *out = w << (64 - p);
+        return AWG_OK;
+    }
+    if (!rne_ratio_shift(f, fs, 64, &w)) return AWG_E_RANGE;
+    if (w < 1 || w >= (1ull << 63)) return AWG_E_RANGE;
+    *out = w;
+    return AWG_OK;
+}
+
+bool smooth(int32_t shape) { return shape == AWG_RAMP_COSINE || shape == AWG_RAMP_MINJERK; }
+
+// Fill H_N[0..N] with up to 8 host threads.
+void fill_table(int32_t shape, uint64_t n, uint64_t *out)
+{
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt == 0) nt = 1;
+    if (nt > 8) nt = 8;
+    if (n < 65536) nt = 1;
+    auto work = [=](unsigned id) {
+        const uint64_t total = n + 1;
+        const uint64_t b = total * id / nt, e = total * (id + 1) / nt;
+        for (uint64_t d = b; d < e; ++d)
+            out[d] = (uint64_t)(shape == AWG_RAMP_MINJERK ? minjerk_entry(n, d) : cosine_entry(n, d));
+    };
+    if (nt == 1) { work(0); return; }
+    std::vector<std::thread> th;
+    for (unsigned i = 0; i < nt; ++i) th.emplace_back(work, i);
+    for (auto &t : th) t.join();
+}
+
+// Device table of a smooth shape, shared through the context.
+awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d_out)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto key = std::make_pair(shape, n);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) { *d_out = it->second.d_data; return AWG_OK; }
+    std::vector<uint64_t> h;
+    try { h.resize(n + 1); } catch (...) { return AWG_E_NOMEM; }
+    fill_table(shape, n, h.data());
+    Table t;
+    t.shape = shape;
+    t.n = n;
+    hipError_t e = hipMalloc((void **)&t.d_data, (n + 1) * sizeof(uint64_t));
+    if (e != hipSuccess) return hip_status(e);
+    e = hipMemcpy(t.d_data, h.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(t.d_data); return hip_status(e); }
+    ctx->tables[key] = t;
+    *d_out = t.d_data;
+    return AWG_OK;
+}
+
+// Words of one tone with one (optional) window, starting from the line (p, f).
+awg_status tone_words(const awg_plan_params &pp, uint64_t p_line, uint64_t f_line, int32_t shape,
+                      uint64_t a, uint64_t n, double f_end, ToneHost *t)
+{
+    t->p0 = p_line;
+    t->f0 = f_line;
+    t->shape = shape;
+    if (shape == AWG_RAMP_NONE) {
+        t->p1 = p_line; t->f1 = f_line; t->a = UINT64_MAX; t->n = 0; t->coef = 0;
+        return AWG_OK;
+    }
+    if (!(shape == AWG_RAMP_LINEAR || smooth(shape))) return AWG_E_INVALID;
+    if (n == 0 || n >= (1ull << 31)) return AWG_E_RANGE;
+    if (a >= kMaxSample || n >= kMaxSample - a) return AWG_E_RANGE;
+    uint64_t f1;
+    awg_status st = freq_word(f_end, pp.fs_hz, pp.period_log2, &f1);
+    if (st != AWG_OK) return st;
+    const int64_t dF = (int64_t)(f1 - f_line);      // both < 2^63
+    t->f1 = f1;
+    t->a = a;
+    t->n = n;
+    t->coef = shape == AWG_RAMP_LINEAR ? rne_div(dF, n) : dF;
+    const uint64_t end = a + n;
+    const uint64_t phi_end = p_line + f_line * end + chirp_end_term(shape, t->coef, dF, n);
+    t->p1 = phi_end - f1 * end;
+    return AWG_OK;
+}
+
+awg_status table_slot(awg_plan *p, int32_t shape, uint64_t n, uint16_t *idx, bool *added)
+{
+    *added = false;
+    auto key = std::make_pair(shape, n);
+    auto it = p->table_index.find(key);
+    if (it != p->table_index.end()) { *idx = it->second; return AWG_OK; }
+    if (p->table_ptrs.size() >= kTablePtrCap) return AWG_E_UNSUPPORTED;
+    const uint64_t *d = nullptr;
+    if (p->ctx) {
+        awg_status st = get_table(p->ctx, shape, n, &d);
+        if (st != AWG_OK) return st;
+    }
+    *idx = (uint16_t)p->table_ptrs.size();
+    p->table_ptrs.push_back(d);
+    p->table_index[key] = *idx;
+    *added = true;
+    return AWG_OK;
+}
+
+void free_plan_device(awg_plan *p)
+{
+    if (p->d_tones) (void)hipFree(p->d_tones);
+    if (p->d_table_ptrs) (void)hipFree(p->d_table_ptrs);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
+    if (p->d_work) (void)hipFree(p->d_work);
+    for (auto &s : p->slots) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.done) (void)hipEventDestroy(s.done);
+    }
+    p->slots.clear();
+}
+
+awg_status check_range(uint64_t n0, uint64_t count)
+{
+    if (n0 >= kMaxSample || count > kMaxSample - n0) return AWG_E_RANGE;
+    return AWG_OK;
+}
+
+awg_status device_ready(awg_plan *p)
+{
+    if (!p) return AWG_E_INVALID;
+    if (!p->ctx) return AWG_E_INVALID;
+    hipError_t e = hipSetDevice(p->ctx->device);
+    return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t awg_version(void) { return 100; }
+
+const char *awg_strerror(awg_status s)
+{
+    switch (s) {
+    case AWG_OK: return "ok";
+    case AWG_E_INVALID: return "invalid argument";
+    case AWG_E_NOMEM: return "out of memory";
+    case AWG_E_HIP: return "HIP runtime error";
+    case AWG_E_RANGE: return "value out of range";
+    case AWG_E_UNSUPPORTED: return "unsupported request";
+    case AWG_E_BUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+awg_status awg_ctx_create(int device, awg_ctx **out)
+{
+    if (!out) return AWG_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return AWG_E_HIP;
+    if (hipSetDevice(device) != hipSuccess) return AWG_E_HIP;
+    awg_ctx *c = new (std::nothrow) awg_ctx();
+    if (!c) return AWG_E_NOMEM;
+    c->device = device;
+    c->upload_stream = nullptr;
+    *out = c;
+    return AWG_OK;
+}
+
+void awg_ctx_destroy(awg_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->tables) (void)hipFree(kv.second.d_data);
+    delete ctx;
+}
+
+awg_status awg_ramp_table(int32_t shape, uint64_t n, uint64_t *out)
+{
+    if (!out || !smooth(shape)) return AWG_E_INVALID;
+    if (n == 0 || n >= (1ull << 31)) return AWG_E_RANGE;
+    fill_table(shape, n, out);
+    return AWG_OK;
+}
+
+awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg_tone *tones,
+                          int32_t n_tones, awg_plan **out, double *f_quantised_hz)
+{
+    if (!out) return AWG_E_INVALID;
+    *out = nullptr;
+    if (!params || !tones || n_tones <= 0) return AWG_E_INVALID;
+    const awg_plan_params pp = *params;
+    if (!std::isfinite(pp.fs_hz) || !(pp.fs_hz > 0.0)) return AWG_E_INVALID;
+    if (!std::isfinite(pp.gain_lsb) || pp.gain_lsb < 0.0) return AWG_E_INVALID;
+    if (pp.period_log2 == 1 || pp.period_log2 > 63) return AWG_E_INVALID;
+    if ((pp.flags & ~AWG_F_METHOD_MASK) != 0 || (pp.flags & AWG_F_METHOD_MASK) == 3) return AWG_E_INVALID;
+    double asum = 0.0;
+    for (int32_t k = 0; k < n_tones; ++k) {
+        const awg_tone &t = tones[k];
+        if (!std::isfinite(t.f_start_hz) || !std::isfinite(t.amplitude) ||
+            !std::isfinite(t.phase_turns) || !(t.amplitude >= 0.0) || t.reserved != 0)
+            return AWG_E_INVALID;
+        if (t.ramp < AWG_RAMP_NONE || t.ramp > AWG_RAMP_MINJERK) return AWG_E_INVALID;
+        if (t.ramp != AWG_RAMP_NONE && !std::isfinite(t.f_end_hz)) return AWG_E_INVALID;
+        asum += std::fabs(t.amplitude);
+    }
+    double gain = pp.gain_lsb;
+    if (gain == 0.0) {
+        if (!(asum > 0.0)) return AWG_E_INVALID;
+        gain = 32767.0 / asum;
+    }
+
+    awg_plan *p = new (std::nothrow) awg_plan();
+    if (!p) return AWG_E_NOMEM;
+    p->ctx = ctx;
+    p->params = pp;
+    p->gain = gain;
+    p->n_tones = n_tones;
+    p->n_ramped = 0;
+    p->d_tones = nullptr;
+    p->d_table_ptrs = nullptr;
+    p->d_table_ptrs_cap = 0;
+    p->cursor = 0;
+    p->device_bytes = 0;
+    p->next_slot = 0;
+    p->d_scratch = nullptr;
+    p->d_scratch_bytes = 0;
+    p->d_work = nullptr;
+    p->d_work_bytes = 0;
+    try {
+        p->host.resize(n_tones);
+        p->dev_mirror.resize(n_tones);
+    } catch (...) { delete p; return AWG_E_NOMEM; }
+
+    awg_status st = AWG_OK;
+    if (ctx && hipSetDevice(ctx->device) != hipSuccess) st = AWG_E_HIP;
+    for (int32_t k = 0; k < n_tones && st == AWG_OK; ++k) {
+        const awg_tone &t = tones[k];
+        uint64_t f0;
+        st = freq_word(t.f_start_hz, pp.fs_hz, pp.period_log2, &f0);
+        if (st != AWG_OK) break;
+        ToneHost &h = p->host[k];
+        st = tone_words(pp, phase_word(t.phase_turns), f0, t.ramp, t.ramp_start, t.ramp_len,
+                        t.f_end_hz, &h);
+        if (st != AWG_OK) break;
+        h.amp = t.amplitude * gain;
+        uint16_t idx = 0;
+        if (smooth(t.ramp)) {
+            bool added;
+            st = table_slot(p, t.ramp, t.ramp_len, &idx, &added);
+            if (st != AWG_OK) break;
+        }
+        if (t.ramp != AWG_RAMP_NONE) p->n_ramped++;
+        p->dev_mirror[k] = to_device(h, idx);
+        if (f_quantised_hz) f_quantised_hz[k] = (double)f0 * pp.fs_hz * 0x1p-64;
+    }
+    if (st == AWG_OK && ctx) {
+        hipError_t e = hipMalloc((void **)&p->d_tones, sizeof(ToneDev) * (size_t)n_tones);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_tones, p->dev_mirror.data(), sizeof(ToneDev) * (size_t)n_tones,
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_table_ptrs, sizeof(uint64_t *) * kTablePtrCap);
+        if (e == hipSuccess) {
+            p->d_table_ptrs_cap = kTablePtrCap;
+            std::vector<const uint64_t *> ptrs(kTablePtrCap, nullptr);
+            for (size_t i = 0; i < p->table_ptrs.size(); ++i) ptrs[i] = p->table_ptrs[i];
+            e = hipMemcpy(p->d_table_ptrs, ptrs.data(), sizeof(uint64_t *) * kTablePtrCap,
+                          hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) st = hip_status(e);
+        p->device_bytes = sizeof(ToneDev) * (size_t)n_tones + sizeof(uint64_t *) * kTablePtrCap;
+    }
+    if (st != AWG_OK) {
+        free_plan_device(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return AWG_OK;
+}
+
+void awg_plan_destroy(awg_plan *p)
+{
+    if (!p) return;
+    if (p->ctx) {
+        (void)hipSetDevice(p->ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    free_plan_device(p);
+    delete p;
+}
+
+awg_status awg_plan_info_get(const awg_plan *p, awg_plan_info *info)
+{
+    if (!p || !info) return AWG_E_INVALID;
+    info->n_tones = p->n_tones;
+    info->n_ramped = p->n_ramped;
+    info->gain_lsb = p->gain;
+    info->flags = p->params.flags;
+    info->period_log2 = p->params.period_log2;
+    info->cursor = p->cursor;
+    info->device_bytes = p->device_bytes + p->d_work_bytes + p->d_scratch_bytes;
+    return AWG_OK;
+}
+
+awg_status awg_plan_words(const awg_plan *p, uint64_t *p0, uint64_t *f0, uint64_t *f1, int64_t *coef)
+{
+    if (!p) return AWG_E_INVALID;
+    for (int32_t k = 0; k < p->n_tones; ++k) {
+        const ToneHost &h = p->host[k];
+        if (p0) p0[k] = h.p0;
+        if (f0) f0[k] = h.f0;
+        if (f1) f1[k] = h.f1;
+        if (coef) coef[k] = h.coef;
+    }
+    return AWG_OK;
+}
+
+awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void *hip_stream)
+{
+    if (!p || (n_ev > 0 && !ev) || n_ev < 0) return AWG_E_INVALID;
+    if (n_ev == 0) return AWG_OK;
+    if ((size_t)n_ev > kSlotRecords) return AWG_E_UNSUPPORTED;
+    // validate all events first so that a failing call changes nothing
+    std::vector<ToneHost> next;
+    std::vector<uint16_t> tidx;
+    try { next.resize(n_ev); tidx.resize(n_ev); } catch (...) { return AWG_E_NOMEM; }
+    for (int32_t i = 0; i < n_ev; ++i) {
+        const awg_retune &r = ev[i];
+        if (r.tone < 0 || r.tone >= p->n_tones) return AWG_E_INVALID;
+        if (!(r.ramp == AWG_RAMP_LINEAR || smooth(r.ramp))) return AWG_E_INVALID;
+        if (!std::isfinite(r.f_end_hz)) return AWG_E_INVALID;
+        for (int32_t j = 0; j < i; ++j)
+            if (ev[j].tone == r.tone) return AWG_E_UNSUPPORTED;   // one window per tone and call
+        const ToneHost &cur = p->host[r.tone];
+        const uint64_t free_from = cur.shape == AWG_RAMP_NONE ? 0 : cur.a + cur.n;
+        if (r.ramp_start < free_from) return AWG_E_RANGE;
+        ToneHost h;
+        awg_status st = tone_words(p->params, cur.p1, cur.f1, r.ramp, r.ramp_start, r.ramp_len,
+                                   r.f_end_hz, &h);
+        if (st != AWG_OK) return st;
+        h.amp = cur.amp;
+        next[i] = h;
+    }
+    awg_status st = AWG_OK;
+    for (int32_t i = 0; i < n_ev && st == AWG_OK; ++i) {
+        tidx[i] = 0;
+        if (smooth(ev[i].ramp)) {
+            bool added;
+            st = table_slot(p, ev[i].ramp, ev[i].ramp_len, &tidx[i], &added);
+            if (st == AWG_OK && added && p->ctx) {
+                hipError_t e = hipSetDevice(p->ctx->device);
+                if (e == hipSuccess)
+                    e = hipMemcpy(p->d_table_ptrs + tidx[i], &p->table_ptrs[tidx[i]], sizeof(uint64_t *),
+                                  hipMemcpyHostToDevice);
+                st = hip_status(e);
+            }
+        }
+    }
+    if (st != AWG_OK) return st;
+    for (int32_t i = 0; i < n_ev; ++i) {
+        const int32_t k = ev[i].tone;
+        if (p->host[k].shape == AWG_RAMP_NONE) p->n_ramped++;
+        p->host[k] = next[i];
+        p->dev_mirror[k] = to_device(next[i], tidx[i]);
+    }
+    if (!p->ctx) return AWG_OK;
+    // stage the new records and scatter them on the stream
+    hipError_t e = hipSetDevice(p->ctx->device);
+    if (e != hipSuccess) return hip_status(e);
+    if (p->slots.empty()) {
+        p->slots.resize(kSlots);
+        for (auto &s : p->slots) {
+            s.host = nullptr; s.done = nullptr; s.used = false;
+        }
+        for (auto &s : p->slots) {
+            e = hipHostMalloc(&s.host, sizeof(ScatterRecord) * kSlotRecords, hipHostMallocDefault);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_status(e);
+        }
+        e = hipMalloc(&p->d_scratch, sizeof(ScatterRecord) * kSlotRecords * kSlots);
+        if (e != hipSuccess) return hip_status(e);
+        p->d_scratch_bytes = sizeof(ScatterRecord) * kSlotRecords * kSlots;
+    }
+    const size_t si = p->next_slot;
+    p->next_slot = (p->next_slot + 1) % kSlots;
+    auto &slot = p->slots[si];
+    if (slot.used) {
+        e = hipEventSynchronize(slot.done);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    ScatterRecord *rec = (ScatterRecord *)slot.host;
+    for (int32_t i = 0; i < n_ev; ++i) {
+        rec[i].index = (uint32_t)ev[i].tone;
+        rec[i].pad = 0;
+        rec[i].tone = p->dev_mirror[ev[i].tone];
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    void *d_rec = (char *)p->d_scratch + si * sizeof(ScatterRecord) * kSlotRecords;
+    e = hipMemcpyAsync(d_rec, rec, sizeof(ScatterRecord) * (size_t)n_ev, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_scatter_tones(p->d_tones, d_rec, n_ev, s);
+    if (e == hipSuccess) e = hipEventRecord(slot.done, s);
+    slot.used = true;
+    return hip_status(e);
+}
+
+awg_status awg_synth_chirp(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d_out, void *hip_stream)
+{
+    awg_status st = device_ready(p);
+    if (st != AWG_OK) return st;
+    if ((st = check_range(n0, count)) != AWG_OK) return st;
+    if (count == 0) return AWG_OK;
+    if (!d_out) return AWG_E_INVALID;
+    return hip_status(launch_direct_i16(p, n0, count, d_out, (hipStream_t)hip_stream));
+}
+
+awg_status awg_synth_static(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d_out, void *hip_stream)
+{
+    awg_status st = device_ready(p);
+    if (st != AWG_OK) return st;
+    if (p->n_ramped > 0) return AWG_E_UNSUPPORTED;
+    if ((st = check_range(n0, count)) != AWG_OK) return st;
+    if (count == 0) return AWG_OK;
+    if (!d_out) return AWG_E_INVALID;
+    const uint32_t method = p->params.flags & AWG_F_METHOD_MASK;
+    if (method == AWG_F_METHOD_DIRECT)
+        return hip_status(launch_direct_i16(p, n0, count, d_out, (hipStream_t)hip_stream));
+    return mfma_static(p, method, n0, count, d_out, nullptr, (hipStream_t)hip_stream);
+}
+
+awg_status awg_synth_f32(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, float *d_y,
+                         void *hip_stream)
+{
+    awg_status st = device_ready(p);
+    if (st != AWG_OK) return st;
+    if (method > AWG_F_METHOD_MFMA_BF16X3) return AWG_E_INVALID;
+    if ((st = check_range(n0, count)) != AWG_OK) return st;
+    if (count == 0) return AWG_OK;
+    if (!d_y) return AWG_E_INVALID;
+    if (method == AWG_F_METHOD_DIRECT)
+        return hip_status(launch_direct_f32(p, n0, count, d_y, (hipStream_t)hip_stream));
+    if (p->n_ramped > 0) return AWG_E_UNSUPPORTED;
+    return mfma_static(p, method, n0, count, nullptr, d_y, (hipStream_t)hip_stream);
+}
+
+awg_status awg_stream_next(awg_plan *p, uint64_t count, int16_t *d_out, void *hip_stream, uint64_t *n0_out)
+{
+    awg_status st = device_ready(p);
+    if (st != AWG_OK) return st;
+    const uint64_t n0 = p->cursor;
+    if ((st = check_range(n0, count)) != AWG_OK) return st;
+    if (count > 0) {
+        if (!d_out) return AWG_E_INVALID;
+        st = hip_status(launch_direct_i16(p, n0, count, d_out, (hipStream_t)hip_stream));
+        if (st != AWG_OK) return st;
+    }
+    p->cursor = n0 + count;
+    if (n0_out) *n0_out = n0;
+    return AWG_OK;
+}
+
+awg_status awg_stream_seek(awg_plan *p, uint64_t n0)
+{
+    if (!p) return AWG_E_INVALID;
+    if (n0 >= kMaxSample) return AWG_E_RANGE;
+    p->cursor = n0;
+    return AWG_OK;
+}
+
+awg_status awg_stream_tell(const awg_plan *p, uint64_t *n0)
+{
+    if (!p || !n0) return AWG_E_INVALID;
+    *n0 = p->cursor;
+    return AWG_OK;
+}
+
+awg_status awg_phase_dump(awg_plan *p, int32_t tone, uint64_t n0, uint64_t count, uint64_t *d_words,
+                          void *hip_stream)
+{
+    awg_status st = device_ready(p);
+    if (st != AWG_OK) return st;
+    if (tone < 0 || tone >= p->n_tones) return AWG_E_INVALID;
+    if ((st = check_range(n0, count)) != AWG_OK) return st;
+    if (count == 0) return AWG_OK;
+    if (!d_words) return AWG_E_INVALID;
+    return hip_status(launch_phase_dump(p, tone, n0, count, d_words, (hipStream_t)hip_stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,254 @@
+// Direct VALU synthesis on gfx950: exact 64-bit phase words, v_sin_f32, FP32 sum.
+//
+// y[n] = sum_k amp_k * sin(2 pi phi_k(n) / 2^64) for a tile of 64*S contiguous
+// samples per workgroup. The 4 waves of a workgroup split the tones into 4 fixed
+// slices and cover the same samples; lane l of a wave owns samples
+// [tile0 + l*S, tile0 + (l+1)*S). Tone parameters are wave-uniform and come in
+// through scalar loads. Inside a slice tones are summed in blocks of 32 (FMA
+// chain per block, block sums added to the slice sum); the 4 slice sums meet in
+// LDS and are added in the order ((s0 + s1) + s2) + s3. The summation order
+// therefore depends only on the tone list, never on the sample range, the tile
+// position or the batch, so chunked, one-shot and batched results are
+// bit-identical.
+//
+// Phase words (the piecewise law of Eq. (8)) are computed per tone and tile in
+// one of four uniform regimes: before the window (line p0 + f0 n), after it
+// (line p1 + f1 n), entirely inside it (incremental exact updates), or
+// straddling an edge (closed form per sample).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "awg_internal.h"
+
+namespace awg {
+
+// floor(R d^2 / 2) mod 2^64 for d < 2^31: R*floor(d^2/2) + (d odd) * floor(R/2).
+__device__ __forceinline__ uint64_t lin_term(int64_t R, uint64_t d)
+{
+    const uint64_t dd = d * d;
+    return (uint64_t)R * (dd >> 1) + ((d & 1) ? (uint64_t)(R >> 1) : 0ull);
+}
+
+// floor(dF * H / 2^16) mod 2^64 for H < 2^47: dF*(H>>16) + floor(dF*(H&0xffff) / 2^16).
+__device__ __forceinline__ uint64_t smooth_term(int64_t dF, uint64_t H)
+{
+    const uint64_t hh = H >> 16;
+    const uint32_t hl = (uint32_t)H & 0xffffu;
+    const uint64_t t1 = (uint64_t)dF * hh;
+    const uint64_t lo = (uint64_t)(uint32_t)dF * hl;                 // < 2^48
+    const int64_t hi = (int64_t)(int32_t)(dF >> 32) * (int64_t)hl;   // |.| < 2^47
+    return t1 + ((uint64_t)hi << 16) + (lo >> 16);
+}
+
+__device__ __forceinline__ uint64_t phase_general(const ToneDev &t, const uint64_t *const *tables,
+                                                  uint64_t n)
+{
+    if (n < t.a) return t.p0 + t.f0 * n;
+    const uint64_t d = n - t.a;
+    if (d <= t.n) {
+        const uint64_t base = t.p0 + t.f0 * n;
+        if (t.shape == AWG_RAMP_LINEAR) return base + lin_term(t.coef, d);
+        return base + smooth_term(t.coef, tables[t.table][d]);
+    }
+    return t.p1 + t.f1 * n;
+}
+
+// sin(2 pi phi / 2^64): the top 23 fraction bits of the (biased) word become the
+// mantissa of a float in [1, 2); v_sin_f32 takes its argument in turns.
+__device__ __forceinline__ float word_sin(uint64_t w)
+{
+    const uint32_t hi = (uint32_t)(w >> 32);
+    return __builtin_amdgcn_sinf(__uint_as_float(__builtin_amdgcn_alignbit(0x7fu, hi, 9u)));
+}
+
+// Calls f(s, phi) for the S samples tile0 + lane*S + s of tone t.
+template <int S, typename F>
+__device__ __forceinline__ void gen_phases(const ToneDev &t, const uint64_t *const *tables,
+                                           uint64_t tile0, uint32_t lane, F &&f)
+{
+    const uint64_t tile_last = tile0 + (uint64_t)(kLanes * S - 1);
+    const uint32_t j = lane * S;                                   // even offset in the tile
+    if (tile_last < t.a || tile0 > t.a + t.n) {                     // static line
+        const bool pre = tile_last < t.a;
+        const uint64_t P = pre ? t.p0 : t.p1, Fw = pre ? t.f0 : t.f1;
+        uint64_t ph = P + Fw * tile0 + Fw * (uint64_t)j;
+#pragma unroll
+        for (int s = 0; s < S; ++s) { f(s, ph); ph += Fw; }
+    } else if (tile0 >= t.a && tile_last <= t.a + t.n) {           // inside the window
+        const uint64_t dt = tile0 - t.a;
+        if (t.shape == AWG_RAMP_LINEAR) {
+            const int64_t R = t.coef;
+            const uint64_t h = (uint64_t)(R >> 1), r = (uint64_t)(R & 1);
+            const uint64_t W = t.p0 + t.f0 * tile0 + lin_term(R, dt);
+            const uint64_t V = t.f0 + (uint64_t)R * dt;
+            const uint64_t I = V + h + ((dt & 1) ? r : 0ull);
+            const uint64_t Dp = (uint64_t)R + ((dt & 1) ? (0ull - r) : r);   // step when d has dt's parity
+            const uint64_t Dq = (uint64_t)R + ((dt & 1) ? r : (0ull - r));   // the other parity
+            uint64_t ph = W + V * (uint64_t)j + (uint64_t)R * (uint64_t)(j * j / 2);
+            uint64_t inc = I + (uint64_t)R * (uint64_t)j;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                f(s, ph);
+                ph += inc;
+                inc += (s & 1) ? Dq : Dp;
+            }
+        } else {
+            const uint64_t *H = tables[t.table] + dt + j;
+            uint64_t ph = t.p0 + t.f0 * tile0 + t.f0 * (uint64_t)j;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                f(s, ph + smooth_term(t.coef, H[s]));
+                ph += t.f0;
+            }
+        }
+    } else {                                                        // straddles an edge
+#pragma unroll
+        for (int s = 0; s < S; ++s) f(s, phase_general(t, tables, tile0 + j + s));
+    }
+}
+
+__device__ __forceinline__ int16_t quantise(float y)
+{
+    float r = __builtin_rintf(y);
+    r = fminf(fmaxf(r, -32768.0f), 32767.0f);
+    return (int16_t)(int32_t)r;
+}
+
+template <int S, bool F32OUT>
+__global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
+                                                     int32_t slice, const uint64_t *const *__restrict__ tables,
+                                                     uint64_t n0, uint64_t count, void *__restrict__ out)
+{
+    constexpr int T = kLanes * S;                 // samples per tile
+    __shared__ float part[kWaves][T];
+    const uint32_t lane = threadIdx.x & 63u;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t tile0 = n0 + (uint64_t)blockIdx.x * T;
+
+    const int kb = wave * slice;
+    const int ke = min(n_tones, kb + slice);
+    float acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = 0.0f;
+
+    for (int k0 = kb; k0 < ke; k0 += kBlock) {
+        const int k1 = min(ke, k0 + kBlock);
+        float blk[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) blk[s] = 0.0f;
+        for (int k = k0; k < k1; ++k) {
+            const ToneDev t = tones[k];
+            const float amp = t.amp;
+            gen_phases<S>(t, tables, tile0, lane, [&](int s, uint64_t ph) {
+                blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+            });
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] += blk[s];
+    }
+
+#pragma unroll
+    for (int s = 0; s < S; ++s) part[wave][lane * S + s] = acc[s];
+    __syncthreads();
+
+    constexpr int PER = T / 256;                  // samples per thread in the epilogue
+    const uint32_t i0 = threadIdx.x * PER;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const uint32_t i = i0 + e;
+        const float y = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+        const uint64_t rel = (uint64_t)blockIdx.x * T + i;
+        if (rel < count) {
+            if (F32OUT) ((float *)out)[rel] = y;
+            else ((int16_t *)out)[rel] = quantise(y);
+        }
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(64) void phase_dump_kernel(const ToneDev *__restrict__ tones, int32_t tone,
+                                                        const uint64_t *const *__restrict__ tables,
+                                                        uint64_t n0, uint64_t count, uint64_t *__restrict__ out)
+{
+    constexpr int T = kLanes * S;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t tile0 = n0 + (uint64_t)blockIdx.x * T;
+    const ToneDev t = tones[tone];
+    gen_phases<S>(t, tables, tile0, lane, [&](int s, uint64_t ph) {
+        const uint64_t rel = (uint64_t)blockIdx.x * T + lane * S + s;
+        if (rel < count) out[rel] = ph - kPhaseBias;
+    });
+}
+
+struct ScatterRecord { uint32_t index; uint32_t pad; ToneDev tone; };
+
+__global__ void scatter_tones_kernel(ToneDev *__restrict__ tones, const ScatterRecord *__restrict__ rec,
+                                     int32_t n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) tones[rec[i].index] = rec[i].tone;
+}
+
+constexpr int kS = 8;                              // samples per lane
+constexpr uint64_t kMaxTilesPerLaunch = 1u << 30;
+
+static int slice_of(int32_t n_tones) { return (n_tones + kWaves - 1) / kWaves; }
+
+template <bool F32OUT>
+static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, void *out, hipStream_t s)
+{
+    constexpr uint64_t T = kLanes * kS;
+    const uint64_t esz = F32OUT ? 4 : 2;
+    while (count > 0) {
+        const uint64_t tiles = (count + T - 1) / T;
+        const uint64_t now_tiles = tiles < kMaxTilesPerLaunch ? tiles : kMaxTilesPerLaunch;
+        const uint64_t now = now_tiles * T < count ? now_tiles * T : count;
+        hipLaunchKernelGGL((direct_kernel<kS, F32OUT>), dim3((uint32_t)now_tiles), dim3(256), 0, s,
+                           p->d_tones, p->n_tones, slice_of(p->n_tones), p->d_table_ptrs, n0, now, out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        n0 += now;
+        count -= now;
+        out = (char *)out + now * esz;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_direct_i16(const awg_plan *p, uint64_t n0, uint64_t count, int16_t *out, hipStream_t s)
+{
+    return launch_direct<false>(p, n0, count, out, s);
+}
+
+hipError_t launch_direct_f32(const awg_plan *p, uint64_t n0, uint64_t count, float *out, hipStream_t s)
+{
+    return launch_direct<true>(p, n0, count, out, s);
+}
+
+hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint64_t count,
+                             uint64_t *out, hipStream_t s)
+{
+    constexpr uint64_t T = kLanes * kS;
+    while (count > 0) {
+        const uint64_t tiles = (count + T - 1) / T;
+        const uint64_t now_tiles = tiles < kMaxTilesPerLaunch ? tiles : kMaxTilesPerLaunch;
+        const uint64_t now = now_tiles * T < count ? now_tiles * T : count;
+        hipLaunchKernelGGL(phase_dump_kernel<kS>, dim3((uint32_t)now_tiles), dim3(64), 0, s,
+                           p->d_tones, tone, p->d_table_ptrs, n0, now, out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        n0 += now;
+        count -= now;
+        out += now;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_tones_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_tones,
+                       (const ScatterRecord *)d_records, n);
+    return hipGetLastError();
+}
+
+}  // namespace awg

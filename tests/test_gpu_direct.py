@@ -1,0 +1,220 @@
+"""GPU parity of the direct kernel against the CPU oracle (through the C ABI).
+
+Phase words must match bit for bit; int16 codes within 1 LSB; the unquantised
+FP32 sum within 0.25 LSB. Sizes: small cases compared element by element over
+several tiles with ragged tails, and the full configurations (2^20 x 100,
+2^24 x 1000, 10 x 2^20 x 1000 chirped) on sampled outputs.
+"""
+import numpy as np
+import pytest
+
+import paper_2403_15582_amd as awg
+from paper_2403_15582_amd import workloads as W
+from oracle import words, csynth
+
+from gpu_common import need_gpu, say, to_np, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_plan(w, tables=True):
+    return words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones, build_tables=tables)
+
+
+def lib_plan(w, method=awg.AWG_F_METHOD_DIRECT):
+    return awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, method)
+
+
+def test_phase_words_bit_exact_small_mixed():
+    torch = need_gpu()
+    w = W.small_mixed()
+    op = oracle_plan(w)
+    pk = csynth.Packed(op)
+    lp = lib_plan(w)
+    for n0, count in [(0, w.count), (3, 1234), (2 ** 40 + 7, 3000), (4095, 1)]:
+        say("phase dump small_mixed n0=%d count=%d" % (n0, count))
+        for k in range(len(w.tones)):
+            got = to_np(lp.phase_dump(k, n0, count)).view(np.uint64)
+            torch.cuda.synchronize()
+            want = csynth.phases(op, k, n0, count, packed=pk)
+            assert np.array_equal(got, want), (k, n0, int(np.sum(got != want)))
+
+
+def test_phase_words_bit_exact_long_ramps():
+    torch = need_gpu()
+    for shape in ("linear", "cosine", "minjerk"):
+        w = W.config3(shape=shape, K=8)
+        op = oracle_plan(w, tables=False)
+        lp = lib_plan(w)
+        N = W.CONFIG3_RAMP_LEN
+        for n0 in [0, 12345, N // 2 - 3, N - 700, N - 1, N + 5, 3 * N]:
+            count = 1500
+            ns = np.arange(n0, n0 + count)
+            csynth.sparse_tables(op, ns)
+            pk = csynth.Packed(op)
+            say("phase dump config3/%s n0=%d" % (shape, n0))
+            for k in range(len(w.tones)):
+                got = to_np(lp.phase_dump(k, n0, count)).view(np.uint64)
+                torch.cuda.synchronize()
+                want = csynth.phases(op, k, n0, count, packed=pk)
+                assert np.array_equal(got, want), (shape, k, n0)
+
+
+@pytest.mark.parametrize("n0,count", [(0, 5000), (1, 1), (7, 511), (100, 513), (2 ** 33 + 5, 4099),
+                                      (2 ** 62, 700)])
+def test_small_mixed_int16_and_f32(n0, count):
+    torch = need_gpu()
+    w = W.small_mixed()
+    op = oracle_plan(w)
+    lp = lib_plan(w)
+    say("small_mixed int16/f32 n0=%d count=%d" % (n0, count))
+    q = to_np(lp.synth_chirp(n0, count))
+    y = to_np(lp.synth_f32(n0, count))
+    torch.cuda.synchronize()
+    qo, yo = csynth.synth(op, n0, count)
+    compare(q, y, qo, yo, "small_mixed n0=%d count=%d" % (n0, count))
+
+
+def test_count_zero_and_errors():
+    torch = need_gpu()
+    w = W.small_mixed()
+    lp = lib_plan(w)
+    out = torch.full((16,), 77, dtype=torch.int16, device="cuda")
+    awg.awg_synth_chirp(lp.handle, 0, 0, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert int(out[0]) == 77
+    with pytest.raises(awg.AwgError) as e:
+        awg.awg_synth_chirp(lp.handle, 2 ** 63 - 4, 8, out.data_ptr())
+    assert e.value.status == awg.AWG_E_RANGE
+    with pytest.raises(awg.AwgError) as e:
+        awg.awg_synth_static(lp.handle, 0, 8, out.data_ptr())      # plan has ramps
+    assert e.value.status == awg.AWG_E_UNSUPPORTED
+    with pytest.raises(awg.AwgError) as e:
+        awg.awg_phase_dump(lp.handle, len(w.tones), 0, 8, out.data_ptr())
+    assert e.value.status == awg.AWG_E_INVALID
+
+
+def test_single_tone_and_quarter_rate():
+    torch = need_gpu()
+    t = awg.make_tones(1)
+    t["f_start_hz"] = 70e6
+    t["amplitude"] = 1.0
+    lp = awg.Plan(t, 280e6, 1000.0, 0)
+    q = to_np(lp.synth_chirp(0, 4096))
+    torch.cuda.synchronize()
+    assert np.array_equal(q, np.tile(np.array([0, 1000, 0, -1000], dtype=np.int16), 1024))
+
+
+def test_config1_full():
+    torch = need_gpu()
+    w = W.config1()
+    lp = lib_plan(w)
+    say("config1 full 2^20 x 100")
+    q = to_np(lp.synth_static(0, w.count))
+    y = to_np(lp.synth_f32(0, w.count))
+    torch.cuda.synchronize()
+    qo, yo = csynth.synth(oracle_plan(w), 0, w.count)
+    compare(q, y, qo, yo, "config1")
+
+
+def _sample_points(rng, total, extra=()):
+    ns = set(rng.integers(0, total, 3000).tolist())
+    ns |= set(range(0, 600)) | set(range(total - 600, total))
+    ns |= set(int(e) for e in extra)
+    return np.array(sorted(n for n in ns if 0 <= n < total), dtype=np.int64)
+
+
+def test_config2_full_direct_sampled_and_periodic():
+    torch = need_gpu()
+    w = W.config2()
+    lp = lib_plan(w)
+    say("config2 full 2^24 x 1000 direct")
+    qd = lp.synth_static(0, w.count)
+    yd = lp.synth_f32(0, w.count)
+    tail = lp.synth_static(w.count, 1 << 16)          # the next period starts over
+    torch.cuda.synchronize()
+    q, y = to_np(qd), to_np(yd)
+    assert np.array_equal(to_np(tail), q[:1 << 16])
+    ns = _sample_points(np.random.default_rng(21), w.count)
+    qo, yo = csynth.synth_at(oracle_plan(w), ns)
+    compare(q[ns], y[ns], qo, yo, "config2 direct (sampled %d)" % len(ns))
+
+
+@pytest.mark.parametrize("shape", ["linear", "cosine", "minjerk", "mixed"])
+def test_config3_streamed_equals_oneshot_and_oracle(shape):
+    torch = need_gpu()
+    w = W.config3(shape=shape)
+    lp = lib_plan(w)
+    say("config3/%s streamed 10 x 2^20 x 1000" % shape)
+    chunks = []
+    for c in range(w.count // w.chunk):
+        n0, out = lp.stream_next(w.chunk)
+        assert n0 == c * w.chunk
+        chunks.append(out)
+    streamed = torch.cat(chunks)
+    oneshot = lp.synth_chirp(0, w.count)
+    y = lp.synth_f32(0, w.count)
+    torch.cuda.synchronize()
+    assert torch.equal(streamed, oneshot)
+    q, yv = to_np(oneshot), to_np(y)
+    N = W.CONFIG3_RAMP_LEN
+    ns = _sample_points(np.random.default_rng(31), w.count, range(N - 300, N + 300))
+    op = oracle_plan(w, tables=False)
+    csynth.sparse_tables(op, ns)
+    qo, yo = csynth.synth_at(op, ns)
+    compare(q[ns], yv[ns], qo, yo, "config3/%s (sampled %d)" % (shape, len(ns)))
+
+
+def test_irregular_chunks_and_resume_bit_identical():
+    torch = need_gpu()
+    w = W.small_mixed(n_total=20000)
+    lp = lib_plan(w)
+    ref = lp.synth_chirp(0, 20000)
+    sizes = [1, 2, 511, 512, 513, 3, 4096, 777, 5000]
+    parts = []
+    for s in sizes:
+        parts.append(lp.stream_next(s)[1])
+    pos = lp.tell()
+    # checkpoint: a fresh plan from the same inputs resumes at the cursor
+    lp2 = lib_plan(w)
+    lp2.seek(pos)
+    parts.append(lp2.stream_next(20000 - pos)[1])
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat(parts), ref)
+
+
+def test_retune_stream_matches_oracle():
+    torch = need_gpu()
+    w = W.config4(K=1000, seconds=0.02, group=100)
+    lp = lib_plan(w)
+    op = oracle_plan(w, tables=False)
+    events = sorted(w.retunes, key=lambda e: e[1])
+    say("config4-small retuned stream: %d retunes" % len(events))
+    outs = []
+    i = 0
+    n_chunks = w.count // w.chunk
+    for c in range(n_chunks):
+        end = (c + 1) * w.chunk
+        batch = []
+        while i < len(events) and events[i][1] < end:
+            k, a, n, shape, f = events[i]
+            batch.append((k, shape, a, n, f))
+            op.add_ramp(k, a, n, shape, f)
+            i += 1
+        # one event per tone per call: split when a tone repeats
+        seen, cur = set(), []
+        for e in batch:
+            if e[0] in seen:
+                lp.retune(cur)
+                seen, cur = set(), []
+            seen.add(e[0])
+            cur.append(e)
+        if cur:
+            lp.retune(cur)
+        outs.append(lp.stream_next(w.chunk)[1])
+    q = to_np(torch.cat(outs))
+    torch.cuda.synchronize()
+    ns = _sample_points(np.random.default_rng(41), n_chunks * w.chunk,
+                        [e[1] + d for e in events[::37] for d in (-1, 0, 1, 2, 140000, W.CONFIG4_RAMP_LEN)])
+    qo, yo = csynth.synth_at(op, ns)
+    compare(q[ns], None, qo, yo, "config4-small (sampled %d)" % len(ns))
