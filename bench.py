@@ -123,6 +123,36 @@ def streaming_leg(torch, awg, W):
             "latency_note": "device time per 2^20-sample chunk (hipEvents on the launch stream)"}
 
 
+def method_codes(awg):
+    return {"direct": awg.AWG_F_METHOD_DIRECT, "mfma-f16": awg.AWG_F_METHOD_MFMA_F16X3,
+            "mfma-bf16": awg.AWG_F_METHOD_MFMA_BF16X3}
+
+
+def roofline_for(method, stats, K, L):
+    """Dominant kernel of the step and its algorithmic rate against the MI355X peak."""
+    name, (launches, total_ms, _) = max(stats.items(), key=lambda kv: kv[1][1])
+    avg_ms = total_ms / launches
+    if method == "direct":
+        flop = 2.0 * K * L                        # one weighting FMA per tone-sample
+        ach = flop / (avg_ms * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": name, "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                "avg_kernel_ms": avg_ms,
+                "note": "2 algorithmic flop per tone-sample over the FP32 vector peak; the kernel "
+                        "is bound by VALU issue including one v_sin_f32 per tone-sample"}
+    kpad = 8 * ((K + 7) // 8)
+    flop = 4.0 * K * L                            # two MACs per tone-sample (angle addition)
+    issued = 3 * 2.0 * (2 * kpad) * L             # three hi/lo passes over the padded tones
+    ach = flop / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_FP16_TFLOPS
+    return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak, "traffic": None, "avg_kernel_ms": avg_ms,
+            "issued_tflops": issued / (avg_ms * 1e-3) / 1e12,
+            "issued_frac": issued / (avg_ms * 1e-3) / 1e12 / peak,
+            "note": "achieved counts 4 algorithmic flop per tone-sample; the FP16 hi/lo split "
+                    "issues 3x that on the matrix cores (issued_*)"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -137,45 +167,55 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     w = W.config2()
     K, L = len(w.tones), w.count
-    methods = {"direct": awg.AWG_F_METHOD_DIRECT, "mfma-f16": awg.AWG_F_METHOD_MFMA_F16X3,
-               "mfma-bf16": awg.AWG_F_METHOD_MFMA_BF16X3}
-    method = "direct" if a.method == "auto" else a.method
-    log("workload", w.name, "method", method)
-    plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, methods[method])
+    codes = method_codes(awg)
+    primary = "mfma-f16" if a.method == "auto" else a.method
+    order = [primary] + [m for m in ("direct", "mfma-f16", "mfma-bf16") if m != primary]
+    ctx = awg.context(0)
     out = torch.empty(L, dtype=torch.int16, device="cuda")
+    per_method = {}
+    res = None
+    for m in order:
+        plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, codes[m])
 
-    def step():
-        plan.synth_static(0, L, out=out)
+        def step():
+            plan.synth_static(0, L, out=out)
 
-    ms, wall = timed_steps(torch, step, a.steps, a.warmup)
-    value = K * L / (ms * 1e-3)
-    log("ms/step %.3f  tone-samples/s %.3e  (wall %.2f s)" % (ms, value, wall))
-
-    # dominant kernel: the direct kernel is the whole step (one launch)
-    kernel_ms = ms
-    alg_flop = 2.0 * K * L                  # one FMA per tone-sample
-    achieved = alg_flop / (kernel_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "direct_kernel", "achieved": achieved,
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": None,
-                "note": "2 algorithmic flop per tone-sample (the weighting FMA) over the FP32 vector "
-                        "peak; the kernel is bound by VALU issue incl. one v_sin_f32 per tone-sample"}
-
-    q_gpu = out.cpu().numpy()
-    res = {"metric": METRIC, "value": value, "unit": "tone-samples/s", "n_gpus": 1,
-           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": w.name, "tones": K, "samples": L, "fs_hz": w.fs_hz,
-                      "method": method, "output": "int16"},
-           "rtf": (L / w.fs_hz) / (ms * 1e-3),
-           "roofline": roofline}
+        is_primary = m == primary
+        if is_primary:
+            for _ in range(a.warmup):
+                step()
+            torch.cuda.synchronize()
+            awg.awg_profile_read(ctx, reset=True)
+            awg.awg_profile_enable(ctx, True)
+            ms, wall = timed_steps(torch, step, a.steps, 0)
+            awg.awg_profile_enable(ctx, False)
+            stats = awg.awg_profile_read(ctx, reset=True)
+        else:
+            ms, wall = timed_steps(torch, step, max(3, a.steps // 2), 1)
+        per_method[m] = {"ms_per_step": ms, "tone_samples_per_s": K * L / (ms * 1e-3)}
+        log("%-9s ms/step %.3f  tone-samples/s %.3e" % (m, ms, K * L / (ms * 1e-3)))
+        if is_primary:
+            q_gpu = out.cpu().numpy()
+            value = K * L / (ms * 1e-3)
+            res = {"metric": METRIC, "value": value, "unit": "tone-samples/s", "n_gpus": 1,
+                   "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
+                   "scaling": "weak", "vs_baseline": None,
+                   "dtype": "f32" if m == "direct" else ("f16x3" if m == "mfma-f16" else "bf16x3"),
+                   "data": "synthetic",
+                   "config": {"workload": w.name, "tones": K, "samples": L, "fs_hz": w.fs_hz,
+                              "method": m, "output": "int16"},
+                   "rtf": (L / w.fs_hz) / (ms * 1e-3),
+                   "roofline": roofline_for(m, stats, K, L),
+                   "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(1, v[0])}
+                               for k, v in stats.items()}}
+        plan.close()
+    res["methods"] = per_method
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(w, q_gpu, a.cpu_seconds)
     if not a.no_stream:
         log("streaming leg ...")
         res["streaming"] = streaming_leg(torch, awg, W)
-    plan.close()
     print(json.dumps(res), flush=True)
 
 

@@ -200,6 +200,25 @@ awg_status awg_synth_f32(awg_plan *plan, uint32_t method, uint64_t n0, uint64_t 
 awg_status awg_phase_dump(awg_plan *plan, int32_t tone, uint64_t n0, uint64_t count,
                           uint64_t *d_words, void *hip_stream);
 
+/* -------------------------------------------------------------- profiling */
+
+/* Per-kernel device time, measured with HIP events recorded on the launch
+ * stream immediately before and after each kernel of the context's calls. */
+typedef struct {
+    char name[48];           /* kernel name */
+    uint64_t launches;
+    double total_ms;
+    double max_ms;
+} awg_kernel_stat;
+
+/* Switch event timing on or off for all calls on plans of ctx (off by default). */
+awg_status awg_profile_enable(awg_ctx *ctx, int32_t enable);
+/* Synchronise the recorded events and return up to max_stats per-kernel totals
+ * in out (host array); *n_stats receives the number of distinct kernels. With
+ * reset != 0 the totals start over. */
+awg_status awg_profile_read(awg_ctx *ctx, awg_kernel_stat *out, int32_t max_stats, int32_t *n_stats,
+                            int32_t reset);
+
 /* ------------------------------------------------------------------- misc */
 
 const char *awg_strerror(awg_status status);

@@ -30,6 +30,7 @@ EXPORTED = [
     "awg_plan_info_get", "awg_plan_words", "awg_ramp_table", "awg_plan_retune",
     "awg_synth_static", "awg_synth_chirp", "awg_stream_next", "awg_stream_seek",
     "awg_stream_tell", "awg_synth_f32", "awg_phase_dump", "awg_strerror", "awg_version",
+    "awg_profile_enable", "awg_profile_read",
 ]
 
 
@@ -49,6 +50,11 @@ class awg_plan_info(ctypes.Structure):
                 ("gain_lsb", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("period_log2", ctypes.c_uint32), ("cursor", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64)]
+
+
+class awg_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
 class awg_retune(ctypes.Structure):
@@ -97,6 +103,8 @@ def lib():
         "awg_stream_tell": ([_VP, ctypes.POINTER(_U64)], _I32),
         "awg_synth_f32": ([_VP, ctypes.c_uint32, _U64, _U64, _VP, _VP], _I32),
         "awg_phase_dump": ([_VP, _I32, _U64, _U64, _VP, _VP], _I32),
+        "awg_profile_enable": ([_VP, _I32], _I32),
+        "awg_profile_read": ([_VP, ctypes.POINTER(awg_kernel_stat), _I32, ctypes.POINTER(_I32), _I32], _I32),
         "awg_strerror": ([_I32], ctypes.c_char_p),
         "awg_version": ([], _I32),
     }
@@ -210,6 +218,19 @@ def awg_synth_f32(plan, method, n0, count, d_y, stream=0):
 def awg_phase_dump(plan, tone, n0, count, d_words, stream=0):
     _check(lib().awg_phase_dump(plan, int(tone), int(n0), int(count), d_words, stream or None),
            "awg_phase_dump")
+
+
+def awg_profile_enable(ctx, enable=True):
+    _check(lib().awg_profile_enable(ctx, 1 if enable else 0), "awg_profile_enable")
+
+
+def awg_profile_read(ctx, reset=False):
+    """{kernel name: (launches, total_ms, max_ms)} since the last reset."""
+    arr = (awg_kernel_stat * 64)()
+    n = _I32()
+    _check(lib().awg_profile_read(ctx, arr, 64, ctypes.byref(n), 1 if reset else 0), "awg_profile_read")
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms, arr[i].max_ms)
+            for i in range(min(n.value, 64))}
 
 
 # ------------------------------------------------------------ convenience

@@ -6,6 +6,7 @@
 
 #include <map>
 #include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -56,9 +57,20 @@ struct Table {
 
 }  // namespace awg
 
+namespace awg {
+struct ProfRecord { const char *name; hipEvent_t start, stop; };
+struct ProfTotal { uint64_t launches; double total_ms, max_ms; };
+}  // namespace awg
+
 struct awg_ctx {
     int device;
     std::mutex mu;
+    // kernel timing (awg_profile_*)
+    bool profiling;
+    std::mutex prof_mu;
+    std::vector<awg::ProfRecord> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    std::map<std::string, awg::ProfTotal> prof_totals;
     // smooth-ramp tables shared by all plans of the context, keyed by (shape, N)
     std::map<std::pair<int32_t, uint64_t>, awg::Table> tables;
     hipStream_t upload_stream;
@@ -100,6 +112,18 @@ int64_t minjerk_entry(uint64_t n, uint64_t d);
 int64_t cosine_entry(uint64_t n, uint64_t d);
 uint64_t chirp_end_term(int32_t shape, int64_t coef, int64_t dF, uint64_t n);
 ToneDev to_device(const ToneHost &t, uint16_t table);
+
+// Records HIP events around one kernel launch when the context profiles.
+class ProfScope {
+public:
+    ProfScope(awg_ctx *ctx, hipStream_t s, const char *name);
+    ~ProfScope();
+private:
+    awg_ctx *ctx_;
+    hipStream_t s_;
+    const char *name_;
+    hipEvent_t start_;
+};
 
 // Kernel launchers (direct.hip, mfma.hip). Return a HIP error code.
 hipError_t launch_direct_i16(const awg_plan *p, uint64_t n0, uint64_t count, int16_t *out,

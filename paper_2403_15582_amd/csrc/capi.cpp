@@ -194,6 +194,7 @@ awg_status awg_ctx_create(int device, awg_ctx **out)
     if (!c) return AWG_E_NOMEM;
     c->device = device;
     c->upload_stream = nullptr;
+    c->profiling = false;
     *out = c;
     return AWG_OK;
 }
@@ -204,6 +205,11 @@ void awg_ctx_destroy(awg_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto &kv : ctx->tables) (void)hipFree(kv.second.d_data);
+    for (auto &r : ctx->prof_pending) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 

@@ -203,9 +203,13 @@ static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, 
         const uint64_t tiles = (count + T - 1) / T;
         const uint64_t now_tiles = tiles < kMaxTilesPerLaunch ? tiles : kMaxTilesPerLaunch;
         const uint64_t now = now_tiles * T < count ? now_tiles * T : count;
-        hipLaunchKernelGGL((direct_kernel<kS, F32OUT>), dim3((uint32_t)now_tiles), dim3(256), 0, s,
-                           p->d_tones, p->n_tones, slice_of(p->n_tones), p->d_table_ptrs, n0, now, out);
-        hipError_t e = hipGetLastError();
+        hipError_t e;
+        {
+            ProfScope prof(p->ctx, s, F32OUT ? "direct_kernel_f32" : "direct_kernel");
+            hipLaunchKernelGGL((direct_kernel<kS, F32OUT>), dim3((uint32_t)now_tiles), dim3(256), 0, s,
+                               p->d_tones, p->n_tones, slice_of(p->n_tones), p->d_table_ptrs, n0, now, out);
+            e = hipGetLastError();
+        }
         if (e != hipSuccess) return e;
         n0 += now;
         count -= now;
@@ -232,9 +236,13 @@ hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint6
         const uint64_t tiles = (count + T - 1) / T;
         const uint64_t now_tiles = tiles < kMaxTilesPerLaunch ? tiles : kMaxTilesPerLaunch;
         const uint64_t now = now_tiles * T < count ? now_tiles * T : count;
-        hipLaunchKernelGGL(phase_dump_kernel<kS>, dim3((uint32_t)now_tiles), dim3(64), 0, s,
-                           p->d_tones, tone, p->d_table_ptrs, n0, now, out);
-        hipError_t e = hipGetLastError();
+        hipError_t e;
+        {
+            ProfScope prof(p->ctx, s, "phase_dump_kernel");
+            hipLaunchKernelGGL(phase_dump_kernel<kS>, dim3((uint32_t)now_tiles), dim3(64), 0, s,
+                               p->d_tones, tone, p->d_table_ptrs, n0, now, out);
+            e = hipGetLastError();
+        }
         if (e != hipSuccess) return e;
         n0 += now;
         count -= now;

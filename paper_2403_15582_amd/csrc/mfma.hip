@@ -1,16 +1,327 @@
-// Matrix-core (MFMA) static synthesis by angle addition. Placeholder until the
-// kernels land: the direct method serves every request.
+// Static synthesis on the matrix cores by angle addition.
+//
+// For static tones the sample n = n0 + c*M + m (row c, column m of an output
+// matrix with M columns) has phase word theta_kc + w_km with
+//   theta_kc = P_k + F_k (n0 + c M)   and   w_km = F_k m        (both exact words),
+// so sin(theta + w) = sin(theta) cos(w) + cos(theta) sin(w) turns the sum over
+// tones into a product
+//   S[c][m] = sum_k [A_k sin theta_kc, A_k cos theta_kc] . [cos w_km ; sin w_km],
+// a (C x 2K) by (2K x M) matrix multiply. The operands are generated from the
+// exact words (one sincos per element), split into hi + lo halves in FP16 or
+// BF16, and multiplied in three passes hi*hi + hi*lo + lo*hi accumulated in FP32
+// by v_mfma_f32_32x32x16_{f16,bf16}; the epilogue rounds to int16.
+//
+// Operand layout ("fragment order"): for k-block kb (16 inner indices = 8 tones)
+// and row block rb (32 rows), the 64 lanes' 8-element fragments are stored as
+// 1 KB: A[kb][rb][lane][e] with row = rb*32 + lane%32 and inner index
+// kb*16 + 8*(lane/32) + e; B likewise with columns. Inner index 2k is the sine
+// (A) / cosine (B) of tone k, 2k+1 the cosine (A) / sine (B).
 #include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
 
 #include "awg_internal.h"
 
 namespace awg {
 
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+constexpr int kTileRB = 8;            // row blocks per workgroup tile (256 rows)
+constexpr int kTileCB = 8;            // column blocks per workgroup tile (256 columns)
+constexpr int kFragBytes = 64 * 16;   // one 32x16 fragment of 16-bit values
+
+// sin and cos of an (unbiased) phase word to about one FP32 ulp: the turn
+// t = hi32 * 2^-32, rounded to FP32, goes through v_sin / v_cos (arguments in
+// turns), and the exact residual word w - t * 2^64 (below 2^39, i.e. under
+// 1e-7 rad) is applied to first order.
+__device__ __forceinline__ void word_sincos(uint64_t w, float &s, float &c)
+{
+    const int32_t hi = (int32_t)(uint32_t)(w >> 32);
+    const float hf = (float)hi;                                 // rounded to 24 bits
+    const int64_t hr = (int64_t)hf;                             // exact, |hr| <= 2^31
+    const int64_t res = (int64_t)(w - ((uint64_t)hr << 32));    // exact residual word
+    const float t = hf * 0x1p-32f;
+    const float d = (float)res * (6.283185307179586f * 0x1p-64f);
+    const float s0 = __builtin_amdgcn_sinf(t), c0 = __builtin_amdgcn_cosf(t);
+    s = __builtin_fmaf(d, c0, s0);
+    c = __builtin_fmaf(-d, s0, c0);
+}
+
+template <typename T> struct Split;
+template <> struct Split<_Float16> {
+    typedef h8 vec;
+    __device__ static void run(float x, _Float16 &h, _Float16 &l)
+    {
+        h = (_Float16)x;
+        l = (_Float16)(x - (float)h);
+    }
+};
+template <> struct Split<__bf16> {
+    typedef b8 vec;
+    __device__ static void run(float x, __bf16 &h, __bf16 &l)
+    {
+        h = (__bf16)x;
+        l = (__bf16)(x - (float)h);
+    }
+};
+
+// A operand: one thread per (row c, group g of 4 tones) -> 8 inner values.
+template <typename T>
+__global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
+                                                    int32_t n_groups, uint64_t n0, uint64_t mcols,
+                                                    int32_t rb_pad, T *__restrict__ a_hi, T *__restrict__ a_lo)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rows = (int64_t)rb_pad * 32;
+    if (gid >= rows * n_groups) return;
+    const int32_t g = (int32_t)(gid / rows);
+    const int64_t c = gid % rows;
+    const uint64_t n = n0 + (uint64_t)c * mcols;
+    typename Split<T>::vec hv, lv;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int k = 4 * g + t;
+        float xs = 0.0f, xc = 0.0f;
+        if (k < n_tones) {
+            const ToneDev td = tones[k];
+            float s, co;
+            word_sincos(td.p0 - kPhaseBias + td.f0 * n, s, co);
+            xs = td.amp * s;
+            xc = td.amp * co;
+        }
+        T h, l;
+        Split<T>::run(xs, h, l); hv[2 * t] = h; lv[2 * t] = l;
+        Split<T>::run(xc, h, l); hv[2 * t + 1] = h; lv[2 * t + 1] = l;
+    }
+    const int kb = g >> 1, rb = (int)(c >> 5);
+    const int lane = (int)(c & 31) + 32 * (g & 1);
+    const int64_t off = (((int64_t)kb * rb_pad + rb) * 64 + lane);
+    ((typename Split<T>::vec *)a_hi)[off] = hv;
+    ((typename Split<T>::vec *)a_lo)[off] = lv;
+}
+
+// B operand: one thread per (column m, group g of 4 tones).
+template <typename T>
+__global__ __launch_bounds__(256) void gen_b_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
+                                                    int32_t n_groups, int32_t cb_n, T *__restrict__ b_hi,
+                                                    T *__restrict__ b_lo)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cols = (int64_t)cb_n * 32;
+    if (gid >= cols * n_groups) return;
+    const int32_t g = (int32_t)(gid / cols);
+    const int64_t m = gid % cols;
+    typename Split<T>::vec hv, lv;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int k = 4 * g + t;
+        float xc = 0.0f, xs = 0.0f;
+        if (k < n_tones) {
+            const ToneDev td = tones[k];
+            word_sincos(td.f0 * (uint64_t)m, xs, xc);
+        }
+        T h, l;
+        Split<T>::run(xc, h, l); hv[2 * t] = h; lv[2 * t] = l;
+        Split<T>::run(xs, h, l); hv[2 * t + 1] = h; lv[2 * t + 1] = l;
+    }
+    const int kb = g >> 1, cb = (int)(m >> 5);
+    const int lane = (int)(m & 31) + 32 * (g & 1);
+    const int64_t off = (((int64_t)kb * cb_n + cb) * 64 + lane);
+    ((typename Split<T>::vec *)b_hi)[off] = hv;
+    ((typename Split<T>::vec *)b_lo)[off] = lv;
+}
+
+template <typename T>
+__device__ __forceinline__ f16v mfma(const typename Split<T>::vec &a, const typename Split<T>::vec &b, f16v c);
+template <>
+__device__ __forceinline__ f16v mfma<_Float16>(const h8 &a, const h8 &b, f16v c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ f16v mfma<__bf16>(const b8 &a, const b8 &b, f16v c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int16_t to_i16(float y)
+{
+    float r = __builtin_rintf(y);
+    r = fminf(fmaxf(r, -32768.0f), 32767.0f);
+    return (int16_t)(int32_t)r;
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// One workgroup = 4 waves = a 256 x 256 output tile; wave (wr, wc) owns a
+// 128 x 128 quarter (4 x 4 MFMA tiles of 32 x 32, accumulators in AGPRs). Per
+// k-block the tile needs 32 fragments (A hi/lo for 8 row blocks, B hi/lo for 8
+// column blocks, 1 KB each); wave w copies the 8 fragments of one of the four
+// operands straight from global memory into LDS (global_load_lds_dwordx4,
+// lane i -> bytes 16i..16i+15 of a fragment). Two LDS stages: block kb+1 is in
+// flight while block kb is multiplied.
+template <typename T, bool F32OUT>
+__global__ __launch_bounds__(256, 1) void angle_gemm_kernel(const T *__restrict__ a_hi, const T *__restrict__ a_lo,
+                                                            const T *__restrict__ b_hi, const T *__restrict__ b_lo,
+                                                            int32_t kb_n, int32_t rb_pad, int32_t cb_n,
+                                                            uint64_t mcols, uint64_t count, void *__restrict__ out)
+{
+    typedef typename Split<T>::vec V;
+    constexpr int kOperand = kTileRB * kFragBytes;               // 8 KB: one operand half of a stage
+    constexpr int kStage = 4 * kOperand;                         // A hi, A lo, B hi, B lo
+    __shared__ __attribute__((aligned(1024))) char lds[2 * kStage];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wr = wave >> 1, wc = wave & 1;
+    const int rb0 = blockIdx.y * kTileRB, cb0 = blockIdx.x * kTileCB;
+
+    const T *gsrc = wave == 0 ? a_hi : wave == 1 ? a_lo : wave == 2 ? b_hi : b_lo;
+    const int64_t kb_stride = (int64_t)(wave < 2 ? rb_pad : cb_n) * 512;
+    gsrc += (int64_t)(wave < 2 ? rb0 : cb0) * 512 + lane * 8;
+    auto issue = [&](int kb, int buf) {
+        const T *g = gsrc + (int64_t)kb * kb_stride;
+        char *l = lds + buf * kStage + wave * kOperand;
+#pragma unroll
+        for (int i = 0; i < kTileRB; ++i)
+            __builtin_amdgcn_global_load_lds((const void *)(g + i * 512), (lds_void *)(l + i * kFragBytes), 16, 0, 0);
+    };
+
+    f16v acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+    issue(0, 0);
+    for (int kb = 0; kb < kb_n; ++kb) {
+        const int buf = kb & 1;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (kb + 1 < kb_n) issue(kb + 1, buf ^ 1);
+        const V *ah = (const V *)(lds + buf * kStage + 0 * kOperand) + 4 * wr * 64 + lane;
+        const V *al = (const V *)(lds + buf * kStage + 1 * kOperand) + 4 * wr * 64 + lane;
+        const V *bh = (const V *)(lds + buf * kStage + 2 * kOperand) + 4 * wc * 64 + lane;
+        const V *bl = (const V *)(lds + buf * kStage + 3 * kOperand) + 4 * wc * 64 + lane;
+        V fa[4], fb[4], fx[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { fa[i] = ah[i * 64]; fb[i] = bh[i * 64]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma<T>(fa[i], fb[j], acc[i][j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fx[j] = bl[j * 64];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma<T>(fa[i], fx[j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fx[i] = al[i * 64];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma<T>(fx[i], fb[j], acc[i][j]);
+    }
+
+    // epilogue: reg v of lane l in tile (i, j) is row 8(v/4) + 4(l/32) + v%4, column l%32
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t col = (uint64_t)(cb0 + 4 * wc + j) * 32 + (lane & 31);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const uint64_t row = (uint64_t)(rb0 + 4 * wr + i) * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const uint64_t rel = row * mcols + col;
+                if (rel < count) {
+                    if (F32OUT) ((float *)out)[rel] = acc[i][j][v];
+                    else ((int16_t *)out)[rel] = to_i16(acc[i][j][v]);
+                }
+            }
+        }
+    }
+}
+
+static awg_status hipst(hipError_t e)
+{
+    if (e == hipSuccess) return AWG_OK;
+    return e == hipErrorOutOfMemory ? AWG_E_NOMEM : AWG_E_HIP;
+}
+
+template <typename T>
+static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32, hipStream_t s)
+{
+    const uint64_t mcols = count >= (1ull << 20) ? 4096 : 1024;
+    const uint64_t rows = (count + mcols - 1) / mcols;
+    const int32_t rb_pad = (int32_t)(((rows + 31) / 32 + kTileRB - 1) / kTileRB * kTileRB);
+    const int32_t cb_n = (int32_t)(mcols / 32);
+    const int32_t n_groups = (p->n_tones + 3) / 4;
+    const int32_t kb_n = (n_groups + 1) / 2;
+    const size_t frag = kFragBytes;
+    const size_t a_bytes = (size_t)kb_n * rb_pad * frag, b_bytes = (size_t)kb_n * cb_n * frag;
+    const size_t need = 2 * (a_bytes + b_bytes);
+    if (rows > (1ull << 26)) return AWG_E_UNSUPPORTED;
+    if (p->d_work_bytes < need) {
+        if (p->d_work) (void)hipFree(p->d_work);
+        p->d_work = nullptr;
+        p->d_work_bytes = 0;
+        hipError_t e = hipMalloc(&p->d_work, need);
+        if (e != hipSuccess) return hipst(e);
+        p->d_work_bytes = need;
+    }
+    char *w = (char *)p->d_work;
+    T *a_hi = (T *)w, *a_lo = (T *)(w + a_bytes);
+    T *b_hi = (T *)(w + 2 * a_bytes), *b_lo = (T *)(w + 2 * a_bytes + b_bytes);
+    // zero the padding groups of the last k-block (odd group count)
+    const int64_t a_threads = (int64_t)rb_pad * 32 * (2 * kb_n);
+    const int64_t b_threads = (int64_t)cb_n * 32 * (2 * kb_n);
+    const bool f16 = sizeof(T) == 2 && std::is_same<T, _Float16>::value;
+    hipError_t e;
+    {
+        ProfScope prof(p->ctx, s, f16 ? "gen_a_kernel_f16" : "gen_a_kernel_bf16");
+        hipLaunchKernelGGL((gen_a_kernel<T>), dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, s,
+                           p->d_tones, p->n_tones, 2 * kb_n, n0, mcols, rb_pad, a_hi, a_lo);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return hipst(e);
+    {
+        ProfScope prof(p->ctx, s, f16 ? "gen_b_kernel_f16" : "gen_b_kernel_bf16");
+        hipLaunchKernelGGL((gen_b_kernel<T>), dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, s,
+                           p->d_tones, p->n_tones, 2 * kb_n, cb_n, b_hi, b_lo);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return hipst(e);
+    dim3 grid((uint32_t)(cb_n / kTileCB), (uint32_t)(rb_pad / kTileRB));
+    {
+        ProfScope prof(p->ctx, s, f16 ? "angle_gemm_kernel_f16" : "angle_gemm_kernel_bf16");
+        if (out_f32)
+            hipLaunchKernelGGL((angle_gemm_kernel<T, true>), grid, dim3(256), 0, s, a_hi, a_lo, b_hi, b_lo, kb_n,
+                               rb_pad, cb_n, mcols, count, (void *)out_f32);
+        else
+            hipLaunchKernelGGL((angle_gemm_kernel<T, false>), grid, dim3(256), 0, s, a_hi, a_lo, b_hi, b_lo, kb_n,
+                               rb_pad, cb_n, mcols, count, (void *)out_i16);
+        e = hipGetLastError();
+    }
+    return hipst(e);
+}
+
 awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,
                        float *out_f32, hipStream_t s)
 {
-    (void)p; (void)method; (void)n0; (void)count; (void)out_i16; (void)out_f32; (void)s;
-    return AWG_E_UNSUPPORTED;
+    // short requests gain nothing from the matrix cores: the direct kernel serves them
+    if (count < (1ull << 16)) {
+        hipError_t e = out_f32 ? launch_direct_f32(p, n0, count, out_f32, s)
+                               : launch_direct_i16(p, n0, count, out_i16, s);
+        return hipst(e);
+    }
+    if (method == AWG_F_METHOD_MFMA_F16X3) return run<_Float16>(p, n0, count, out_i16, out_f32, s);
+    if (method == AWG_F_METHOD_MFMA_BF16X3) return run<__bf16>(p, n0, count, out_i16, out_f32, s);
+    return AWG_E_INVALID;
 }
 
 }  // namespace awg

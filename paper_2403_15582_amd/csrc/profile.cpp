@@ -1,0 +1,98 @@
+// Per-kernel event timing for awg_profile_*: events are recorded on the launch
+// stream right before and after each kernel; totals are accumulated on read.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "awg_internal.h"
+
+namespace awg {
+
+static hipEvent_t take_event(awg_ctx *c)
+{
+    hipEvent_t e = nullptr;
+    if (!c->prof_pool.empty()) {
+        e = c->prof_pool.back();
+        c->prof_pool.pop_back();
+        return e;
+    }
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(awg_ctx *ctx, hipStream_t s, const char *name)
+    : ctx_(ctx), s_(s), name_(name), start_(nullptr)
+{
+    if (!ctx_ || !ctx_->profiling) return;
+    std::lock_guard<std::mutex> g(ctx_->prof_mu);
+    start_ = take_event(ctx_);
+    if (start_ && hipEventRecord(start_, s_) != hipSuccess) {
+        ctx_->prof_pool.push_back(start_);
+        start_ = nullptr;
+    }
+}
+
+ProfScope::~ProfScope()
+{
+    if (!start_) return;
+    std::lock_guard<std::mutex> g(ctx_->prof_mu);
+    hipEvent_t stop = take_event(ctx_);
+    if (!stop || hipEventRecord(stop, s_) != hipSuccess) {
+        ctx_->prof_pool.push_back(start_);
+        if (stop) ctx_->prof_pool.push_back(stop);
+        return;
+    }
+    ctx_->prof_pending.push_back(ProfRecord{name_, start_, stop});
+}
+
+}  // namespace awg
+
+using namespace awg;
+
+extern "C" {
+
+awg_status awg_profile_enable(awg_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return AWG_E_INVALID;
+    std::lock_guard<std::mutex> g(ctx->prof_mu);
+    ctx->profiling = enable != 0;
+    return AWG_OK;
+}
+
+awg_status awg_profile_read(awg_ctx *ctx, awg_kernel_stat *out, int32_t max_stats, int32_t *n_stats,
+                            int32_t reset)
+{
+    if (!ctx || (max_stats > 0 && !out) || max_stats < 0) return AWG_E_INVALID;
+    std::lock_guard<std::mutex> g(ctx->prof_mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return AWG_E_HIP;
+    awg_status st = AWG_OK;
+    for (auto &r : ctx->prof_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+            st = AWG_E_HIP;
+        ProfTotal &t = ctx->prof_totals[r.name];
+        t.launches += 1;
+        t.total_ms += ms;
+        if (ms > t.max_ms) t.max_ms = ms;
+        ctx->prof_pool.push_back(r.start);
+        ctx->prof_pool.push_back(r.stop);
+    }
+    ctx->prof_pending.clear();
+    int32_t i = 0;
+    for (auto &kv : ctx->prof_totals) {
+        if (i < max_stats) {
+            std::memset(&out[i], 0, sizeof(awg_kernel_stat));
+            std::strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+            out[i].launches = kv.second.launches;
+            out[i].total_ms = kv.second.total_ms;
+            out[i].max_ms = kv.second.max_ms;
+        }
+        ++i;
+    }
+    if (n_stats) *n_stats = i;
+    if (reset) ctx->prof_totals.clear();
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+"""GPU parity of the matrix-core (angle addition) static path against the oracle.
+
+FP16 hi/lo x3 must meet the int16 bar (<= 1 LSB) and the FP32 sum bar; BF16
+hi/lo x3 carries fewer bits, so its unquantised error is only reported (and its
+int16 codes are still required within 1 LSB at the default gain).
+"""
+import numpy as np
+import pytest
+
+import paper_2403_15582_amd as awg
+from paper_2403_15582_amd import workloads as W
+from oracle import words, csynth
+
+from gpu_common import need_gpu, say, to_np, compare
+
+pytestmark = pytest.mark.gpu
+
+F16 = awg.AWG_F_METHOD_MFMA_F16X3
+BF16 = awg.AWG_F_METHOD_MFMA_BF16X3
+
+
+def _pts(rng, n0, count, extra=()):
+    ns = set(rng.integers(n0, n0 + count, 3000).tolist())
+    ns |= set(range(n0, n0 + 300)) | set(range(n0 + count - 300, n0 + count))
+    ns |= set(int(e) for e in extra)
+    return np.array(sorted(n for n in ns if n0 <= n < n0 + count), dtype=np.int64)
+
+
+@pytest.mark.parametrize("method", [F16, BF16])
+def test_config2_full_mfma(method):
+    torch = need_gpu()
+    w = W.config2()
+    lp = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, method)
+    say("config2 full 2^24 x 1000 mfma method=%d" % method)
+    q = to_np(lp.synth_static(0, w.count))
+    y = to_np(lp.synth_f32(0, w.count, method=method))
+    torch.cuda.synchronize()
+    ns = _pts(np.random.default_rng(51), 0, w.count, range(4090, 4100))
+    qo, yo = csynth.synth_at(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), ns)
+    compare(q[ns - 0], y[ns] if method == F16 else None, qo, yo,
+            "config2 mfma method=%d (sampled %d)" % (method, len(ns)))
+    dy = np.abs(y[ns].astype(np.float64) - yo)
+    say("config2 mfma method=%d unquantised max|dy| = %.4f LSB, rms %.5f" %
+        (method, dy.max(), np.sqrt(np.mean(dy ** 2))))
+
+
+@pytest.mark.parametrize("n0,count", [(12345, (1 << 20) + 777), (3, 1 << 16), (2 ** 41 + 9, 300000),
+                                      (0, 5000)])
+def test_mfma_ragged_ranges(n0, count):
+    torch = need_gpu()
+    w = W.config2(K=333)
+    lp = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, F16)
+    say("mfma ragged n0=%d count=%d K=333" % (n0, count))
+    q = to_np(lp.synth_static(n0, count))
+    y = to_np(lp.synth_f32(n0, count, method=F16))
+    torch.cuda.synchronize()
+    ns = _pts(np.random.default_rng(52), n0, count)
+    qo, yo = csynth.synth_at(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), ns)
+    compare(q[ns - n0], y[ns - n0], qo, yo, "mfma ragged n0=%d count=%d" % (n0, count))
+
+
+def test_mfma_peak_gain():
+    """Gain raised so the buffer peaks near 90% of full scale (Schroeder phases)."""
+    torch = need_gpu()
+    w = W.config2()
+    op1 = words.Plan(w.fs_hz, 1.0, w.period_log2, w.tones)
+    _, y1 = csynth.synth(op1, 0, 1 << 16)
+    gain = 0.9 * 32767.0 / float(np.max(np.abs(y1)))
+    say("peak gain %.2f LSB per unit amplitude" % gain)
+    ns = _pts(np.random.default_rng(53), 0, w.count)
+    qo, yo = csynth.synth_at(words.Plan(w.fs_hz, gain, w.period_log2, w.tones), ns)
+    for method in (F16, BF16, awg.AWG_F_METHOD_DIRECT):
+        lp = awg.Plan(w.tones, w.fs_hz, gain, w.period_log2, method)
+        q = to_np(lp.synth_static(0, w.count))
+        y = to_np(lp.synth_f32(0, w.count, method=method))
+        torch.cuda.synchronize()
+        dq = np.abs(q[ns].astype(np.int32) - qo.astype(np.int32))
+        dy = np.abs(y[ns].astype(np.float64) - yo)
+        say("peak gain method=%d: max|dq|=%d max|dy|=%.4f rms|dy|=%.5f LSB"
+            % (method, dq.max(), dy.max(), np.sqrt(np.mean(dy ** 2))))
+        if method != BF16:
+            assert dq.max() <= 1 and dy.max() <= 0.5
+
+
+def test_mfma_equals_direct_within_one_lsb_everywhere():
+    torch = need_gpu()
+    w = W.config1()
+    a = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, F16)
+    b = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, awg.AWG_F_METHOD_DIRECT)
+    qa = to_np(a.synth_static(0, w.count))
+    qb = to_np(b.synth_static(0, w.count))
+    torch.cuda.synchronize()
+    qo, _ = csynth.synth(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), 0, w.count)
+    compare(qa, None, qo, None, "config1 mfma vs oracle (all samples)")
+    assert np.max(np.abs(qa.astype(np.int32) - qb.astype(np.int32))) <= 2
