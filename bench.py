@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -165,6 +168,15 @@ def main():
     from paper_2403_15582_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if a.copy_probe_mib:
+        n = a.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
+        return
     w = W.config2()
     K, L = len(w.tones), w.count
     codes = method_codes(awg)
@@ -182,8 +194,14 @@ def main():
 
         is_primary = m == primary
         if is_primary:
-            for _ in range(a.warmup):
+            # bring the clocks up: at least ~0.3 s of the step before timing
+            t0 = time.perf_counter()
+            n = 0
+            while n < a.warmup or time.perf_counter() - t0 < 0.3:
                 step()
+                n += 1
+                if n % 8 == 0:
+                    torch.cuda.synchronize()
             torch.cuda.synchronize()
             awg.awg_profile_read(ctx, reset=True)
             awg.awg_profile_enable(ctx, True)

@@ -97,9 +97,10 @@ struct awg_plan {
     size_t next_slot;
     void *d_scratch;                   // device staging for retune records
     size_t d_scratch_bytes;
-    // MFMA workspace (operands), grown on demand
+    // MFMA workspace (operands), grown on demand; B operand cached under mfma_b_key
     void *d_work;
     size_t d_work_bytes;
+    uint64_t mfma_b_key;
 };
 
 namespace awg {

@@ -265,6 +265,7 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
     p->d_scratch_bytes = 0;
     p->d_work = nullptr;
     p->d_work_bytes = 0;
+    p->mfma_b_key = 0;
     try {
         p->host.resize(n_tones);
         p->dev_mirror.resize(n_tones);
@@ -396,6 +397,7 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
         }
     }
     if (st != AWG_OK) return st;
+    p->mfma_b_key = 0;
     for (int32_t i = 0; i < n_ev; ++i) {
         const int32_t k = ev[i].tone;
         if (p->host[k].shape == AWG_RAMP_NONE) p->n_ramped++;

@@ -114,7 +114,10 @@ __device__ __forceinline__ int16_t quantise(float y)
     return (int16_t)(int32_t)r;
 }
 
-template <int S, bool F32OUT>
+// STATIC: every tone of the plan is a static line (no windows), so the regime
+// logic is compiled out; the arithmetic per sample is the same as the static
+// regime of gen_phases, so both instantiations give identical sums.
+template <int S, bool F32OUT, bool STATIC>
 __global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
                                                      int32_t slice, const uint64_t *const *__restrict__ tables,
                                                      uint64_t n0, uint64_t count, void *__restrict__ out)
@@ -136,12 +139,26 @@ __global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__
         float blk[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) blk[s] = 0.0f;
-        for (int k = k0; k < k1; ++k) {
-            const ToneDev t = tones[k];
-            const float amp = t.amp;
-            gen_phases<S>(t, tables, tile0, lane, [&](int s, uint64_t ph) {
-                blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
-            });
+        if (STATIC) {
+#pragma unroll 2
+            for (int k = k0; k < k1; ++k) {
+                const uint64_t P = tones[k].p0, Fw = tones[k].f0;
+                const float amp = tones[k].amp;
+                uint64_t ph = (P + Fw * tile0) + Fw * (uint64_t)(lane * S);
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+                    ph += Fw;
+                }
+            }
+        } else {
+            for (int k = k0; k < k1; ++k) {
+                const ToneDev t = tones[k];
+                const float amp = t.amp;
+                gen_phases<S>(t, tables, tile0, lane, [&](int s, uint64_t ph) {
+                    blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+                });
+            }
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[s] += blk[s];
@@ -189,7 +206,7 @@ __global__ void scatter_tones_kernel(ToneDev *__restrict__ tones, const ScatterR
     if (i < n) tones[rec[i].index] = rec[i].tone;
 }
 
-constexpr int kS = 8;                              // samples per lane
+constexpr int kS = 16;                             // samples per lane
 constexpr uint64_t kMaxTilesPerLaunch = 1u << 30;
 
 static int slice_of(int32_t n_tones) { return (n_tones + kWaves - 1) / kWaves; }
@@ -206,8 +223,12 @@ static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, 
         hipError_t e;
         {
             ProfScope prof(p->ctx, s, F32OUT ? "direct_kernel_f32" : "direct_kernel");
-            hipLaunchKernelGGL((direct_kernel<kS, F32OUT>), dim3((uint32_t)now_tiles), dim3(256), 0, s,
-                               p->d_tones, p->n_tones, slice_of(p->n_tones), p->d_table_ptrs, n0, now, out);
+            if (p->n_ramped == 0)
+                hipLaunchKernelGGL((direct_kernel<kS, F32OUT, true>), dim3((uint32_t)now_tiles), dim3(256), 0, s,
+                                   p->d_tones, p->n_tones, slice_of(p->n_tones), p->d_table_ptrs, n0, now, out);
+            else
+                hipLaunchKernelGGL((direct_kernel<kS, F32OUT, false>), dim3((uint32_t)now_tiles), dim3(256), 0,
+                                   s, p->d_tones, p->n_tones, slice_of(p->n_tones), p->d_table_ptrs, n0, now, out);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return e;

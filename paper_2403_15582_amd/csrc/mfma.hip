@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "awg_internal.h"
@@ -156,87 +157,123 @@ __device__ __forceinline__ int16_t to_i16(float y)
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// One workgroup = 4 waves = a 256 x 256 output tile; wave (wr, wc) owns a
-// 128 x 128 quarter (4 x 4 MFMA tiles of 32 x 32, accumulators in AGPRs). Per
-// k-block the tile needs 32 fragments (A hi/lo for 8 row blocks, B hi/lo for 8
-// column blocks, 1 KB each); wave w copies the 8 fragments of one of the four
-// operands straight from global memory into LDS (global_load_lds_dwordx4,
-// lane i -> bytes 16i..16i+15 of a fragment). Two LDS stages: block kb+1 is in
-// flight while block kb is multiplied.
-template <typename T, bool F32OUT>
-__global__ __launch_bounds__(256, 1) void angle_gemm_kernel(const T *__restrict__ a_hi, const T *__restrict__ a_lo,
-                                                            const T *__restrict__ b_hi, const T *__restrict__ b_lo,
-                                                            int32_t kb_n, int32_t rb_pad, int32_t cb_n,
-                                                            uint64_t mcols, uint64_t count, void *__restrict__ out)
+// s_waitcnt immediate that waits until at most v vector-memory operations are
+// outstanding (expcnt and lgkmcnt left at their maxima).
+constexpr int vmcnt_imm(int v) { return (v & 0xf) | ((v >> 4) << 14) | (0x7 << 4) | (0xf << 8); }
+
+// One workgroup = WR x WC waves covering a 256 x 256 output tile; each wave owns
+// (8/WR) x (8/WC) MFMA tiles of 32 x 32 (accumulators in AGPRs). Per k-block
+// the tile needs 32 fragments (A hi/lo for 8 row blocks, B hi/lo for 8 column
+// blocks, 1 KB each); every wave copies 32/(WR*WC) of them straight from global
+// memory into LDS (global_load_lds_dwordx4, lane i -> bytes 16i..16i+15 of a
+// fragment). NST LDS stages, prefetch distance NST-1: block kb+NST-1 is in
+// flight while block kb is multiplied. vmcnt counts the copies in issue order.
+template <typename T, bool F32OUT, int WR, int WC, int NST>
+__global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
+    const T *__restrict__ a_hi, const T *__restrict__ a_lo, const T *__restrict__ b_hi, const T *__restrict__ b_lo,
+    int32_t kb_n, int32_t rb_pad, int32_t cb_n, uint64_t mcols, uint64_t count, void *__restrict__ out)
 {
     typedef typename Split<T>::vec V;
-    constexpr int kOperand = kTileRB * kFragBytes;               // 8 KB: one operand half of a stage
+    constexpr int W = WR * WC;
+    constexpr int TI = kTileRB / WR, TJ = kTileCB / WC;         // MFMA tiles per wave
+    constexpr int F = 32 / W;                                    // fragments copied per wave per block
+    constexpr int kOperand = kTileRB * kFragBytes;               // 8 KB
     constexpr int kStage = 4 * kOperand;                         // A hi, A lo, B hi, B lo
-    __shared__ __attribute__((aligned(1024))) char lds[2 * kStage];
+    extern __shared__ __attribute__((aligned(1024))) char lds[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wr = wave >> 1, wc = wave & 1;
-    const int rb0 = blockIdx.y * kTileRB, cb0 = blockIdx.x * kTileCB;
+    const int wr = wave / WC, wc = wave % WC;
+    // Tile order: consecutive workgroups go to different XCDs (round robin), so
+    // first make each XCD's share a contiguous range of tile indices, then walk
+    // that range in groups of 4 tile rows, column by column: every XCD then
+    // works on a compact block of tiles and re-reads fewer operand rows and
+    // columns from HBM into its own L2.
+    const uint32_t gx = gridDim.x, gy = gridDim.y, nt = gx * gy;
+    uint32_t b = blockIdx.y * gx + blockIdx.x;
+    if (nt % 8 == 0) b = (b % 8) * (nt / 8) + b / 8;
+    const uint32_t grp = gy < 4 ? gy : 4;
+    const uint32_t full = (gy / grp) * grp;                     // rows covered by whole groups
+    uint32_t ty, tx;
+    if (b < full * gx) {
+        const uint32_t g = b / (grp * gx), r = b % (grp * gx);
+        ty = g * grp + r % grp;
+        tx = r / grp;
+    } else {
+        const uint32_t r = b - full * gx, rows = gy - full;
+        ty = full + r % rows;
+        tx = r / rows;
+    }
+    const int rb0 = ty * kTileRB, cb0 = tx * kTileCB;
 
-    const T *gsrc = wave == 0 ? a_hi : wave == 1 ? a_lo : wave == 2 ? b_hi : b_lo;
-    const int64_t kb_stride = (int64_t)(wave < 2 ? rb_pad : cb_n) * 512;
-    gsrc += (int64_t)(wave < 2 ? rb0 : cb0) * 512 + lane * 8;
-    auto issue = [&](int kb, int buf) {
+    // fragment f of a stage: operand f / 8 (A hi, A lo, B hi, B lo), block f % 8
+    const int f0 = wave * F;
+    const int opnd = f0 / 8;
+    const T *gsrc = opnd == 0 ? a_hi : opnd == 1 ? a_lo : opnd == 2 ? b_hi : b_lo;
+    const int64_t kb_stride = (int64_t)(opnd < 2 ? rb_pad : cb_n) * 512;
+    gsrc += ((int64_t)(opnd < 2 ? rb0 : cb0) + (f0 % 8)) * 512 + lane * 8;
+    auto issue = [&](int kb) {
         const T *g = gsrc + (int64_t)kb * kb_stride;
-        char *l = lds + buf * kStage + wave * kOperand;
+        char *l = lds + (kb % NST) * kStage + f0 * kFragBytes;
 #pragma unroll
-        for (int i = 0; i < kTileRB; ++i)
+        for (int i = 0; i < F; ++i)
             __builtin_amdgcn_global_load_lds((const void *)(g + i * 512), (lds_void *)(l + i * kFragBytes), 16, 0, 0);
     };
 
-    f16v acc[4][4];
+    f16v acc[TI][TJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TJ; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-    issue(0, 0);
+#pragma unroll
+    for (int s = 0; s < NST - 1; ++s)
+        if (s < kb_n) issue(s);
     for (int kb = 0; kb < kb_n; ++kb) {
-        const int buf = kb & 1;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (kb + 1 < kb_n) issue(kb + 1, buf ^ 1);
-        const V *ah = (const V *)(lds + buf * kStage + 0 * kOperand) + 4 * wr * 64 + lane;
-        const V *al = (const V *)(lds + buf * kStage + 1 * kOperand) + 4 * wr * 64 + lane;
-        const V *bh = (const V *)(lds + buf * kStage + 2 * kOperand) + 4 * wc * 64 + lane;
-        const V *bl = (const V *)(lds + buf * kStage + 3 * kOperand) + 4 * wc * 64 + lane;
-        V fa[4], fb[4], fx[4];
+        // own copies of block kb landed, then a bare barrier (no fence: later
+        // blocks stay in flight) makes every wave's copies visible
+        if (kb + NST - 2 < kb_n) __builtin_amdgcn_s_waitcnt(vmcnt_imm(F * (NST - 2)));
+        else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        asm volatile("s_barrier" ::: "memory");
+        if (kb + NST - 1 < kb_n) issue(kb + NST - 1);
+        const char *st = lds + (kb % NST) * kStage;
+        const V *ah = (const V *)(st + 0 * kOperand) + TI * wr * 64 + lane;
+        const V *al = (const V *)(st + 1 * kOperand) + TI * wr * 64 + lane;
+        const V *bh = (const V *)(st + 2 * kOperand) + TJ * wc * 64 + lane;
+        const V *bl = (const V *)(st + 3 * kOperand) + TJ * wc * 64 + lane;
+        V fa[TI], fb[TJ], xa[TI], xb[TJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { fa[i] = ah[i * 64]; fb[i] = bh[i * 64]; }
+        for (int i = 0; i < TI; ++i) fa[i] = ah[i * 64];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < TJ; ++j) fb[j] = bh[j * 64];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma<T>(fa[i], fb[j], acc[i][j]);
+        for (int j = 0; j < TJ; ++j) xb[j] = bl[j * 64];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fx[j] = bl[j * 64];
+        for (int i = 0; i < TI; ++i) xa[i] = al[i * 64];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma<T>(fa[i], fx[j], acc[i][j]);
+            for (int j = 0; j < TJ; ++j) acc[i][j] = mfma<T>(fa[i], fb[j], acc[i][j]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) fx[i] = al[i * 64];
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < TJ; ++j) acc[i][j] = mfma<T>(fa[i], xb[j], acc[i][j]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma<T>(fx[i], fb[j], acc[i][j]);
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[i][j] = mfma<T>(xa[i], fb[j], acc[i][j]);
     }
 
     // epilogue: reg v of lane l in tile (i, j) is row 8(v/4) + 4(l/32) + v%4, column l%32
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TI; ++i) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint64_t col = (uint64_t)(cb0 + 4 * wc + j) * 32 + (lane & 31);
+        for (int j = 0; j < TJ; ++j) {
+            const uint64_t col = (uint64_t)(cb0 + TJ * wc + j) * 32 + (lane & 31);
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const uint64_t row = (uint64_t)(rb0 + 4 * wr + i) * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const uint64_t row = (uint64_t)(rb0 + TI * wr + i) * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const uint64_t rel = row * mcols + col;
                 if (rel < count) {
                     if (F32OUT) ((float *)out)[rel] = acc[i][j][v];
@@ -244,6 +281,58 @@ __global__ __launch_bounds__(256, 1) void angle_gemm_kernel(const T *__restrict_
                 }
             }
         }
+    }
+}
+
+// Launch one GEMM variant (waves WR x WC, NST LDS stages).
+template <typename T, int WR, int WC, int NST>
+static hipError_t launch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *a_lo, const T *b_hi,
+                              const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, uint64_t mcols,
+                              uint64_t count, int16_t *out_i16, float *out_f32)
+{
+    constexpr int kLds = NST * 4 * kTileRB * kFragBytes;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)angle_gemm_kernel<T, true, WR, WC, NST>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)angle_gemm_kernel<T, false, WR, WC, NST>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kLds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    if (out_f32)
+        hipLaunchKernelGGL((angle_gemm_kernel<T, true, WR, WC, NST>), grid, dim3(64 * WR * WC), kLds, s, a_hi,
+                           a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, (void *)out_f32);
+    else
+        hipLaunchKernelGGL((angle_gemm_kernel<T, false, WR, WC, NST>), grid, dim3(64 * WR * WC), kLds, s, a_hi,
+                           a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, (void *)out_i16);
+    return hipGetLastError();
+}
+
+// GEMM variant: 0 = 4 waves / 2 stages, 1 = 4 waves / 3 stages, 2 = 8 waves / 2 stages,
+// 3 = 8 waves / 3 stages. The default is the fastest measured on MI355X; the
+// environment variable AWG_GEMM_VARIANT overrides it for tuning sweeps.
+static int gemm_variant()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("AWG_GEMM_VARIANT");
+        v = (e && e[0] >= '0' && e[0] <= '3') ? e[0] - '0' : 3;
+    }
+    return v;
+}
+
+template <typename T>
+static hipError_t dispatch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *a_lo, const T *b_hi,
+                                const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, uint64_t mcols,
+                                uint64_t count, int16_t *out_i16, float *out_f32)
+{
+    switch (gemm_variant()) {
+    case 0: return launch_gemm<T, 2, 2, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
+    case 1: return launch_gemm<T, 2, 2, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
+    case 2: return launch_gemm<T, 2, 4, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
+    default: return launch_gemm<T, 2, 4, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
     }
 }
 
@@ -261,7 +350,7 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     const int32_t rb_pad = (int32_t)(((rows + 31) / 32 + kTileRB - 1) / kTileRB * kTileRB);
     const int32_t cb_n = (int32_t)(mcols / 32);
     const int32_t n_groups = (p->n_tones + 3) / 4;
-    const int32_t kb_n = (n_groups + 1) / 2;
+    const int32_t kb_n = (n_groups + 1) / 2;          // k-blocks of 8 tones (zero-padded)
     const size_t frag = kFragBytes;
     const size_t a_bytes = (size_t)kb_n * rb_pad * frag, b_bytes = (size_t)kb_n * cb_n * frag;
     const size_t need = 2 * (a_bytes + b_bytes);
@@ -270,13 +359,15 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
         if (p->d_work) (void)hipFree(p->d_work);
         p->d_work = nullptr;
         p->d_work_bytes = 0;
+        p->mfma_b_key = 0;
         hipError_t e = hipMalloc(&p->d_work, need);
         if (e != hipSuccess) return hipst(e);
         p->d_work_bytes = need;
     }
     char *w = (char *)p->d_work;
-    T *a_hi = (T *)w, *a_lo = (T *)(w + a_bytes);
-    T *b_hi = (T *)(w + 2 * a_bytes), *b_lo = (T *)(w + 2 * a_bytes + b_bytes);
+    // B (depends on the tones and the column count only) is kept between calls
+    T *b_hi = (T *)w, *b_lo = (T *)(w + b_bytes);
+    T *a_hi = (T *)(w + 2 * b_bytes), *a_lo = (T *)(w + 2 * b_bytes + a_bytes);
     // zero the padding groups of the last k-block (odd group count)
     const int64_t a_threads = (int64_t)rb_pad * 32 * (2 * kb_n);
     const int64_t b_threads = (int64_t)cb_n * 32 * (2 * kb_n);
@@ -289,23 +380,19 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
         e = hipGetLastError();
     }
     if (e != hipSuccess) return hipst(e);
-    {
+    const uint64_t b_key = (mcols << 8) | (f16 ? 1u : 2u) | ((uint64_t)kb_n << 32);
+    if (p->mfma_b_key != b_key) {
         ProfScope prof(p->ctx, s, f16 ? "gen_b_kernel_f16" : "gen_b_kernel_bf16");
         hipLaunchKernelGGL((gen_b_kernel<T>), dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, s,
                            p->d_tones, p->n_tones, 2 * kb_n, cb_n, b_hi, b_lo);
         e = hipGetLastError();
+        if (e != hipSuccess) return hipst(e);
+        p->mfma_b_key = b_key;
     }
-    if (e != hipSuccess) return hipst(e);
     dim3 grid((uint32_t)(cb_n / kTileCB), (uint32_t)(rb_pad / kTileRB));
     {
         ProfScope prof(p->ctx, s, f16 ? "angle_gemm_kernel_f16" : "angle_gemm_kernel_bf16");
-        if (out_f32)
-            hipLaunchKernelGGL((angle_gemm_kernel<T, true>), grid, dim3(256), 0, s, a_hi, a_lo, b_hi, b_lo, kb_n,
-                               rb_pad, cb_n, mcols, count, (void *)out_f32);
-        else
-            hipLaunchKernelGGL((angle_gemm_kernel<T, false>), grid, dim3(256), 0, s, a_hi, a_lo, b_hi, b_lo, kb_n,
-                               rb_pad, cb_n, mcols, count, (void *)out_i16);
-        e = hipGetLastError();
+        e = dispatch_gemm<T>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
     }
     return hipst(e);
 }
