@@ -131,6 +131,22 @@ def method_codes(awg):
             "mfma-bf16": awg.AWG_F_METHOD_MFMA_BF16X3}
 
 
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/traffic.json), or None when it is missing or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["sha256_16"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def roofline_for(method, stats, K, L):
     """Dominant kernel of the step and its algorithmic rate against the MI355X peak."""
     name, (launches, total_ms, _) = max(stats.items(), key=lambda kv: kv[1][1])
@@ -139,7 +155,7 @@ def roofline_for(method, stats, K, L):
         flop = 2.0 * K * L                        # one weighting FMA per tone-sample
         ach = flop / (avg_ms * 1e-3) / 1e12
         return {"bound": "alu", "kernel": name, "achieved": ach, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": traffic_for(name),
                 "avg_kernel_ms": avg_ms,
                 "note": "2 algorithmic flop per tone-sample over the FP32 vector peak; the kernel "
                         "is bound by VALU issue including one v_sin_f32 per tone-sample"}
@@ -149,7 +165,7 @@ def roofline_for(method, stats, K, L):
     ach = flop / (avg_ms * 1e-3) / 1e12
     peak = PEAK_FP16_TFLOPS
     return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-            "frac": ach / peak, "traffic": None, "avg_kernel_ms": avg_ms,
+            "frac": ach / peak, "traffic": traffic_for(name), "avg_kernel_ms": avg_ms,
             "issued_tflops": issued / (avg_ms * 1e-3) / 1e12,
             "issued_frac": issued / (avg_ms * 1e-3) / 1e12 / peak,
             "note": "achieved counts 4 algorithmic flop per tone-sample; the FP16 hi/lo split "
