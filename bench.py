@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--method", default="auto", choices=["auto", "direct", "mfma-f16", "mfma-bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streaming, serving and large-array legs")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -124,6 +125,71 @@ def streaming_leg(torch, awg, W):
             "tone_samples_per_s": len(w.tones) * w.chunk / (float(np.mean(lat)) * 1e-3),
             "rtf_p99": chunk_s / (p99 * 1e-3), "rtf_mean": chunk_s / (float(np.mean(lat)) * 1e-3),
             "latency_note": "device time per 2^20-sample chunk (hipEvents on the launch stream)"}
+
+
+def serving_leg(W, seconds):
+    """Config-5 style trace in real time: Poisson arrivals of chirp jobs, batched
+    by the library's server; latency, throughput and deadline misses."""
+    from paper_2403_15582_amd.serving import Server
+    jobs = W.config5(seconds=seconds)
+    with Server(mem_budget_bytes=1 << 30, max_jobs=512, ring_slots=256, playout_delay_ms=5.0) as srv:
+        t0 = time.perf_counter()
+        srv.run_trace(jobs, time_scale=1.0, timeout_s=300.0)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    offered = sum(len(j.tones) * j.n_samples for j in jobs) / seconds
+    return {"workload": "poisson-chirp-jobs-2000/s", "jobs": len(jobs), "arrival_seconds": seconds,
+            "offered_tone_samples_per_s": offered,
+            "tone_samples_per_s": st["tone_samples"] / (st["wall_ms"] * 1e-3),
+            "device_busy_frac": st["device_busy_ms"] / st["wall_ms"],
+            "output_seconds_per_second": st["audio_seconds"] / (st["wall_ms"] * 1e-3),
+            "p50_chunk_ms": st["chunk_latency_p50_ms"], "p99_chunk_ms": st["chunk_latency_p99_ms"],
+            "p50_first_chunk_ms": st["first_chunk_latency_p50_ms"],
+            "p99_first_chunk_ms": st["first_chunk_latency_p99_ms"],
+            "deadline_misses": st["deadline_misses"], "chunks": st["chunks_done"],
+            "mean_batch": st["mean_batch"], "max_batch": st["max_batch"], "steps": st["steps"],
+            "wall_s": wall,
+            "latency_note": "chunk latency = chunk ready - job arrival (host clock); deadline = "
+                            "arrival + 5 ms + chunk start / fs"}
+
+
+def large_array_leg(torch, awg, W, K):
+    """Config-4 style stream: K tones, groups of 100 retuned (1 ms linear chirps)
+    in turn, 2^20-sample chunks over 1 s of output; per-chunk device time."""
+    w = W.config4(K=K)
+    plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2)
+    events = sorted(w.retunes, key=lambda e: e[1])
+    n_chunks = w.count // w.chunk
+    buf = [torch.empty(w.chunk, dtype=torch.int16, device="cuda") for _ in range(2)]
+    s = torch.cuda.current_stream()
+    i = 0
+    evs = []
+    t0 = time.perf_counter()
+    for c in range(n_chunks):
+        end = (c + 1) * w.chunk
+        batch = []
+        while i < len(events) and events[i][1] < end:
+            k, a, n, shape, f = events[i]
+            batch.append((k, shape, a, n, f))
+            i += 1
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        if batch:
+            plan.retune(batch)
+        plan.stream_next(w.chunk, out=buf[c % 2])
+        e1.record(s)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    chunk_s = w.chunk / w.fs_hz
+    plan.close()
+    return {"workload": w.name, "tones": K, "chunks": n_chunks, "retunes": len(events),
+            "p50_chunk_ms": float(np.percentile(lat, 50)), "p99_chunk_ms": float(np.percentile(lat, 99)),
+            "tone_samples_per_s": K * w.chunk / (float(np.mean(lat)) * 1e-3),
+            "rtf_mean": chunk_s / (float(np.mean(lat)) * 1e-3), "rtf_p99": chunk_s / (float(np.percentile(lat, 99)) * 1e-3),
+            "wall_s": wall}
 
 
 def method_codes(awg):
@@ -250,6 +316,10 @@ def main():
     if not a.no_stream:
         log("streaming leg ...")
         res["streaming"] = streaming_leg(torch, awg, W)
+        log("large-array legs ...")
+        res["large_arrays"] = [large_array_leg(torch, awg, W, K) for K in (5000, 10000)]
+        log("serving leg ...")
+        res["serving"] = serving_leg(W, a.serve_seconds)
     print(json.dumps(res), flush=True)
 
 

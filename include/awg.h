@@ -200,6 +200,83 @@ awg_status awg_synth_f32(awg_plan *plan, uint32_t method, uint64_t n0, uint64_t 
 awg_status awg_phase_dump(awg_plan *plan, int32_t tone, uint64_t n0, uint64_t count,
                           uint64_t *d_words, void *hip_stream);
 
+/* ---------------------------------------------------------------- serving */
+
+/* Continuous batching of synthesis jobs on one device. A job is one tone set
+ * with its own sample rate and length (e.g. a tweezer rearrangement: every tone
+ * chirps across the job). Jobs are admitted in arrival order as job slots and
+ * device memory free up; every step takes one chunk from each admitted job that
+ * has samples left and a free slot in the device output ring, and runs all of
+ * them in one launch (a replayed hipGraph of the batched kernel). A job's
+ * samples are bit-identical to awg_synth_chirp of the same tones, whatever it
+ * is batched with. The consumer (the DAC's stand-in) polls chunk events, reads
+ * the ring slot and releases it. */
+typedef struct awg_server awg_server;
+
+typedef struct {
+    uint64_t mem_budget_bytes;   /* device memory for the ring and the jobs' tone tables */
+    int32_t max_jobs;            /* jobs admitted at once (also the largest batch) */
+    int32_t ring_slots;          /* output chunk slots in the device ring */
+    uint32_t chunk_len;          /* samples per chunk, a multiple of 1024 */
+    int32_t max_pending;         /* submitted jobs waiting for admission */
+    double playout_delay_ms;     /* chunk c of a job is due at submit + delay + c * chunk_len / fs */
+} awg_server_params;
+
+typedef struct {
+    double fs_hz;
+    double gain_lsb;             /* as in awg_plan_params */
+    uint32_t period_log2;
+    uint32_t reserved;           /* must be 0 */
+    const awg_tone *tones;       /* host, n_tones entries, read during the call */
+    int32_t n_tones;
+    int32_t reserved2;           /* must be 0 */
+    uint64_t n_samples;          /* job length: samples 0 .. n_samples-1 */
+    uint64_t user_tag;
+} awg_job;
+
+typedef struct {
+    uint64_t job_id, user_tag;
+    uint64_t chunk_index;
+    uint64_t n0, count;          /* samples n0 .. n0+count-1 of the job */
+    int32_t slot;                /* ring slot holding them (awg_server_slot) */
+    int32_t last;                /* 1 on the job's final chunk */
+    double t_submit_ms, t_ready_ms;   /* host steady clock */
+} awg_chunk_event;
+
+typedef struct {
+    uint64_t jobs_submitted, jobs_admitted, jobs_done, jobs_pending, jobs_active;
+    uint64_t chunks_done, steps, max_batch;
+    double mean_batch;
+    double tone_samples;             /* synthesised tone-samples */
+    double audio_seconds;            /* synthesised output duration, sum over jobs */
+    double device_busy_ms;           /* device time of all steps */
+    double wall_ms;                  /* first submit to last chunk ready */
+    double chunk_latency_p50_ms, chunk_latency_p99_ms;            /* chunk ready - job submit */
+    double first_chunk_latency_p50_ms, first_chunk_latency_p99_ms;
+    uint64_t deadline_misses;        /* chunks ready after submit + delay + n0 / fs */
+    uint64_t pool_free_bytes;
+} awg_server_stats;
+
+/* Start a server (and its scheduler thread) on ctx's device. AWG_E_INVALID for
+ * bad parameters, AWG_E_RANGE if the budget cannot hold the ring. */
+awg_status awg_server_create(awg_ctx *ctx, const awg_server_params *params, awg_server **out);
+/* Stop the scheduler, wait for running steps and free everything. */
+awg_status awg_server_destroy(awg_server *srv);
+/* Queue a job. The words are planned here (errors as awg_plan_tones);
+ * AWG_E_BUSY when max_pending jobs already wait, AWG_E_NOMEM when the job's
+ * tables can never fit the budget. */
+awg_status awg_server_submit(awg_server *srv, const awg_job *job, uint64_t *job_id);
+/* Completed chunks, oldest first (up to max_events into out, count in *n_events). */
+awg_status awg_server_poll(awg_server *srv, awg_chunk_event *out, int32_t max_events, int32_t *n_events);
+/* Device address of ring slot `slot` (chunk_len int16 samples). */
+awg_status awg_server_slot(awg_server *srv, int32_t slot, int16_t **d_ptr);
+/* Copy the first count samples of a ready slot (one the consumer holds) to dst,
+ * host or device memory; returns when the copy is done. */
+awg_status awg_server_read(awg_server *srv, int32_t slot, uint64_t count, int16_t *dst);
+/* Hand a slot back after its chunk has been consumed. */
+awg_status awg_server_release(awg_server *srv, int32_t slot);
+awg_status awg_server_stats_get(awg_server *srv, awg_server_stats *stats);
+
 /* -------------------------------------------------------------- profiling */
 
 /* Per-kernel device time, measured with HIP events recorded on the launch

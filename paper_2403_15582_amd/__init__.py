@@ -31,6 +31,8 @@ EXPORTED = [
     "awg_synth_static", "awg_synth_chirp", "awg_stream_next", "awg_stream_seek",
     "awg_stream_tell", "awg_synth_f32", "awg_phase_dump", "awg_strerror", "awg_version",
     "awg_profile_enable", "awg_profile_read",
+    "awg_server_create", "awg_server_destroy", "awg_server_submit", "awg_server_poll",
+    "awg_server_slot", "awg_server_read", "awg_server_release", "awg_server_stats_get",
 ]
 
 
@@ -55,6 +57,37 @@ class awg_plan_info(ctypes.Structure):
 class awg_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64),
                 ("total_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
+class awg_server_params(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_jobs", ctypes.c_int32),
+                ("ring_slots", ctypes.c_int32), ("chunk_len", ctypes.c_uint32),
+                ("max_pending", ctypes.c_int32), ("playout_delay_ms", ctypes.c_double)]
+
+
+class awg_job(ctypes.Structure):
+    _fields_ = [("fs_hz", ctypes.c_double), ("gain_lsb", ctypes.c_double),
+                ("period_log2", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("tones", ctypes.c_void_p), ("n_tones", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("n_samples", ctypes.c_uint64), ("user_tag", ctypes.c_uint64)]
+
+
+class awg_chunk_event(ctypes.Structure):
+    _fields_ = [("job_id", ctypes.c_uint64), ("user_tag", ctypes.c_uint64),
+                ("chunk_index", ctypes.c_uint64), ("n0", ctypes.c_uint64), ("count", ctypes.c_uint64),
+                ("slot", ctypes.c_int32), ("last", ctypes.c_int32),
+                ("t_submit_ms", ctypes.c_double), ("t_ready_ms", ctypes.c_double)]
+
+
+class awg_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("jobs_submitted", "jobs_admitted", "jobs_done",
+                                               "jobs_pending", "jobs_active", "chunks_done", "steps",
+                                               "max_batch")] + \
+               [(n, ctypes.c_double) for n in ("mean_batch", "tone_samples", "audio_seconds",
+                                               "device_busy_ms", "wall_ms", "chunk_latency_p50_ms",
+                                               "chunk_latency_p99_ms", "first_chunk_latency_p50_ms",
+                                               "first_chunk_latency_p99_ms")] + \
+               [("deadline_misses", ctypes.c_uint64), ("pool_free_bytes", ctypes.c_uint64)]
 
 
 class awg_retune(ctypes.Structure):
@@ -105,6 +138,14 @@ def lib():
         "awg_phase_dump": ([_VP, _I32, _U64, _U64, _VP, _VP], _I32),
         "awg_profile_enable": ([_VP, _I32], _I32),
         "awg_profile_read": ([_VP, ctypes.POINTER(awg_kernel_stat), _I32, ctypes.POINTER(_I32), _I32], _I32),
+        "awg_server_create": ([_VP, ctypes.POINTER(awg_server_params), ctypes.POINTER(_VP)], _I32),
+        "awg_server_destroy": ([_VP], _I32),
+        "awg_server_submit": ([_VP, ctypes.POINTER(awg_job), ctypes.POINTER(_U64)], _I32),
+        "awg_server_poll": ([_VP, ctypes.POINTER(awg_chunk_event), _I32, ctypes.POINTER(_I32)], _I32),
+        "awg_server_slot": ([_VP, _I32, ctypes.POINTER(_VP)], _I32),
+        "awg_server_read": ([_VP, _I32, _U64, _VP], _I32),
+        "awg_server_release": ([_VP, _I32], _I32),
+        "awg_server_stats_get": ([_VP, ctypes.POINTER(awg_server_stats)], _I32),
         "awg_strerror": ([_I32], ctypes.c_char_p),
         "awg_version": ([], _I32),
     }
@@ -231,6 +272,56 @@ def awg_profile_read(ctx, reset=False):
     _check(lib().awg_profile_read(ctx, arr, 64, ctypes.byref(n), 1 if reset else 0), "awg_profile_read")
     return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms, arr[i].max_ms)
             for i in range(min(n.value, 64))}
+
+
+def awg_server_create(ctx, mem_budget_bytes, max_jobs, ring_slots, chunk_len=1 << 20, max_pending=4096,
+                      playout_delay_ms=5.0):
+    p = awg_server_params(int(mem_budget_bytes), int(max_jobs), int(ring_slots), int(chunk_len),
+                          int(max_pending), float(playout_delay_ms))
+    h = _VP()
+    _check(lib().awg_server_create(ctx, ctypes.byref(p), ctypes.byref(h)), "awg_server_create")
+    return h.value
+
+
+def awg_server_destroy(srv):
+    if srv:
+        _check(lib().awg_server_destroy(srv), "awg_server_destroy")
+
+
+def awg_server_submit(srv, fs_hz, tones, n_samples, gain_lsb=0.0, period_log2=0, user_tag=0):
+    t = np.ascontiguousarray(tones, dtype=TONE_DTYPE)
+    j = awg_job(float(fs_hz), float(gain_lsb), int(period_log2), 0, t.ctypes.data, len(t), 0,
+                int(n_samples), int(user_tag))
+    jid = _U64()
+    _check(lib().awg_server_submit(srv, ctypes.byref(j), ctypes.byref(jid)), "awg_server_submit")
+    return jid.value
+
+
+def awg_server_poll(srv, max_events=256):
+    arr = (awg_chunk_event * max_events)()
+    n = _I32()
+    _check(lib().awg_server_poll(srv, arr, max_events, ctypes.byref(n)), "awg_server_poll")
+    return [{f: getattr(arr[i], f) for f, _ in awg_chunk_event._fields_} for i in range(n.value)]
+
+
+def awg_server_slot(srv, slot):
+    p = _VP()
+    _check(lib().awg_server_slot(srv, int(slot), ctypes.byref(p)), "awg_server_slot")
+    return p.value
+
+
+def awg_server_read(srv, slot, count, dst):
+    _check(lib().awg_server_read(srv, int(slot), int(count), dst), "awg_server_read")
+
+
+def awg_server_release(srv, slot):
+    _check(lib().awg_server_release(srv, int(slot)), "awg_server_release")
+
+
+def awg_server_stats_get(srv):
+    st = awg_server_stats()
+    _check(lib().awg_server_stats_get(srv, ctypes.byref(st)), "awg_server_stats_get")
+    return {f: getattr(st, f) for f, _ in awg_server_stats._fields_}
 
 
 # ------------------------------------------------------------ convenience

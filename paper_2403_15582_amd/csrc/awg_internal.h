@@ -49,6 +49,22 @@ struct ToneHost {
     double amp;          // A_k * G in FP64
 };
 
+// One chunk of one plan in a batched launch (64 bytes).
+struct BatchItem {
+    const ToneDev *tones;
+    const uint64_t *const *tables;
+    void *out;               // int16 output of this chunk
+    uint64_t n0, count;      // absolute first sample, samples in the chunk
+    uint32_t tile_begin;     // first tile of this item in the launch
+    int32_t n_tones, slice;
+    int32_t is_static;       // 1: no tone has a window
+    int32_t pad[2];
+};
+static_assert(sizeof(BatchItem) == 64, "BatchItem must be 64 bytes");
+
+// Samples per direct-kernel tile (4 waves x 64 lanes x 16 samples per lane).
+constexpr int kTileSamples = 1024;
+
 struct Table {
     int32_t shape;
     uint64_t n;
@@ -114,6 +130,9 @@ int64_t cosine_entry(uint64_t n, uint64_t d);
 uint64_t chirp_end_term(int32_t shape, int64_t coef, int64_t dF, uint64_t n);
 ToneDev to_device(const ToneHost &t, uint16_t table);
 
+// Device table H_N of a smooth shape, created once per context (capi.cpp).
+awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d_out);
+
 // Records HIP events around one kernel launch when the context profiles.
 class ProfScope {
 public:
@@ -135,6 +154,7 @@ hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint6
                              uint64_t *out, hipStream_t s);
 hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n,
                                 hipStream_t s);
+hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint32_t grid, hipStream_t s);
 // MFMA static synthesis; out_i16 or out_f32 (exactly one non-null).
 awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count,
                        int16_t *out_i16, float *out_f32, hipStream_t s);

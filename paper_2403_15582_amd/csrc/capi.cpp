@@ -67,28 +67,6 @@ void fill_table(int32_t shape, uint64_t n, uint64_t *out)
     for (auto &t : th) t.join();
 }
 
-// Device table of a smooth shape, shared through the context.
-awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d_out)
-{
-    std::lock_guard<std::mutex> g(ctx->mu);
-    auto key = std::make_pair(shape, n);
-    auto it = ctx->tables.find(key);
-    if (it != ctx->tables.end()) { *d_out = it->second.d_data; return AWG_OK; }
-    std::vector<uint64_t> h;
-    try { h.resize(n + 1); } catch (...) { return AWG_E_NOMEM; }
-    fill_table(shape, n, h.data());
-    Table t;
-    t.shape = shape;
-    t.n = n;
-    hipError_t e = hipMalloc((void **)&t.d_data, (n + 1) * sizeof(uint64_t));
-    if (e != hipSuccess) return hip_status(e);
-    e = hipMemcpy(t.d_data, h.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { (void)hipFree(t.d_data); return hip_status(e); }
-    ctx->tables[key] = t;
-    *d_out = t.d_data;
-    return AWG_OK;
-}
-
 // Words of one tone with one (optional) window, starting from the line (p, f).
 awg_status tone_words(const awg_plan_params &pp, uint64_t p_line, uint64_t f_line, int32_t shape,
                       uint64_t a, uint64_t n, double f_end, ToneHost *t)
@@ -164,6 +142,32 @@ awg_status device_ready(awg_plan *p)
 }
 
 }  // namespace
+
+namespace awg {
+
+// Device table of a smooth shape, shared through the context.
+awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d_out)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto key = std::make_pair(shape, n);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) { *d_out = it->second.d_data; return AWG_OK; }
+    std::vector<uint64_t> h;
+    try { h.resize(n + 1); } catch (...) { return AWG_E_NOMEM; }
+    fill_table(shape, n, h.data());
+    Table t;
+    t.shape = shape;
+    t.n = n;
+    hipError_t e = hipMalloc((void **)&t.d_data, (n + 1) * sizeof(uint64_t));
+    if (e != hipSuccess) return hip_status(e);
+    e = hipMemcpy(t.d_data, h.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(t.d_data); return hip_status(e); }
+    ctx->tables[key] = t;
+    *d_out = t.d_data;
+    return AWG_OK;
+}
+
+}  // namespace awg
 
 extern "C" {
 

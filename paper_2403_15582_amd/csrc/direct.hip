@@ -114,19 +114,20 @@ __device__ __forceinline__ int16_t quantise(float y)
     return (int16_t)(int32_t)r;
 }
 
-// STATIC: every tone of the plan is a static line (no windows), so the regime
-// logic is compiled out; the arithmetic per sample is the same as the static
-// regime of gen_phases, so both instantiations give identical sums.
+// One tile: the 64*S samples tile0 .. tile0 + 64*S - 1 of a tone list, summed
+// by the 4 waves of the workgroup and written to out[0 .. valid). STATIC: every
+// tone is a static line (no windows), so the regime logic is compiled out; the
+// arithmetic per sample is the same as the static regime of gen_phases, so both
+// instantiations give identical sums. Ends with a barrier so `part` can be
+// reused by the next tile of the same workgroup.
 template <int S, bool F32OUT, bool STATIC>
-__global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
-                                                     int32_t slice, const uint64_t *const *__restrict__ tables,
-                                                     uint64_t n0, uint64_t count, void *__restrict__ out)
+__device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, int32_t n_tones, int32_t slice,
+                                           const uint64_t *const *__restrict__ tables, uint64_t tile0,
+                                           uint32_t valid, void *__restrict__ out, float (*part)[kLanes * S])
 {
     constexpr int T = kLanes * S;                 // samples per tile
-    __shared__ float part[kWaves][T];
     const uint32_t lane = threadIdx.x & 63u;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t tile0 = n0 + (uint64_t)blockIdx.x * T;
 
     const int kb = wave * slice;
     const int ke = min(n_tones, kb + slice);
@@ -174,11 +175,55 @@ __global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = i0 + e;
         const float y = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
-        const uint64_t rel = (uint64_t)blockIdx.x * T + i;
-        if (rel < count) {
-            if (F32OUT) ((float *)out)[rel] = y;
-            else ((int16_t *)out)[rel] = quantise(y);
+        if (i < valid) {
+            if (F32OUT) ((float *)out)[i] = y;
+            else ((int16_t *)out)[i] = quantise(y);
         }
+    }
+    __syncthreads();
+}
+
+template <int S, bool F32OUT, bool STATIC>
+__global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
+                                                     int32_t slice, const uint64_t *const *__restrict__ tables,
+                                                     uint64_t n0, uint64_t count, void *__restrict__ out)
+{
+    constexpr int T = kLanes * S;
+    __shared__ float part[kWaves][T];
+    const uint64_t rel = (uint64_t)blockIdx.x * T;
+    const uint64_t left = count - rel;
+    const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
+    void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
+    synth_tile<S, F32OUT, STATIC>(tones, n_tones, slice, tables, n0 + rel, valid, o, part);
+}
+
+// Batched synthesis of many plans' chunks in one launch (continuous batching).
+// items[0 .. n_items) are sorted by tile_begin and cover tiles [0, total_tiles)
+// without gaps; a fixed grid walks the tiles with a stride of gridDim.x, so one
+// launch shape serves every batch (hipGraph replay). Each tile runs exactly the
+// same code as direct_kernel, so a plan's output does not depend on the batch.
+template <int S>
+__global__ __launch_bounds__(256) void batch_kernel(const BatchItem *__restrict__ items,
+                                                    const uint32_t *__restrict__ header)
+{
+    constexpr int T = kLanes * S;
+    __shared__ float part[kWaves][T];
+    const uint32_t n_items = header[0], total = header[1];
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        uint32_t lo = 0, hi = n_items;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (items[mid].tile_begin <= t) lo = mid; else hi = mid;
+        }
+        const BatchItem &it = items[lo];
+        const uint64_t rel = (uint64_t)(t - it.tile_begin) * T;
+        const uint64_t left = it.count - rel;
+        const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
+        int16_t *o = (int16_t *)it.out + rel;
+        if (it.is_static)
+            synth_tile<S, false, true>(it.tones, it.n_tones, it.slice, it.tables, it.n0 + rel, valid, o, part);
+        else
+            synth_tile<S, false, false>(it.tones, it.n_tones, it.slice, it.tables, it.n0 + rel, valid, o, part);
     }
 }
 
@@ -270,6 +315,12 @@ hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint6
         out += now;
     }
     return hipSuccess;
+}
+
+hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_kernel<kS>, dim3(grid), dim3(256), 0, s, d_items, d_header);
+    return hipGetLastError();
 }
 
 hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n, hipStream_t s)

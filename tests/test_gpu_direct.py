@@ -218,3 +218,43 @@ def test_retune_stream_matches_oracle():
                         [e[1] + d for e in events[::37] for d in (-1, 0, 1, 2, 140000, W.CONFIG4_RAMP_LEN)])
     qo, yo = csynth.synth_at(op, ns)
     compare(q[ns], None, qo, yo, "config4-small (sampled %d)" % len(ns))
+
+
+@pytest.mark.parametrize("K", [5000, 10000])
+def test_config4_full_second_streamed(K):
+    """Large array: 1 s at 280 MS/s (268 chunks), groups of 100 tones retuned in turn."""
+    torch = need_gpu()
+    w = W.config4(K=K)
+    lp = lib_plan(w)
+    op = oracle_plan(w, tables=False)
+    events = sorted(w.retunes, key=lambda e: e[1])
+    n_chunks = w.count // w.chunk
+    say("config4 K=%d: %d chunks, %d retunes" % (K, n_chunks, len(events)))
+    rng = np.random.default_rng(K)
+    picks = sorted(set([0, 1, 2, n_chunks // 2, n_chunks - 1]) | set(rng.integers(0, n_chunks, 4).tolist()))
+    kept = {}
+    i = 0
+    for c in range(n_chunks):
+        end = (c + 1) * w.chunk
+        batch = []
+        while i < len(events) and events[i][1] < end:
+            k, a, n, shape, f = events[i]
+            batch.append((k, shape, a, n, f))
+            op.add_ramp(k, a, n, shape, f)
+            i += 1
+        if batch:
+            lp.retune(batch)
+        n0, out = lp.stream_next(w.chunk)
+        if c in picks:
+            kept[c] = out
+    torch.cuda.synchronize()
+    pk = csynth.Packed(op)
+    for c in picks:
+        q = to_np(kept[c])
+        base = c * w.chunk
+        ns = np.unique(np.concatenate([rng.integers(0, w.chunk, 400), [0, 1, w.chunk - 1]]))
+        ramp_edges = [e[1] - base + d for e in events for d in (-1, 0, 1, W.CONFIG4_RAMP_LEN)
+                      if 0 <= e[1] - base + d < w.chunk]
+        ns = np.unique(np.concatenate([ns, np.array(ramp_edges[:200], dtype=np.int64)]))
+        qo, yo = csynth.synth_at(op, ns + base, packed=pk)
+        compare(q[ns], None, qo, yo, "config4 K=%d chunk %d (sampled %d)" % (K, c, len(ns)))

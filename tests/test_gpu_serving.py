@@ -1,0 +1,114 @@
+"""Batched serving: alone == in the mix (bit-identical), parity with the oracle,
+admission by memory, ring back-pressure, and many replays of the step graph."""
+import numpy as np
+import pytest
+
+import paper_2403_15582_amd as awg
+from paper_2403_15582_amd import workloads as W
+from paper_2403_15582_amd.serving import Server
+from oracle import words, csynth
+
+from gpu_common import need_gpu, say, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _jobs(n, seed=5, dmax_ms=6.0):
+    return W.config5(seed=seed, max_jobs=n, dmax_ms=dmax_ms, kmax=800)
+
+
+def _solo(torch, job):
+    """The same job through the plain Playback call (no server, no batching)."""
+    p = awg.Plan(job.tones, job.fs_hz, 0.0, 0)
+    q = p.synth_chirp(0, job.n_samples)
+    torch.cuda.synchronize()
+    return q.cpu().numpy()
+
+
+def test_mix_equals_alone_and_oracle():
+    torch = need_gpu()
+    jobs = _jobs(40)
+    say("serving mix of %d jobs, %d chunks" % (len(jobs), sum((j.n_samples + (1 << 20) - 1) >> 20 for j in jobs)))
+    keep = [0, 1, 7, 19, 39]
+    with Server(max_jobs=16, ring_slots=24) as srv:
+        mixed = srv.run_trace(jobs, collect=keep, time_scale=0.05)
+        st = srv.stats()
+    say("stats: steps=%d mean_batch=%.1f max_batch=%d p99 chunk latency %.2f ms"
+        % (st["steps"], st["mean_batch"], st["max_batch"], st["chunk_latency_p99_ms"]))
+    assert st["jobs_done"] == len(jobs) and st["max_batch"] > 1
+    for k in keep:
+        solo = _solo(torch, jobs[k])
+        assert np.array_equal(mixed[k], solo), k
+    # the same job through a server on its own
+    with Server(max_jobs=4, ring_slots=4) as srv:
+        alone = srv.run_trace([jobs[7]], collect=[0])[0]
+    assert np.array_equal(alone, mixed[7])
+    for k in (0, 19):
+        j = jobs[k]
+        op = words.Plan(j.fs_hz, 0.0, 0, j.tones)
+        ns = np.unique(np.concatenate([np.arange(0, min(j.n_samples, 300)),
+                                       np.random.default_rng(k).integers(0, j.n_samples, 1500),
+                                       np.arange(max(0, j.n_samples - 300), j.n_samples)]))
+        qo, yo = csynth.synth_at(op, ns)
+        compare(mixed[k][ns], None, qo, yo, "served job %d (K=%d, %d samples)" % (k, len(j.tones), j.n_samples))
+
+
+def test_admission_by_memory_and_backpressure():
+    torch = need_gpu()
+    jobs = _jobs(12, seed=9)
+    biggest = max(len(j.tones) for j in jobs)
+    ring = 2 * (1 << 20) * 2
+    # room for the ring plus the tone table of about one large job at a time
+    budget = ring + (biggest * 64 + 4096)
+    with Server(mem_budget_bytes=budget, max_jobs=8, ring_slots=2) as srv:
+        out = srv.run_trace(jobs, collect=range(len(jobs)), time_scale=0.0)
+        st = srv.stats()
+    say("tiny budget: admitted %d, done %d, max batch %d" % (st["jobs_admitted"], st["jobs_done"], st["max_batch"]))
+    assert st["jobs_done"] == len(jobs)
+    for k in (0, 5, 11):
+        assert np.array_equal(out[k], _solo(torch, jobs[k]))
+    # a job whose tables can never fit is refused, a full queue says busy
+    with Server(mem_budget_bytes=ring + 4096, max_jobs=2, ring_slots=2, max_pending=1) as srv:
+        with pytest.raises(awg.AwgError) as e:
+            awg.awg_server_submit(srv.handle, jobs[0].fs_hz, np.concatenate([jobs[0].tones] * 200),
+                                  1000)
+        assert e.value.status == awg.AWG_E_NOMEM
+        small = jobs[0].tones[:4]
+        codes = []
+        for _ in range(200):
+            try:
+                awg.awg_server_submit(srv.handle, jobs[0].fs_hz, small, 1 << 22)
+                codes.append(0)
+            except awg.AwgError as err:
+                codes.append(err.status)
+        assert awg.AWG_E_BUSY in codes
+        # drain everything that was accepted
+        accepted = codes.count(0)
+        done = 0
+        import time
+        t0 = time.time()
+        while done < accepted and time.time() - t0 < 60:
+            for ev in awg.awg_server_poll(srv.handle):
+                awg.awg_server_release(srv.handle, ev["slot"])
+                done += ev["last"]
+        assert done == accepted
+
+
+def test_invalid_server_arguments():
+    need_gpu()
+    with pytest.raises(awg.AwgError) as e:
+        awg.awg_server_create(awg.context(0), 1 << 20, 4, 4, chunk_len=1000)
+    assert e.value.status == awg.AWG_E_INVALID
+    with pytest.raises(awg.AwgError) as e:
+        awg.awg_server_create(awg.context(0), 1 << 20, 4, 64)
+    assert e.value.status == awg.AWG_E_RANGE
+    with Server(max_jobs=2, ring_slots=2) as srv:
+        with pytest.raises(awg.AwgError) as e:
+            awg.awg_server_release(srv.handle, 0)          # not held by the consumer
+        assert e.value.status == awg.AWG_E_INVALID
+        t = awg.make_tones(1)
+        t["f_start_hz"] = 1e6
+        t["amplitude"] = 1.0
+        with pytest.raises(awg.AwgError) as e:
+            awg.awg_server_submit(srv.handle, 280e6, t, 0)
+        assert e.value.status == awg.AWG_E_INVALID
