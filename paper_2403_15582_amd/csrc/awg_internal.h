@@ -58,7 +58,7 @@ struct BatchItem {
     uint32_t tile_begin;     // first tile of this item in the launch
     int32_t n_tones, slice;
     int32_t is_static;       // 1: no tone has a window
-    int32_t pad[2];
+    const uint8_t *uniform;  // per (slice, block of 32 tones): 1 if the block shares one window and shape
 };
 static_assert(sizeof(BatchItem) == 64, "BatchItem must be 64 bytes");
 
@@ -69,6 +69,7 @@ struct Table {
     int32_t shape;
     uint64_t n;
     uint64_t *d_data;    // device, n + 1 entries
+    bool monotone;       // never decreasing with steps below 2^31 (pointers handed out carry it in bit 0)
 };
 
 }  // namespace awg
@@ -98,10 +99,15 @@ struct awg_plan {
     double gain;
     int32_t n_tones;
     int32_t n_ramped;
-    std::vector<awg::ToneHost> host;   // authoritative tone state
-    std::vector<awg::ToneDev> dev_mirror;
+    std::vector<awg::ToneHost> host;   // authoritative tone state, caller's tone order
+    std::vector<awg::ToneDev> dev_mirror;   // device order: sorted by (shape, window, table)
+    std::vector<int32_t> perm;         // device position -> caller's tone index
+    std::vector<int32_t> inv;          // caller's tone index -> device position
     std::vector<const uint64_t *> table_ptrs;   // device pointers, indexed by ToneDev::table
     std::map<std::pair<int32_t, uint64_t>, uint16_t> table_index;
+    int32_t slice;                     // tones per wave slice: ceil(n_tones / 4)
+    std::vector<uint8_t> uniform;      // block flags, see BatchItem::uniform
+    uint8_t *d_uniform;
     awg::ToneDev *d_tones;             // device copy of dev_mirror
     const uint64_t **d_table_ptrs;     // device copy of table_ptrs
     size_t d_table_ptrs_cap;
@@ -129,6 +135,8 @@ int64_t minjerk_entry(uint64_t n, uint64_t d);
 int64_t cosine_entry(uint64_t n, uint64_t d);
 uint64_t chirp_end_term(int32_t shape, int64_t coef, int64_t dF, uint64_t n);
 ToneDev to_device(const ToneHost &t, uint16_t table);
+// Block flags of a tone list for the direct kernel's slice/block layout.
+void block_flags(const std::vector<ToneDev> &tones, int32_t slice, std::vector<uint8_t> *out);
 
 // Device table H_N of a smooth shape, created once per context (capi.cpp).
 awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d_out);

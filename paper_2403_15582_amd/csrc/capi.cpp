@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <thread>
@@ -117,6 +118,7 @@ awg_status table_slot(awg_plan *p, int32_t shape, uint64_t n, uint16_t *idx, boo
 void free_plan_device(awg_plan *p)
 {
     if (p->d_tones) (void)hipFree(p->d_tones);
+    if (p->d_uniform) (void)hipFree(p->d_uniform);
     if (p->d_table_ptrs) (void)hipFree(p->d_table_ptrs);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     if (p->d_work) (void)hipFree(p->d_work);
@@ -151,19 +153,26 @@ awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d
     std::lock_guard<std::mutex> g(ctx->mu);
     auto key = std::make_pair(shape, n);
     auto it = ctx->tables.find(key);
-    if (it != ctx->tables.end()) { *d_out = it->second.d_data; return AWG_OK; }
+    if (it != ctx->tables.end()) {
+        *d_out = (const uint64_t *)((uintptr_t)it->second.d_data | (it->second.monotone ? 1u : 0u));
+        return AWG_OK;
+    }
     std::vector<uint64_t> h;
     try { h.resize(n + 1); } catch (...) { return AWG_E_NOMEM; }
     fill_table(shape, n, h.data());
     Table t;
     t.shape = shape;
     t.n = n;
+    // tag for the kernels: never decreasing, steps below 2^31
+    t.monotone = true;
+    for (uint64_t d = 0; d < n && t.monotone; ++d)
+        t.monotone = h[d + 1] >= h[d] && h[d + 1] - h[d] < (1ull << 31);
     hipError_t e = hipMalloc((void **)&t.d_data, (n + 1) * sizeof(uint64_t));
     if (e != hipSuccess) return hip_status(e);
     e = hipMemcpy(t.d_data, h.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(t.d_data); return hip_status(e); }
     ctx->tables[key] = t;
-    *d_out = t.d_data;
+    *d_out = (const uint64_t *)((uintptr_t)t.d_data | (t.monotone ? 1u : 0u));
     return AWG_OK;
 }
 
@@ -270,9 +279,15 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
     p->d_work = nullptr;
     p->d_work_bytes = 0;
     p->mfma_b_key = 0;
+    p->slice = (n_tones + kWaves - 1) / kWaves;
+    p->d_uniform = nullptr;
+    std::vector<uint16_t> tidx;
     try {
         p->host.resize(n_tones);
         p->dev_mirror.resize(n_tones);
+        p->perm.resize(n_tones);
+        p->inv.resize(n_tones);
+        tidx.resize(n_tones);
     } catch (...) { delete p; return AWG_E_NOMEM; }
 
     awg_status st = AWG_OK;
@@ -294,11 +309,32 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
             if (st != AWG_OK) break;
         }
         if (t.ramp != AWG_RAMP_NONE) p->n_ramped++;
-        p->dev_mirror[k] = to_device(h, idx);
+        tidx[k] = idx;
         if (f_quantised_hz) f_quantised_hz[k] = (double)f0 * pp.fs_hz * 0x1p-64;
+    }
+    if (st == AWG_OK) {
+        // device order: tones that share shape and window next to each other, so
+        // the kernel's blocks of 32 mostly take one regime per tile (stable: the
+        // caller's order within a group, identity for all-static plans)
+        for (int32_t k = 0; k < n_tones; ++k) p->perm[k] = k;
+        std::stable_sort(p->perm.begin(), p->perm.end(), [&](int32_t x, int32_t y) {
+            const ToneHost &a = p->host[x], &b = p->host[y];
+            if (a.shape != b.shape) return a.shape < b.shape;
+            if (a.a != b.a) return a.a < b.a;
+            if (a.n != b.n) return a.n < b.n;
+            return tidx[x] < tidx[y];
+        });
+        for (int32_t i = 0; i < n_tones; ++i) {
+            p->inv[p->perm[i]] = i;
+            p->dev_mirror[i] = to_device(p->host[p->perm[i]], tidx[p->perm[i]]);
+        }
+        block_flags(p->dev_mirror, p->slice, &p->uniform);
     }
     if (st == AWG_OK && ctx) {
         hipError_t e = hipMalloc((void **)&p->d_tones, sizeof(ToneDev) * (size_t)n_tones);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_uniform, p->uniform.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_uniform, p->uniform.data(), p->uniform.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_tones, p->dev_mirror.data(), sizeof(ToneDev) * (size_t)n_tones,
                           hipMemcpyHostToDevice);
@@ -311,7 +347,7 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
                           hipMemcpyHostToDevice);
         }
         if (e != hipSuccess) st = hip_status(e);
-        p->device_bytes = sizeof(ToneDev) * (size_t)n_tones + sizeof(uint64_t *) * kTablePtrCap;
+        p->device_bytes = sizeof(ToneDev) * (size_t)n_tones + sizeof(uint64_t *) * kTablePtrCap + p->uniform.size();
     }
     if (st != AWG_OK) {
         free_plan_device(p);
@@ -406,8 +442,9 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
         const int32_t k = ev[i].tone;
         if (p->host[k].shape == AWG_RAMP_NONE) p->n_ramped++;
         p->host[k] = next[i];
-        p->dev_mirror[k] = to_device(next[i], tidx[i]);
+        p->dev_mirror[p->inv[k]] = to_device(next[i], tidx[i]);
     }
+    block_flags(p->dev_mirror, p->slice, &p->uniform);
     if (!p->ctx) return AWG_OK;
     // stage the new records and scatter them on the stream
     hipError_t e = hipSetDevice(p->ctx->device);
@@ -418,7 +455,8 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
             s.host = nullptr; s.done = nullptr; s.used = false;
         }
         for (auto &s : p->slots) {
-            e = hipHostMalloc(&s.host, sizeof(ScatterRecord) * kSlotRecords, hipHostMallocDefault);
+            e = hipHostMalloc(&s.host, sizeof(ScatterRecord) * kSlotRecords + p->uniform.size(),
+                              hipHostMallocDefault);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
             if (e != hipSuccess) return hip_status(e);
         }
@@ -435,14 +473,19 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
     }
     ScatterRecord *rec = (ScatterRecord *)slot.host;
     for (int32_t i = 0; i < n_ev; ++i) {
-        rec[i].index = (uint32_t)ev[i].tone;
+        rec[i].index = (uint32_t)p->inv[ev[i].tone];
         rec[i].pad = 0;
-        rec[i].tone = p->dev_mirror[ev[i].tone];
+        rec[i].tone = p->dev_mirror[p->inv[ev[i].tone]];
     }
     hipStream_t s = (hipStream_t)hip_stream;
     void *d_rec = (char *)p->d_scratch + si * sizeof(ScatterRecord) * kSlotRecords;
     e = hipMemcpyAsync(d_rec, rec, sizeof(ScatterRecord) * (size_t)n_ev, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_scatter_tones(p->d_tones, d_rec, n_ev, s);
+    // the block flags follow the records in the same pinned slot
+    uint8_t *flags = (uint8_t *)slot.host + sizeof(ScatterRecord) * kSlotRecords;
+    std::memcpy(flags, p->uniform.data(), p->uniform.size());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_uniform, flags, p->uniform.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     slot.used = true;
     return hip_status(e);
@@ -527,7 +570,7 @@ awg_status awg_phase_dump(awg_plan *p, int32_t tone, uint64_t n0, uint64_t count
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
     if (!d_words) return AWG_E_INVALID;
-    return hip_status(launch_phase_dump(p, tone, n0, count, d_words, (hipStream_t)hip_stream));
+    return hip_status(launch_phase_dump(p, p->inv[tone], n0, count, d_words, (hipStream_t)hip_stream));
 }
 
 }  // extern "C"

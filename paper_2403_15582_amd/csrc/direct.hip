@@ -40,6 +40,18 @@ __device__ __forceinline__ uint64_t smooth_term(int64_t dF, uint64_t H)
     return t1 + ((uint64_t)hi << 16) + (lo >> 16);
 }
 
+// Table pointers carry a tag in bit 0: set when the table never decreases and
+// its steps fit 31 bits, which the incremental smooth path relies on.
+__device__ __forceinline__ const uint64_t *table_of(const uint64_t *const *tables, uint32_t i)
+{
+    return (const uint64_t *)((uintptr_t)tables[i] & ~(uintptr_t)1);
+}
+
+__device__ __forceinline__ bool table_monotone(const uint64_t *const *tables, uint32_t i)
+{
+    return ((uintptr_t)tables[i] & 1) != 0;
+}
+
 __device__ __forceinline__ uint64_t phase_general(const ToneDev &t, const uint64_t *const *tables,
                                                   uint64_t n)
 {
@@ -48,7 +60,7 @@ __device__ __forceinline__ uint64_t phase_general(const ToneDev &t, const uint64
     if (d <= t.n) {
         const uint64_t base = t.p0 + t.f0 * n;
         if (t.shape == AWG_RAMP_LINEAR) return base + lin_term(t.coef, d);
-        return base + smooth_term(t.coef, tables[t.table][d]);
+        return base + smooth_term(t.coef, table_of(tables, t.table)[d]);
     }
     return t.p1 + t.f1 * n;
 }
@@ -93,7 +105,7 @@ __device__ __forceinline__ void gen_phases(const ToneDev &t, const uint64_t *con
                 inc += (s & 1) ? Dq : Dp;
             }
         } else {
-            const uint64_t *H = tables[t.table] + dt + j;
+            const uint64_t *H = table_of(tables, t.table) + dt + j;
             uint64_t ph = t.p0 + t.f0 * tile0 + t.f0 * (uint64_t)j;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -104,6 +116,36 @@ __device__ __forceinline__ void gen_phases(const ToneDev &t, const uint64_t *con
     } else {                                                        // straddles an edge
 #pragma unroll
         for (int s = 0; s < S; ++s) f(s, phase_general(t, tables, tile0 + j + s));
+    }
+}
+
+// Regime loops for a block of tones that share one window and shape (one
+// regime per tile for the whole block); same arithmetic as gen_phases.
+template <int S, typename F>
+__device__ __forceinline__ void static_run(uint64_t P, uint64_t Fw, uint64_t tile0, uint32_t j, F &&f)
+{
+    uint64_t ph = P + Fw * tile0 + Fw * (uint64_t)j;
+#pragma unroll
+    for (int s = 0; s < S; ++s) { f(s, ph); ph += Fw; }
+}
+
+template <int S, typename F>
+__device__ __forceinline__ void linear_run(const ToneDev &t, uint64_t tile0, uint64_t dt, uint32_t j, F &&f)
+{
+    const int64_t R = t.coef;
+    const uint64_t h = (uint64_t)(R >> 1), r = (uint64_t)(R & 1);
+    const uint64_t W = t.p0 + t.f0 * tile0 + lin_term(R, dt);
+    const uint64_t V = t.f0 + (uint64_t)R * dt;
+    const uint64_t I = V + h + ((dt & 1) ? r : 0ull);
+    const uint64_t Dp = (uint64_t)R + ((dt & 1) ? (0ull - r) : r);
+    const uint64_t Dq = (uint64_t)R + ((dt & 1) ? r : (0ull - r));
+    uint64_t ph = W + V * (uint64_t)j + (uint64_t)R * (uint64_t)(j * j / 2);
+    uint64_t inc = I + (uint64_t)R * (uint64_t)j;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        f(s, ph);
+        ph += inc;
+        inc += (s & 1) ? Dq : Dp;
     }
 }
 
@@ -122,7 +164,8 @@ __device__ __forceinline__ int16_t quantise(float y)
 // reused by the next tile of the same workgroup.
 template <int S, bool F32OUT, bool STATIC>
 __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, int32_t n_tones, int32_t slice,
-                                           const uint64_t *const *__restrict__ tables, uint64_t tile0,
+                                           const uint64_t *const *__restrict__ tables,
+                                           const uint8_t *__restrict__ uniform, uint64_t tile0,
                                            uint32_t valid, void *__restrict__ out, float (*part)[kLanes * S])
 {
     constexpr int T = kLanes * S;                 // samples per tile
@@ -135,12 +178,81 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, in
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0f;
 
-    for (int k0 = kb; k0 < ke; k0 += kBlock) {
+    const int nbps = (slice + kBlock - 1) / kBlock;      // blocks per slice
+    const uint64_t tile_last = tile0 + (uint64_t)(T - 1);
+    const uint32_t j = lane * S;
+    for (int k0 = kb, bi = wave * nbps; k0 < ke; k0 += kBlock, ++bi) {
         const int k1 = min(ke, k0 + kBlock);
         float blk[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) blk[s] = 0.0f;
-        if (STATIC) {
+        if (!STATIC && uniform[bi]) {
+            // every tone of the block has the window and shape of tones[k0]
+            const ToneDev r = tones[k0];
+            const bool pre = tile_last < r.a, post = tile0 > r.a + r.n;
+            if (pre || post) {
+                for (int k = k0; k < k1; ++k) {
+                    const uint64_t P = pre ? tones[k].p0 : tones[k].p1, Fw = pre ? tones[k].f0 : tones[k].f1;
+                    const float amp = tones[k].amp;
+                    static_run<S>(P, Fw, tile0, j, [&](int s, uint64_t ph) {
+                        blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+                    });
+                }
+            } else if (tile0 >= r.a && tile_last <= r.a + r.n) {
+                const uint64_t dt = tile0 - r.a;
+                if (r.shape == AWG_RAMP_LINEAR) {
+                    for (int k = k0; k < k1; ++k) {
+                        const ToneDev t = tones[k];
+                        const float amp = t.amp;
+                        linear_run<S>(t, tile0, dt, j, [&](int s, uint64_t ph) {
+                            blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+                        });
+                    }
+                } else {
+                    // the table values of this lane's samples serve every tone of the block
+                    const uint64_t *H = table_of(tables, r.table) + dt + j;
+                    const bool mono = table_monotone(tables, r.table);
+                    uint64_t hv[S];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) hv[s] = H[s];
+                    // successive table differences (non-negative, below 2^31 when tagged)
+                    uint32_t dh[S];
+#pragma unroll
+                    for (int s = 0; s + 1 < S; ++s) dh[s] = (uint32_t)(hv[s + 1] - hv[s]);
+                    for (int k = k0; k < k1; ++k) {
+                        const uint64_t p0 = tones[k].p0, f0 = tones[k].f0;
+                        const int64_t dF = tones[k].coef;
+                        const float amp = tones[k].amp;
+                        uint64_t ph = p0 + f0 * tile0 + f0 * (uint64_t)j;
+                        if (mono && (dF & 0xffff) == 0) {
+                            // dF a multiple of 2^16 (always for bin frequencies): the chirp
+                            // term is exactly m*H with m = dF/2^16, and moves by m*dh per sample
+                            const uint64_t m = (uint64_t)(dF >> 16);
+                            ph += m * hv[0];
+#pragma unroll
+                            for (int s = 0; s < S; ++s) {
+                                blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+                                if (s + 1 < S) ph += f0 + m * (uint64_t)dh[s];
+                            }
+                        } else {
+#pragma unroll
+                            for (int s = 0; s < S; ++s) {
+                                blk[s] = __builtin_fmaf(amp, word_sin(ph + smooth_term(dF, hv[s])), blk[s]);
+                                ph += f0;
+                            }
+                        }
+                    }
+                }
+            } else {
+                for (int k = k0; k < k1; ++k) {
+                    const ToneDev t = tones[k];
+                    const float amp = t.amp;
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        blk[s] = __builtin_fmaf(amp, word_sin(phase_general(t, tables, tile0 + j + s)), blk[s]);
+                }
+            }
+        } else if (STATIC) {
 #pragma unroll 2
             for (int k = k0; k < k1; ++k) {
                 const uint64_t P = tones[k].p0, Fw = tones[k].f0;
@@ -186,7 +298,8 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, in
 template <int S, bool F32OUT, bool STATIC>
 __global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
                                                      int32_t slice, const uint64_t *const *__restrict__ tables,
-                                                     uint64_t n0, uint64_t count, void *__restrict__ out)
+                                                     const uint8_t *__restrict__ uniform, uint64_t n0,
+                                                     uint64_t count, void *__restrict__ out)
 {
     constexpr int T = kLanes * S;
     __shared__ float part[kWaves][T];
@@ -194,7 +307,7 @@ __global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__
     const uint64_t left = count - rel;
     const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
     void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
-    synth_tile<S, F32OUT, STATIC>(tones, n_tones, slice, tables, n0 + rel, valid, o, part);
+    synth_tile<S, F32OUT, STATIC>(tones, n_tones, slice, tables, uniform, n0 + rel, valid, o, part);
 }
 
 // Batched synthesis of many plans' chunks in one launch (continuous batching).
@@ -221,9 +334,11 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem *__restrict_
         const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
         int16_t *o = (int16_t *)it.out + rel;
         if (it.is_static)
-            synth_tile<S, false, true>(it.tones, it.n_tones, it.slice, it.tables, it.n0 + rel, valid, o, part);
+            synth_tile<S, false, true>(it.tones, it.n_tones, it.slice, it.tables, it.uniform, it.n0 + rel, valid,
+                                       o, part);
         else
-            synth_tile<S, false, false>(it.tones, it.n_tones, it.slice, it.tables, it.n0 + rel, valid, o, part);
+            synth_tile<S, false, false>(it.tones, it.n_tones, it.slice, it.tables, it.uniform, it.n0 + rel, valid,
+                                        o, part);
     }
 }
 
@@ -254,7 +369,7 @@ __global__ void scatter_tones_kernel(ToneDev *__restrict__ tones, const ScatterR
 constexpr int kS = 16;                             // samples per lane
 constexpr uint64_t kMaxTilesPerLaunch = 1u << 30;
 
-static int slice_of(int32_t n_tones) { return (n_tones + kWaves - 1) / kWaves; }
+static_assert(kLanes * kS == kTileSamples, "tile size");
 
 template <bool F32OUT>
 static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, void *out, hipStream_t s)
@@ -270,10 +385,10 @@ static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, 
             ProfScope prof(p->ctx, s, F32OUT ? "direct_kernel_f32" : "direct_kernel");
             if (p->n_ramped == 0)
                 hipLaunchKernelGGL((direct_kernel<kS, F32OUT, true>), dim3((uint32_t)now_tiles), dim3(256), 0, s,
-                                   p->d_tones, p->n_tones, slice_of(p->n_tones), p->d_table_ptrs, n0, now, out);
+                                   p->d_tones, p->n_tones, p->slice, p->d_table_ptrs, p->d_uniform, n0, now, out);
             else
                 hipLaunchKernelGGL((direct_kernel<kS, F32OUT, false>), dim3((uint32_t)now_tiles), dim3(256), 0,
-                                   s, p->d_tones, p->n_tones, slice_of(p->n_tones), p->d_table_ptrs, n0, now, out);
+                                   s, p->d_tones, p->n_tones, p->slice, p->d_table_ptrs, p->d_uniform, n0, now, out);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return e;

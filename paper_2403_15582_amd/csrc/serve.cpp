@@ -61,6 +61,7 @@ struct Job {
     size_t off, bytes;           // arena block
     ToneDev *d_tones;
     const uint64_t **d_tabs;
+    uint8_t *d_uniform;
     int32_t n_tones, slice, is_static;
     uint64_t n_samples, next_n0;
     uint32_t chunks_total, chunks_done;
@@ -162,7 +163,8 @@ void pool_free(awg_server *s, size_t off, size_t bytes)
 
 size_t job_bytes(const awg_plan *p)
 {
-    return align_up(sizeof(ToneDev) * (size_t)p->n_tones) + align_up(sizeof(uint64_t *) * (p->table_ptrs.size() + 1));
+    return align_up(sizeof(ToneDev) * (size_t)p->n_tones) + align_up(sizeof(uint64_t *) * (p->table_ptrs.size() + 1)) +
+           align_up(p->uniform.size());
 }
 
 // Admit queued jobs in order while a job slot and arena space are available.
@@ -179,8 +181,9 @@ void admit(awg_server *s)
         char *base = s->d_arena + s->pool_off + off;
         j.d_tones = (ToneDev *)base;
         j.d_tabs = (const uint64_t **)(base + align_up(sizeof(ToneDev) * (size_t)pd.plan->n_tones));
+        j.d_uniform = (uint8_t *)((char *)j.d_tabs + align_up(sizeof(uint64_t *) * (pd.plan->table_ptrs.size() + 1)));
         j.n_tones = pd.plan->n_tones;
-        j.slice = (j.n_tones + kWaves - 1) / kWaves;
+        j.slice = pd.plan->slice;
         j.is_static = pd.plan->n_ramped == 0;
         j.n_samples = pd.n_samples;
         j.next_n0 = 0;
@@ -196,6 +199,9 @@ void admit(awg_server *s)
         if (e == hipSuccess && nt > 0)
             e = hipMemcpyAsync(j.d_tabs, pd.plan->table_ptrs.data(), sizeof(uint64_t *) * nt,
                                hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(j.d_uniform, pd.plan->uniform.data(), pd.plan->uniform.size(), hipMemcpyHostToDevice,
+                               s->stream);
         if (e != hipSuccess) { s->error = hipst(e); pool_free(s, off, bytes); break; }
         s->jobs[j.id] = j;
         s->pending.pop_front();
@@ -280,6 +286,7 @@ bool launch_step(awg_server *s)
         b.n_tones = j.n_tones;
         b.slice = j.slice;
         b.is_static = j.is_static;
+        b.uniform = j.d_uniform;
         tiles += (uint32_t)((count + kTileSamples - 1) / kTileSamples);
         st->items.push_back(StepItem{j.id, slot, j.next_n0, count, (uint32_t)(j.next_n0 / s->prm.chunk_len)});
         s->slot_state[slot] = 1;

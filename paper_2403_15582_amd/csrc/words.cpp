@@ -3,6 +3,7 @@
 // rounding is half-to-even on an exactly computed rational.
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 
 #include "awg_internal.h"
@@ -201,6 +202,28 @@ ToneDev to_device(const ToneHost &t, uint16_t table)
     d.shape = (uint16_t)t.shape;
     d.table = table;
     return d;
+}
+
+// For wave w and block i of its slice (tones w*slice + 32i .. +31, clipped to
+// the slice and the list): 1 when all those tones have the same shape, window
+// and table, so the kernel can take the block's regime from its first tone.
+void block_flags(const std::vector<ToneDev> &tones, int32_t slice, std::vector<uint8_t> *out)
+{
+    const int32_t n = (int32_t)tones.size();
+    const int32_t nbps = (slice + kBlock - 1) / kBlock;
+    out->assign((size_t)kWaves * nbps, 0);
+    for (int32_t w = 0; w < kWaves; ++w) {
+        const int32_t kb = w * slice, ke = std::min(n, kb + slice);
+        for (int32_t i = 0; i < nbps; ++i) {
+            const int32_t b = kb + i * kBlock, e = std::min(ke, b + kBlock);
+            bool same = b < e;
+            for (int32_t k = b + 1; k < e && same; ++k) {
+                const ToneDev &x = tones[b], &y = tones[k];
+                same = x.shape == y.shape && x.a == y.a && x.n == y.n && x.table == y.table;
+            }
+            (*out)[(size_t)w * nbps + i] = same ? 1 : 0;
+        }
+    }
 }
 
 }  // namespace awg
