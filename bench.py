@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming, serving and large-array legs")
+    ap.add_argument("--legs", default="stream,arrays,serve",
+                    help="comma list of extra legs to run: stream, arrays, serve")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (calibrates the "
@@ -313,11 +315,14 @@ def main():
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(w, q_gpu, a.cpu_seconds)
-    if not a.no_stream:
+    legs = set() if a.no_stream else set(x for x in a.legs.split(",") if x)
+    if "stream" in legs:
         log("streaming leg ...")
         res["streaming"] = streaming_leg(torch, awg, W)
+    if "arrays" in legs:
         log("large-array legs ...")
         res["large_arrays"] = [large_array_leg(torch, awg, W, K) for K in (5000, 10000)]
+    if "serve" in legs:
         log("serving leg ...")
         res["serving"] = serving_leg(W, a.serve_seconds)
     print(json.dumps(res), flush=True)

@@ -1,0 +1,167 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that a pin fails.
+
+Each case patches one piece of oracle/words.py (a dropped term, a wrong sign or
+index, a swapped operand, a wrong rounding) or compiles a mutated copy of
+oracle/synth.c, then runs the pin tests that should notice and asserts that at
+least one of them fails. Nothing here touches the library or a GPU.
+"""
+import subprocess
+from fractions import Fraction
+
+import pytest
+
+import test_oracle_pins as pins
+from oracle import words, csynth
+
+WORD_PINS = [pins.test_eq4_bin_error_matches_paper, pins.test_tuning_word_closed_forms,
+             pins.test_phase_word_closed_forms]
+CHIRP_PINS = [pins.test_linear_chirp_matches_continuous_phase, pins.test_minjerk_matches_eq8_as_printed,
+              pins.test_minjerk_end_phase_golden, pins.test_cosine_ramp_matches_continuous_phase,
+              pins.test_all_shapes_share_end_phase, pins.test_retune_chain_is_continuous]
+SUM_PINS = [pins.test_quarter_rate_tone_is_exact, pins.test_eighth_rate_tone,
+            pins.test_static_tones_match_eq2_in_long_double, pins.test_dirichlet_kernel,
+            pins.test_periodicity_with_bin_frequencies, pins.test_mean_power_and_default_gain,
+            pins.test_held_tone_is_periodic_after_ramp, pins.test_brute_force_long_double,
+            pins.test_c_sum_equals_python_bigint]
+
+
+def some_pin_fails(tests):
+    for t in tests:
+        try:
+            if "case" in t.__code__.co_varnames[:t.__code__.co_argcount]:
+                for c in range(6):
+                    t(True, c)
+            elif t.__code__.co_argcount == 1:
+                t(True)
+            elif t.__code__.co_argcount == 0:
+                t()
+            else:
+                t(words.RAMP_COSINE)
+                t(words.RAMP_MINJERK)
+        except Exception:
+            return True
+    return False
+
+
+def test_unmutated_oracle_passes_every_pin_used_here(oracle_built):
+    """Control: the harness itself reports no failure on the real oracle."""
+    assert not some_pin_fails(WORD_PINS)
+    assert not some_pin_fails(CHIRP_PINS)
+    assert not some_pin_fails(SUM_PINS)
+
+
+def _floor_round(x):
+    x = Fraction(x)
+    return x.numerator // x.denominator
+
+
+def _tuning_word_truncating(f_hz, fs_hz, period_log2=0):
+    f, fs = Fraction(f_hz), Fraction(fs_hz)
+    if period_log2 > 0:
+        return _floor_round(f * (1 << period_log2) / fs) << (64 - period_log2)
+    return _floor_round(f * words.TWO64 / fs)
+
+
+WORD_MUTANTS = {
+    "bin snapping truncates instead of rounding": ("tuning_word", _tuning_word_truncating),
+    "phase word has the wrong sign": ("phase_word", lambda t: (-words.rne(Fraction(t) * words.TWO64)) & words.MASK64),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WORD_MUTANTS))
+def test_word_mutants_are_caught(monkeypatch, oracle_built, name):
+    attr, fn = WORD_MUTANTS[name]
+    monkeypatch.setattr(words, attr, fn)
+    assert some_pin_fails(WORD_PINS + SUM_PINS), name
+
+
+def _minjerk_wrong_coefficient(N, d):
+    num = (d ** 4) * (5 * N * N - 5 * d * N + 2 * d * d) << 15      # 6 -> 5
+    return words.rne(Fraction(num, N ** 5))
+
+
+def _cosine_missing_pi(N, d):
+    import math
+    s = math.sin((math.pi * float(d)) / float(N))
+    x = ((32768.0 * float(N)) / 1.0) * s                            # dropped 1/pi
+    return (d << 15) - words.rne(Fraction(x))
+
+
+def _linear_term_no_half(self, d):
+    if self.shape == words.RAMP_LINEAR:
+        return self.coef * d * d                                    # dropped the /2
+    return (self.coef * self.table_at(d)) >> words.TABLE_SHIFT
+
+
+def _linear_term_plus_sign(self, d):
+    if self.shape == words.RAMP_LINEAR:
+        return -((self.coef * d * d) >> 1)                          # wrong sign
+    return (self.coef * self.table_at(d)) >> words.TABLE_SHIFT
+
+
+def _smooth_term_wrong_shift(self, d):
+    if self.shape == words.RAMP_LINEAR:
+        return (self.coef * d * d) >> 1
+    return (self.coef * self.table_at(d)) >> (words.TABLE_SHIFT - 1)
+
+
+CHIRP_MUTANTS = {
+    "min-jerk table coefficient": ("minjerk_table_entry", _minjerk_wrong_coefficient, words),
+    "cosine table without 1/pi": ("cosine_table_entry", _cosine_missing_pi, words),
+    "linear chirp term without 1/2": ("chirp_term", _linear_term_no_half, words.Ramp),
+    "linear chirp term with the wrong sign": ("chirp_term", _linear_term_plus_sign, words.Ramp),
+    "smooth chirp term scaled by 2": ("chirp_term", _smooth_term_wrong_shift, words.Ramp),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CHIRP_MUTANTS))
+def test_chirp_mutants_are_caught(monkeypatch, oracle_built, name):
+    attr, fn, owner = CHIRP_MUTANTS[name]
+    monkeypatch.setattr(owner, attr, fn)
+    assert some_pin_fails(CHIRP_PINS), name
+
+
+def test_post_window_line_mutant_is_caught(monkeypatch, oracle_built):
+    orig = words.Ramp.__init__
+
+    def init(self, a, N, shape, p_line, f_line, f_to, table=None):
+        orig(self, a, N, shape, p_line, f_line, f_to, table)
+        end = self.a + self.N
+        phi_end = (self.p_line + self.f_line * end + self.chirp_term(self.N)) & words.MASK64
+        self.p_after = (phi_end - self.f_line * end) & words.MASK64     # start frequency after the window
+
+    monkeypatch.setattr(words.Ramp, "__init__", init)
+    assert some_pin_fails(CHIRP_PINS)
+
+
+def test_default_gain_mutant_is_caught(monkeypatch, oracle_built):
+    monkeypatch.setattr(words, "default_gain", lambda amps: 32767.0 / sum(float(a) ** 2 for a in amps))
+    assert some_pin_fails([pins.test_mean_power_and_default_gain])
+
+
+C_MUTANTS = {
+    "sum uses cosine": ("acc += tones[k].amp * sin(two_pi * turns);", "acc += tones[k].amp * cos(two_pi * turns);"),
+    "turn scale off by 2": ("double turns = (double)(int64_t)w * 0x1p-64;", "double turns = (double)(int64_t)w * 0x1p-63;"),
+    "linear term without 1/2": ("return (uint64_t)(prod >> 1);", "return (uint64_t)(prod);"),
+    "post-window line uses the start frequency": ("return r->p_after + r->f_after * n;", "return r->p_after + r->f_line * n;"),
+    "rounding truncates": ("double r = nearbyint(acc);", "double r = trunc(acc);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(C_MUTANTS))
+def test_c_oracle_mutants_are_caught(monkeypatch, tmp_path, oracle_built, name):
+    old, new = C_MUTANTS[name]
+    src = open(csynth._SRC).read()
+    assert src.count(old) >= 1, name
+    mutated = tmp_path / "synth_mut.c"
+    mutated.write_text(src.replace(old, new))
+    lib = tmp_path / "synth_mut.so"
+    subprocess.check_call(["gcc", "-std=c99", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                           str(mutated), "-o", str(lib), "-lm"])
+    monkeypatch.setattr(csynth, "_LIB", str(lib))
+    monkeypatch.setattr(csynth, "_lib", None)
+    monkeypatch.setattr(csynth, "build", lambda force=True: str(lib))
+    try:
+        assert some_pin_fails(SUM_PINS), name
+    finally:
+        csynth._lib = None
