@@ -155,18 +155,22 @@ def serving_leg(W, seconds):
                             "arrival + 5 ms + chunk start / fs"}
 
 
-def large_array_leg(torch, awg, W, K):
+def large_array_leg(torch, awg, W, K, method="direct"):
     """Config-4 style stream: K tones, groups of 100 retuned (1 ms linear chirps)
-    in turn, 2^20-sample chunks over 1 s of output; per-chunk device time."""
+    in turn, 2^20-sample chunks over 1 s of output; per-chunk device time. With a
+    matrix-core method the chunks take the hybrid path (line tones on the matrix
+    cores, ramping tones on the direct kernel); the last 12 chunks run again with
+    kernel timing on for the per-kernel split."""
     w = W.config4(K=K)
-    plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2)
+    plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, method_codes(awg)[method])
     events = sorted(w.retunes, key=lambda e: e[1])
     n_chunks = w.count // w.chunk
     buf = [torch.empty(w.chunk, dtype=torch.int16, device="cuda") for _ in range(2)]
     s = torch.cuda.current_stream()
+    # the retune schedule as ready-made C arrays, one per chunk (the controller's
+    # side of the stream; building them is not part of the synthesis)
+    batches = []
     i = 0
-    evs = []
-    t0 = time.perf_counter()
     for c in range(n_chunks):
         end = (c + 1) * w.chunk
         batch = []
@@ -174,11 +178,15 @@ def large_array_leg(torch, awg, W, K):
             k, a, n, shape, f = events[i]
             batch.append((k, shape, a, n, f))
             i += 1
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        batches.append(awg.retune_array(batch) if batch else None)
+    ticks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_chunks)]
+    evs = []
+    t0 = time.perf_counter()
+    for c in range(n_chunks):
+        e0, e1 = ticks[c]
         e0.record(s)
-        if batch:
-            plan.retune(batch)
+        if batches[c] is not None:
+            plan.retune(batches[c])
         plan.stream_next(w.chunk, out=buf[c % 2])
         e1.record(s)
         evs.append((e0, e1))
@@ -186,8 +194,19 @@ def large_array_leg(torch, awg, W, K):
     wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     chunk_s = w.chunk / w.fs_hz
+    # per-kernel split: the last 12 chunks again (within one retune cycle, so the
+    # tones still hold the windows those chunks were streamed with)
+    ctx = awg.context(0)
+    awg.awg_profile_read(ctx, reset=True)
+    awg.awg_profile_enable(ctx, True)
+    for c in range(max(0, n_chunks - 12), n_chunks):
+        plan.synth_chirp(c * w.chunk, w.chunk, out=buf[c % 2])
+    torch.cuda.synchronize()
+    awg.awg_profile_enable(ctx, False)
+    stats = awg.awg_profile_read(ctx, reset=True)
     plan.close()
-    return {"workload": w.name, "tones": K, "chunks": n_chunks, "retunes": len(events),
+    return {"workload": w.name, "method": method, "tones": K, "chunks": n_chunks, "retunes": len(events),
+            "kernels_avg_ms": {k: v[1] / max(1, v[0]) for k, v in stats.items()},
             "p50_chunk_ms": float(np.percentile(lat, 50)), "p99_chunk_ms": float(np.percentile(lat, 99)),
             "tone_samples_per_s": K * w.chunk / (float(np.mean(lat)) * 1e-3),
             "rtf_mean": chunk_s / (float(np.mean(lat)) * 1e-3), "rtf_p99": chunk_s / (float(np.percentile(lat, 99)) * 1e-3),
@@ -321,7 +340,8 @@ def main():
         res["streaming"] = streaming_leg(torch, awg, W)
     if "arrays" in legs:
         log("large-array legs ...")
-        res["large_arrays"] = [large_array_leg(torch, awg, W, K) for K in (5000, 10000)]
+        res["large_arrays"] = [large_array_leg(torch, awg, W, K, m) for K in (5000, 10000)
+                               for m in ("direct", "mfma-f16", "mfma-bf16")]
     if "serve" in legs:
         log("serving leg ...")
         res["serving"] = serving_leg(W, a.serve_seconds)

@@ -174,7 +174,21 @@ awg_status awg_synth_static(awg_plan *plan, uint64_t n0, uint64_t count, int16_t
                             void *hip_stream);
 
 /* Playback pathway: any sample range of any plan (static or chirped) with the
- * direct method. count = 0 is a no-op. */
+ * plan's method. count = 0 is a no-op.
+ *  - AWG_F_METHOD_DIRECT: the direct kernel.
+ *  - An MFMA method on a static plan: as awg_synth_static.
+ *  - An MFMA method on a ramped plan, count >= 65536: the hybrid path.
+ *    The range is cut into rows of 1024 samples from n0. On each row, the tones
+ *    whose window [a, a+N] misses the row are on a straight phase line before or
+ *    after the window. Those (tone, row) pairs are summed by angle addition on the
+ *    matrix cores; the ramping pairs go to the direct kernel, which adds the two
+ *    sums and rounds. This is the static-buffer plus dynamic-part split of
+ *    Eqs. (5)-(7), taken per row from exact words. Same error bar as the
+ *    static MFMA method. The result depends on (n0, count) through the row grid:
+ *    equal calls give equal samples.
+ *  - An MFMA method on a ramped plan, count < 65536: the direct kernel.
+ * Retune and synthesise on one stream: the hybrid path reads the tones'
+ * windows on the host when the call is made. */
 awg_status awg_synth_chirp(awg_plan *plan, uint64_t n0, uint64_t count, int16_t *d_out,
                            void *hip_stream);
 
@@ -182,7 +196,9 @@ awg_status awg_synth_chirp(awg_plan *plan, uint64_t n0, uint64_t count, int16_t 
  * then advance the cursor. *n0_out (nullable) receives the first sample index.
  * Results are bit-identical to awg_synth_chirp over the same range: the phase is
  * a closed form in the absolute sample index and the sum order depends on the
- * plan only. */
+ * plan only. With the direct method, any split of a range into consecutive
+ * calls also gives bit-identical samples; with the hybrid path, only the same
+ * (n0, count) does. */
 awg_status awg_stream_next(awg_plan *plan, uint64_t count, int16_t *d_out, void *hip_stream,
                            uint64_t *n0_out);
 /* Cursor access for checkpoint / resume: (plan inputs, cursor) restore a stream. */
@@ -190,8 +206,9 @@ awg_status awg_stream_seek(awg_plan *plan, uint64_t n0);
 awg_status awg_stream_tell(const awg_plan *plan, uint64_t *n0);
 
 /* Unquantised sum y[n] (FP32, LSB units) for error reporting: the same kernels
- * as the int16 calls with the rounding left out. method: AWG_F_METHOD_* (MFMA
- * methods only for static plans). */
+ * as the int16 calls with the rounding left out. method: AWG_F_METHOD_*,
+ * overriding the plan's (an MFMA method on a ramped plan takes the hybrid path,
+ * as in awg_synth_chirp). */
 awg_status awg_synth_f32(awg_plan *plan, uint32_t method, uint64_t n0, uint64_t count,
                          float *d_y, void *hip_stream);
 

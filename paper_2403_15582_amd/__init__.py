@@ -217,13 +217,22 @@ def awg_ramp_table(shape, n):
     return out
 
 
-def awg_plan_retune(plan, events, stream=0):
-    """events: iterable of (tone, ramp, ramp_start, ramp_len, f_end_hz)."""
+def retune_array(events):
+    """ctypes array of awg_retune from (tone, ramp, ramp_start, ramp_len, f_end_hz)
+    tuples; awg_plan_retune takes it as is (callers on a hot loop build it once)."""
     ev = list(events)
     arr = (awg_retune * max(1, len(ev)))()
     for i, (k, shape, a, n, f) in enumerate(ev):
         arr[i] = awg_retune(int(k), int(shape), int(a), int(n), float(f))
-    _check(lib().awg_plan_retune(plan, arr, len(ev), stream or None), "awg_plan_retune")
+    arr.n_events = len(ev)
+    return arr
+
+
+def awg_plan_retune(plan, events, stream=0):
+    """events: iterable of (tone, ramp, ramp_start, ramp_len, f_end_hz), or an
+    array from retune_array."""
+    arr = events if hasattr(events, "n_events") else retune_array(events)
+    _check(lib().awg_plan_retune(plan, arr, arr.n_events, stream or None), "awg_plan_retune")
 
 
 def awg_synth_static(plan, n0, count, d_out, stream=0):

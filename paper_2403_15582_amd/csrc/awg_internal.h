@@ -21,12 +21,12 @@ constexpr uint64_t kPhaseBias = 1ull << 40;
 // Ramp tables hold 2^16 * N * Psi(d / N).
 constexpr int kTableShift = 16;
 
-// Direct kernel geometry: a workgroup is 4 waves; each wave sums one fixed slice
-// of the tones for the same 64 * S samples, and the 4 slice sums are added in a
-// fixed order. Inside a slice tones are summed in blocks of kBlock.
+// Direct kernel geometry: a workgroup is 4 waves covering the same 64 * S
+// samples; the tone list is cut into blocks (see Block), block i is summed by
+// wave i % 4, and the 4 wave sums are added in a fixed order.
 constexpr int kWaves = 4;
 constexpr int kLanes = 64;
-constexpr int kBlock = 32;
+constexpr int kBlock = 32;          // largest block
 
 // One tone as the kernels read it (64 bytes, read with scalar loads).
 // Static tones have a = UINT64_MAX, n = 0 (their window never opens).
@@ -49,6 +49,22 @@ struct ToneHost {
     double amp;          // A_k * G in FP64
 };
 
+// A block of contiguous tones [begin, begin + count) of a tone list, summed by
+// one wave as one FMA chain per sample. A table of blocks starts with a header
+// entry whose `begin` is the number of blocks that follow; block i (0-based,
+// after the header) belongs to wave i % kWaves. Runs of tones sharing shape,
+// window and table are cut into near-equal blocks in multiples of kWaves, so a
+// run that ramps while the rest of the list is on a line still spreads over
+// all four waves.
+struct Block {
+    uint32_t begin;
+    uint16_t count;
+    uint16_t flags;
+};
+static_assert(sizeof(Block) == 8, "Block must be 8 bytes");
+constexpr uint16_t kBlockUniform = 1;   // every tone shares the first one's shape, window and table
+constexpr uint16_t kBlockSplit = 2;     // hybrid path: on line tiles the tones are summed elsewhere
+
 // One chunk of one plan in a batched launch (64 bytes).
 struct BatchItem {
     const ToneDev *tones;
@@ -56,14 +72,27 @@ struct BatchItem {
     void *out;               // int16 output of this chunk
     uint64_t n0, count;      // absolute first sample, samples in the chunk
     uint32_t tile_begin;     // first tile of this item in the launch
-    int32_t n_tones, slice;
+    int32_t n_tones, pad;
     int32_t is_static;       // 1: no tone has a window
-    const uint8_t *uniform;  // per (slice, block of 32 tones): 1 if the block shares one window and shape
+    const Block *blocks;     // the plan's block table
 };
 static_assert(sizeof(BatchItem) == 64, "BatchItem must be 64 bytes");
 
 // Samples per direct-kernel tile (4 waves x 64 lanes x 16 samples per lane).
 constexpr int kTileSamples = 1024;
+
+// Geometry of the hybrid path's product over count samples in rows of
+// kTileSamples (one row = one direct-kernel tile): row blocks padded to whole
+// 256-row tiles, 8-entry k-blocks, gz split-K slices of kb_split k-blocks, and
+// gz FP32 planes of `plane` elements. Workspace: B hi, B lo, A hi, A lo, planes.
+struct LinesGeom {
+    int32_t kb_n, rb_pad, cb_n, gz, kb_split;
+    uint64_t plane;
+    size_t a_bytes, b_bytes, plane_bytes;
+    size_t work_bytes() const { return 2 * (a_bytes + b_bytes) + plane_bytes; }
+};
+
+struct HybridState;
 
 struct Table {
     int32_t shape;
@@ -105,9 +134,8 @@ struct awg_plan {
     std::vector<int32_t> inv;          // caller's tone index -> device position
     std::vector<const uint64_t *> table_ptrs;   // device pointers, indexed by ToneDev::table
     std::map<std::pair<int32_t, uint64_t>, uint16_t> table_index;
-    int32_t slice;                     // tones per wave slice: ceil(n_tones / 4)
-    std::vector<uint8_t> uniform;      // block flags, see BatchItem::uniform
-    uint8_t *d_uniform;
+    std::vector<awg::Block> blocks;    // block table of dev_mirror (header first)
+    awg::Block *d_blocks;              // device copy, room for n_tones + 1 entries
     awg::ToneDev *d_tones;             // device copy of dev_mirror
     const uint64_t **d_table_ptrs;     // device copy of table_ptrs
     size_t d_table_ptrs_cap;
@@ -123,6 +151,8 @@ struct awg_plan {
     void *d_work;
     size_t d_work_bytes;
     uint64_t mfma_b_key;
+    // hybrid path (matrix cores + direct kernel for ramped plans), created on first use
+    awg::HybridState *hyb;
 };
 
 namespace awg {
@@ -135,8 +165,9 @@ int64_t minjerk_entry(uint64_t n, uint64_t d);
 int64_t cosine_entry(uint64_t n, uint64_t d);
 uint64_t chirp_end_term(int32_t shape, int64_t coef, int64_t dF, uint64_t n);
 ToneDev to_device(const ToneHost &t, uint16_t table);
-// Block flags of a tone list for the direct kernel's slice/block layout.
-void block_flags(const std::vector<ToneDev> &tones, int32_t slice, std::vector<uint8_t> *out);
+// Block table of a tone list (see Block). Tones [0, n_split) are marked split
+// (hybrid path) and no block spans position n_split. At most n + 1 entries.
+void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vector<Block> *out);
 
 // Device table H_N of a smooth shape, created once per context (capi.cpp).
 awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d_out);
@@ -166,5 +197,23 @@ hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint
 // MFMA static synthesis; out_i16 or out_f32 (exactly one non-null).
 awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count,
                        int16_t *out_i16, float *out_f32, hipStream_t s);
+
+// Hybrid path (hybrid.cpp): a ramped plan's samples with the line tones on the
+// matrix cores and the ramping ones on the direct kernel.
+awg_status hybrid_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,
+                        float *out_f32, hipStream_t s);
+void hybrid_release(awg_plan *p);
+size_t hybrid_bytes(const awg_plan *p);       // device memory held by the hybrid path
+// Its two launches (mfma.hip, direct.hip). Line entries: bits 0..28 the tone's
+// device position, bits 29..31 the mode (kLineMode*).
+constexpr uint32_t kLineShift = 29;
+enum : uint32_t { kLinePre = 0, kLinePost = 1, kLineSplitPre = 2, kLineSplitPost = 3 };
+LinesGeom lines_geometry(int32_t n_entries, uint64_t count);
+hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, const uint32_t *d_entries,
+                        int32_t n_entries, uint64_t n0, uint64_t count, void *d_work, hipStream_t s);
+hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks,
+                                const uint32_t *d_order, uint64_t n0, uint64_t count, const float *planes,
+                                int32_t n_planes, uint64_t plane_stride, int16_t *out_i16, float *out_f32,
+                                hipStream_t s);
 
 }  // namespace awg

@@ -16,6 +16,7 @@ using namespace awg;
 
 namespace {
 
+constexpr uint64_t kHybridMin = 1ull << 16;           // shortest request for the hybrid path
 constexpr uint64_t kMaxSample = 1ull << 63;          // n0 + count must stay below
 constexpr size_t kTablePtrCap = 1024;                 // distinct smooth tables per plan
 constexpr size_t kSlots = 16;                         // retune staging slots
@@ -117,8 +118,9 @@ awg_status table_slot(awg_plan *p, int32_t shape, uint64_t n, uint16_t *idx, boo
 
 void free_plan_device(awg_plan *p)
 {
+    hybrid_release(p);
     if (p->d_tones) (void)hipFree(p->d_tones);
-    if (p->d_uniform) (void)hipFree(p->d_uniform);
+    if (p->d_blocks) (void)hipFree(p->d_blocks);
     if (p->d_table_ptrs) (void)hipFree(p->d_table_ptrs);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     if (p->d_work) (void)hipFree(p->d_work);
@@ -277,10 +279,10 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
     p->d_scratch = nullptr;
     p->d_scratch_bytes = 0;
     p->d_work = nullptr;
+    p->hyb = nullptr;
     p->d_work_bytes = 0;
     p->mfma_b_key = 0;
-    p->slice = (n_tones + kWaves - 1) / kWaves;
-    p->d_uniform = nullptr;
+    p->d_blocks = nullptr;
     std::vector<uint16_t> tidx;
     try {
         p->host.resize(n_tones);
@@ -314,7 +316,7 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
     }
     if (st == AWG_OK) {
         // device order: tones that share shape and window next to each other, so
-        // the kernel's blocks of 32 mostly take one regime per tile (stable: the
+        // the kernel's blocks mostly take one regime per tile (stable: the
         // caller's order within a group, identity for all-static plans)
         for (int32_t k = 0; k < n_tones; ++k) p->perm[k] = k;
         std::stable_sort(p->perm.begin(), p->perm.end(), [&](int32_t x, int32_t y) {
@@ -328,13 +330,14 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
             p->inv[p->perm[i]] = i;
             p->dev_mirror[i] = to_device(p->host[p->perm[i]], tidx[p->perm[i]]);
         }
-        block_flags(p->dev_mirror, p->slice, &p->uniform);
+        build_blocks(p->dev_mirror, -1, &p->blocks);
     }
+    const size_t blocks_cap = sizeof(Block) * ((size_t)n_tones + 1);     // largest possible table
     if (st == AWG_OK && ctx) {
         hipError_t e = hipMalloc((void **)&p->d_tones, sizeof(ToneDev) * (size_t)n_tones);
-        if (e == hipSuccess) e = hipMalloc((void **)&p->d_uniform, p->uniform.size());
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_blocks, blocks_cap);
         if (e == hipSuccess)
-            e = hipMemcpy(p->d_uniform, p->uniform.data(), p->uniform.size(), hipMemcpyHostToDevice);
+            e = hipMemcpy(p->d_blocks, p->blocks.data(), sizeof(Block) * p->blocks.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_tones, p->dev_mirror.data(), sizeof(ToneDev) * (size_t)n_tones,
                           hipMemcpyHostToDevice);
@@ -347,7 +350,7 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
                           hipMemcpyHostToDevice);
         }
         if (e != hipSuccess) st = hip_status(e);
-        p->device_bytes = sizeof(ToneDev) * (size_t)n_tones + sizeof(uint64_t *) * kTablePtrCap + p->uniform.size();
+        p->device_bytes = sizeof(ToneDev) * (size_t)n_tones + sizeof(uint64_t *) * kTablePtrCap + blocks_cap;
     }
     if (st != AWG_OK) {
         free_plan_device(p);
@@ -378,7 +381,7 @@ awg_status awg_plan_info_get(const awg_plan *p, awg_plan_info *info)
     info->flags = p->params.flags;
     info->period_log2 = p->params.period_log2;
     info->cursor = p->cursor;
-    info->device_bytes = p->device_bytes + p->d_work_bytes + p->d_scratch_bytes;
+    info->device_bytes = p->device_bytes + p->d_work_bytes + p->d_scratch_bytes + hybrid_bytes(p);
     return AWG_OK;
 }
 
@@ -444,7 +447,7 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
         p->host[k] = next[i];
         p->dev_mirror[p->inv[k]] = to_device(next[i], tidx[i]);
     }
-    block_flags(p->dev_mirror, p->slice, &p->uniform);
+    build_blocks(p->dev_mirror, -1, &p->blocks);
     if (!p->ctx) return AWG_OK;
     // stage the new records and scatter them on the stream
     hipError_t e = hipSetDevice(p->ctx->device);
@@ -455,7 +458,7 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
             s.host = nullptr; s.done = nullptr; s.used = false;
         }
         for (auto &s : p->slots) {
-            e = hipHostMalloc(&s.host, sizeof(ScatterRecord) * kSlotRecords + p->uniform.size(),
+            e = hipHostMalloc(&s.host, sizeof(ScatterRecord) * kSlotRecords + sizeof(Block) * ((size_t)p->n_tones + 1),
                               hipHostMallocDefault);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
             if (e != hipSuccess) return hip_status(e);
@@ -481,14 +484,27 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
     void *d_rec = (char *)p->d_scratch + si * sizeof(ScatterRecord) * kSlotRecords;
     e = hipMemcpyAsync(d_rec, rec, sizeof(ScatterRecord) * (size_t)n_ev, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_scatter_tones(p->d_tones, d_rec, n_ev, s);
-    // the block flags follow the records in the same pinned slot
-    uint8_t *flags = (uint8_t *)slot.host + sizeof(ScatterRecord) * kSlotRecords;
-    std::memcpy(flags, p->uniform.data(), p->uniform.size());
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_uniform, flags, p->uniform.size(), hipMemcpyHostToDevice, s);
+    // the block table follows the records in the same pinned slot
+    Block *blk = (Block *)((char *)slot.host + sizeof(ScatterRecord) * kSlotRecords);
+    const size_t blk_bytes = sizeof(Block) * p->blocks.size();
+    std::memcpy(blk, p->blocks.data(), blk_bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_blocks, blk, blk_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     slot.used = true;
     return hip_status(e);
+}
+
+// Samples of any plan with the given method: the direct kernel; the matrix
+// cores for static plans; the hybrid of both for ramped plans (short requests
+// stay on the direct kernel, which gains nothing from the matrix cores there).
+static awg_status synth_any(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,
+                            float *out_f32, hipStream_t s)
+{
+    if (method != AWG_F_METHOD_DIRECT) {
+        if (p->n_ramped == 0) return mfma_static(p, method, n0, count, out_i16, out_f32, s);
+        if (count >= kHybridMin) return hybrid_synth(p, method, n0, count, out_i16, out_f32, s);
+    }
+    return hip_status(out_f32 ? launch_direct_f32(p, n0, count, out_f32, s) : launch_direct_i16(p, n0, count, out_i16, s));
 }
 
 awg_status awg_synth_chirp(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d_out, void *hip_stream)
@@ -498,7 +514,7 @@ awg_status awg_synth_chirp(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d_
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
     if (!d_out) return AWG_E_INVALID;
-    return hip_status(launch_direct_i16(p, n0, count, d_out, (hipStream_t)hip_stream));
+    return synth_any(p, p->params.flags & AWG_F_METHOD_MASK, n0, count, d_out, nullptr, (hipStream_t)hip_stream);
 }
 
 awg_status awg_synth_static(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d_out, void *hip_stream)
@@ -524,10 +540,7 @@ awg_status awg_synth_f32(awg_plan *p, uint32_t method, uint64_t n0, uint64_t cou
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
     if (!d_y) return AWG_E_INVALID;
-    if (method == AWG_F_METHOD_DIRECT)
-        return hip_status(launch_direct_f32(p, n0, count, d_y, (hipStream_t)hip_stream));
-    if (p->n_ramped > 0) return AWG_E_UNSUPPORTED;
-    return mfma_static(p, method, n0, count, nullptr, d_y, (hipStream_t)hip_stream);
+    return synth_any(p, method, n0, count, nullptr, d_y, (hipStream_t)hip_stream);
 }
 
 awg_status awg_stream_next(awg_plan *p, uint64_t count, int16_t *d_out, void *hip_stream, uint64_t *n0_out)
@@ -538,7 +551,8 @@ awg_status awg_stream_next(awg_plan *p, uint64_t count, int16_t *d_out, void *hi
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count > 0) {
         if (!d_out) return AWG_E_INVALID;
-        st = hip_status(launch_direct_i16(p, n0, count, d_out, (hipStream_t)hip_stream));
+        st = synth_any(p, p->params.flags & AWG_F_METHOD_MASK, n0, count, d_out, nullptr,
+                       (hipStream_t)hip_stream);
         if (st != AWG_OK) return st;
     }
     p->cursor = n0 + count;

@@ -1,15 +1,15 @@
 // Direct VALU synthesis on gfx950: exact 64-bit phase words, v_sin_f32, FP32 sum.
 //
 // y[n] = sum_k amp_k * sin(2 pi phi_k(n) / 2^64) for a tile of 64*S contiguous
-// samples per workgroup. The 4 waves of a workgroup split the tones into 4 fixed
-// slices and cover the same samples; lane l of a wave owns samples
-// [tile0 + l*S, tile0 + (l+1)*S). Tone parameters are wave-uniform and come in
-// through scalar loads. Inside a slice tones are summed in blocks of 32 (FMA
-// chain per block, block sums added to the slice sum); the 4 slice sums meet in
-// LDS and are added in the order ((s0 + s1) + s2) + s3. The summation order
-// therefore depends only on the tone list, never on the sample range, the tile
-// position or the batch, so chunked, one-shot and batched results are
-// bit-identical.
+// samples per workgroup. The 4 waves of a workgroup cover the same samples;
+// lane l of a wave owns samples [tile0 + l*S, tile0 + (l+1)*S). The tone list
+// comes with a block table (contiguous runs of at most 32 tones): wave w sums
+// blocks w, w+4, w+8, ... (FMA chain per block, block sums added to the wave
+// sum in block order), and the 4 wave sums meet in LDS and are added in the
+// order ((s0 + s1) + s2) + s3. Tone parameters are wave-uniform and come in
+// through scalar loads. The summation order therefore depends only on the tone
+// list and its table, never on the sample range, the tile position or the
+// batch, so chunked, one-shot and batched results are bit-identical.
 //
 // Phase words (the piecewise law of Eq. (8)) are computed per tone and tile in
 // one of four uniform regimes: before the window (line p0 + f0 n), after it
@@ -73,6 +73,43 @@ __device__ __forceinline__ float word_sin(uint64_t w)
     return __builtin_amdgcn_sinf(__uint_as_float(__builtin_amdgcn_alignbit(0x7fu, hi, 9u)));
 }
 
+// A tile in which an edge of the window falls (some samples before or after it,
+// some inside): the lane's first word in closed form, then exact increments
+// phi(n+1) - phi(n) picked per sample: f0 before the window, f1 after it, and
+// inside a linear window f0 + T(d+1) - T(d) with T(d) = floor(R d^2 / 2), i.e.
+// R d + floor(R/2) for even d and R (d+1) - floor(R/2) for odd d. A smooth
+// window adds its table term to the line p0 + f0 min(n, a+N) + f1 max(d-N, 0)
+// (the table starts at 0, so before the window the term vanishes).
+template <int S, typename F>
+__device__ __forceinline__ void edge_run(const ToneDev &t, const uint64_t *const *tables, uint64_t n, F &&f)
+{
+    int64_t d = (int64_t)(n - t.a);                    // |d| < 2^62 for valid inputs
+    const int64_t N = (int64_t)t.n;
+    if (t.shape == AWG_RAMP_LINEAR) {
+        const uint64_t R = (uint64_t)t.coef, h = (uint64_t)(t.coef >> 1), Rh = R - h;
+        uint64_t ph = phase_general(t, tables, n);
+        uint64_t Rd = R * (uint64_t)d;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            f(s, ph);
+            const uint64_t in = t.f0 + Rd + ((d & 1) ? Rh : h);
+            ph += d < 0 ? t.f0 : (d < N ? in : t.f1);
+            ++d;
+            Rd += R;
+        }
+    } else {
+        const uint64_t *H = table_of(tables, t.table);
+        uint64_t line = d < N ? t.p0 + t.f0 * n : t.p0 + t.f0 * (t.a + t.n) + t.f1 * (uint64_t)(d - N);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t e = d < 0 ? 0 : (d < N ? d : N);
+            f(s, line + smooth_term(t.coef, H[e]));
+            line += d < N ? t.f0 : t.f1;
+            ++d;
+        }
+    }
+}
+
 // Calls f(s, phi) for the S samples tile0 + lane*S + s of tone t.
 template <int S, typename F>
 __device__ __forceinline__ void gen_phases(const ToneDev &t, const uint64_t *const *tables,
@@ -114,8 +151,7 @@ __device__ __forceinline__ void gen_phases(const ToneDev &t, const uint64_t *con
             }
         }
     } else {                                                        // straddles an edge
-#pragma unroll
-        for (int s = 0; s < S; ++s) f(s, phase_general(t, tables, tile0 + j + s));
+        edge_run<S>(t, tables, tile0 + j, f);
     }
 }
 
@@ -156,42 +192,53 @@ __device__ __forceinline__ int16_t quantise(float y)
     return (int16_t)(int32_t)r;
 }
 
+// Extra input of the hybrid path: the tones of blocks flagged kBlockSplit are
+// summed elsewhere (the matrix cores) on the tiles where they are on a line, so
+// the tile skips them there; add[z * add_stride + i], z < n_add, are partial
+// sums of sample i of the tile, added in z order before the tile's own sum.
+struct HybridIn {
+    int32_t n_add;
+    const float *add;
+    uint64_t add_stride;
+};
+
 // One tile: the 64*S samples tile0 .. tile0 + 64*S - 1 of a tone list, summed
 // by the 4 waves of the workgroup and written to out[0 .. valid). STATIC: every
 // tone is a static line (no windows), so the regime logic is compiled out; the
 // arithmetic per sample is the same as the static regime of gen_phases, so both
-// instantiations give identical sums. Ends with a barrier so `part` can be
-// reused by the next tile of the same workgroup.
-template <int S, bool F32OUT, bool STATIC>
-__device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, int32_t n_tones, int32_t slice,
-                                           const uint64_t *const *__restrict__ tables,
-                                           const uint8_t *__restrict__ uniform, uint64_t tile0,
-                                           uint32_t valid, void *__restrict__ out, float (*part)[kLanes * S])
+// instantiations give identical sums. HYB: see HybridIn. Ends with a barrier so
+// `part` can be reused by the next tile of the same workgroup.
+template <int S, bool F32OUT, bool STATIC, bool HYB = false>
+__device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, const Block *__restrict__ blocks,
+                                           const uint64_t *const *__restrict__ tables, uint64_t tile0,
+                                           uint32_t valid, void *__restrict__ out, float (*part)[kLanes * S],
+                                           const HybridIn &hyb = HybridIn{0, nullptr, 0})
 {
     constexpr int T = kLanes * S;                 // samples per tile
     const uint32_t lane = threadIdx.x & 63u;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    const int kb = wave * slice;
-    const int ke = min(n_tones, kb + slice);
     float acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0f;
 
-    const int nbps = (slice + kBlock - 1) / kBlock;      // blocks per slice
+    const int n_blocks = (int)blocks[0].begin;
     const uint64_t tile_last = tile0 + (uint64_t)(T - 1);
     const uint32_t j = lane * S;
-    for (int k0 = kb, bi = wave * nbps; k0 < ke; k0 += kBlock, ++bi) {
-        const int k1 = min(ke, k0 + kBlock);
+    for (int bi = wave; bi < n_blocks; bi += kWaves) {
+        const Block bk = blocks[1 + bi];
+        const int k0 = (int)bk.begin, k1 = k0 + (int)bk.count;
+        const bool split = HYB && (bk.flags & kBlockSplit);
         float blk[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) blk[s] = 0.0f;
-        if (!STATIC && uniform[bi]) {
+        if (!STATIC && (bk.flags & kBlockUniform)) {
             // every tone of the block has the window and shape of tones[k0]
             const ToneDev r = tones[k0];
             const bool pre = tile_last < r.a, post = tile0 > r.a + r.n;
             if (pre || post) {
-                for (int k = k0; k < k1; ++k) {
+                // (a block of split tones on a line is summed elsewhere)
+                for (int k = k0; k < (split ? k0 : k1); ++k) {
                     const uint64_t P = pre ? tones[k].p0 : tones[k].p1, Fw = pre ? tones[k].f0 : tones[k].f1;
                     const float amp = tones[k].amp;
                     static_run<S>(P, Fw, tile0, j, [&](int s, uint64_t ph) {
@@ -247,9 +294,9 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, in
                 for (int k = k0; k < k1; ++k) {
                     const ToneDev t = tones[k];
                     const float amp = t.amp;
-#pragma unroll
-                    for (int s = 0; s < S; ++s)
-                        blk[s] = __builtin_fmaf(amp, word_sin(phase_general(t, tables, tile0 + j + s)), blk[s]);
+                    edge_run<S>(t, tables, tile0 + j, [&](int s, uint64_t ph) {
+                        blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+                    });
                 }
             }
         } else if (STATIC) {
@@ -267,6 +314,7 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, in
         } else {
             for (int k = k0; k < k1; ++k) {
                 const ToneDev t = tones[k];
+                if (split && (tile_last < t.a || tile0 > t.a + t.n)) continue;
                 const float amp = t.amp;
                 gen_phases<S>(t, tables, tile0, lane, [&](int s, uint64_t ph) {
                     blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
@@ -282,11 +330,44 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, in
     __syncthreads();
 
     constexpr int PER = T / 256;                  // samples per thread in the epilogue
+    static_assert(PER == 4, "epilogue reads float4");
     const uint32_t i0 = threadIdx.x * PER;
+    float g[PER];
+    if (HYB && hyb.n_add > 0) {
+        if (i0 + PER <= valid) {
+            // loads of up to 8 planes in flight together, added in plane order
+            constexpr int kBatch = 8;
+            for (int z0 = 0; z0 < hyb.n_add; z0 += kBatch) {
+                float4 u[kBatch];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q)
+                    if (z0 + q < hyb.n_add) u[q] = *(const float4 *)(hyb.add + (uint64_t)(z0 + q) * hyb.add_stride + i0);
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    if (z0 + q >= hyb.n_add) break;
+                    if (z0 + q == 0) {
+                        g[0] = u[q].x; g[1] = u[q].y; g[2] = u[q].z; g[3] = u[q].w;
+                    } else {
+                        g[0] += u[q].x; g[1] += u[q].y; g[2] += u[q].z; g[3] += u[q].w;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                g[e] = 0.0f;
+                if (i0 + e < valid) {
+                    g[e] = hyb.add[i0 + e];
+                    for (int z = 1; z < hyb.n_add; ++z) g[e] += hyb.add[(uint64_t)z * hyb.add_stride + i0 + e];
+                }
+            }
+        }
+    }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = i0 + e;
-        const float y = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+        float y = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+        if (HYB && hyb.n_add > 0) y = g[e] + y;
         if (i < valid) {
             if (F32OUT) ((float *)out)[i] = y;
             else ((int16_t *)out)[i] = quantise(y);
@@ -296,9 +377,9 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, in
 }
 
 template <int S, bool F32OUT, bool STATIC>
-__global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
-                                                     int32_t slice, const uint64_t *const *__restrict__ tables,
-                                                     const uint8_t *__restrict__ uniform, uint64_t n0,
+__global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__ tones,
+                                                     const Block *__restrict__ blocks,
+                                                     const uint64_t *const *__restrict__ tables, uint64_t n0,
                                                      uint64_t count, void *__restrict__ out)
 {
     constexpr int T = kLanes * S;
@@ -307,7 +388,30 @@ __global__ __launch_bounds__(256) void direct_kernel(const ToneDev *__restrict__
     const uint64_t left = count - rel;
     const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
     void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
-    synth_tile<S, F32OUT, STATIC>(tones, n_tones, slice, tables, uniform, n0 + rel, valid, o, part);
+    synth_tile<S, F32OUT, STATIC>(tones, blocks, tables, n0 + rel, valid, o, part);
+}
+
+// Hybrid path: the tiles of a ramped plan's range with the line tones summed by
+// the matrix cores into n_planes partial planes (see HybridIn). Workgroup b
+// takes tile order[b]: the host puts the costliest tiles (window edges) first,
+// so they do not start last and hold up the end of the launch.
+template <int S, bool F32OUT>
+__global__ __launch_bounds__(256) void direct_hybrid_kernel(const ToneDev *__restrict__ tones,
+                                                            const Block *__restrict__ blocks,
+                                                            const uint32_t *__restrict__ order,
+                                                            const uint64_t *const *__restrict__ tables,
+                                                            uint64_t n0, uint64_t count, void *__restrict__ out,
+                                                            const float *__restrict__ planes, int32_t n_planes,
+                                                            uint64_t plane_stride)
+{
+    constexpr int T = kLanes * S;
+    __shared__ float part[kWaves][T];
+    const uint64_t rel = (uint64_t)order[blockIdx.x] * T;
+    const uint64_t left = count - rel;
+    const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
+    void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
+    const HybridIn hyb{n_planes, planes + rel, plane_stride};
+    synth_tile<S, F32OUT, false, true>(tones, blocks, tables, n0 + rel, valid, o, part, hyb);
 }
 
 // Batched synthesis of many plans' chunks in one launch (continuous batching).
@@ -334,11 +438,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem *__restrict_
         const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
         int16_t *o = (int16_t *)it.out + rel;
         if (it.is_static)
-            synth_tile<S, false, true>(it.tones, it.n_tones, it.slice, it.tables, it.uniform, it.n0 + rel, valid,
-                                       o, part);
+            synth_tile<S, false, true>(it.tones, it.blocks, it.tables, it.n0 + rel, valid, o, part);
         else
-            synth_tile<S, false, false>(it.tones, it.n_tones, it.slice, it.tables, it.uniform, it.n0 + rel, valid,
-                                        o, part);
+            synth_tile<S, false, false>(it.tones, it.blocks, it.tables, it.n0 + rel, valid, o, part);
     }
 }
 
@@ -385,10 +487,10 @@ static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, 
             ProfScope prof(p->ctx, s, F32OUT ? "direct_kernel_f32" : "direct_kernel");
             if (p->n_ramped == 0)
                 hipLaunchKernelGGL((direct_kernel<kS, F32OUT, true>), dim3((uint32_t)now_tiles), dim3(256), 0, s,
-                                   p->d_tones, p->n_tones, p->slice, p->d_table_ptrs, p->d_uniform, n0, now, out);
+                                   p->d_tones, p->d_blocks, p->d_table_ptrs, n0, now, out);
             else
                 hipLaunchKernelGGL((direct_kernel<kS, F32OUT, false>), dim3((uint32_t)now_tiles), dim3(256), 0,
-                                   s, p->d_tones, p->n_tones, p->slice, p->d_table_ptrs, p->d_uniform, n0, now, out);
+                                   s, p->d_tones, p->d_blocks, p->d_table_ptrs, n0, now, out);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return e;
@@ -430,6 +532,27 @@ hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint6
         out += now;
     }
     return hipSuccess;
+}
+
+hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks,
+                                const uint32_t *d_order, uint64_t n0, uint64_t count, const float *planes,
+                                int32_t n_planes, uint64_t plane_stride, int16_t *out_i16, float *out_f32,
+                                hipStream_t s)
+{
+    constexpr uint64_t T = kLanes * kS;
+    const uint64_t tiles = (count + T - 1) / T;
+    if (tiles == 0) return hipSuccess;
+    if (tiles > kMaxTilesPerLaunch) return hipErrorInvalidValue;
+    ProfScope prof(p->ctx, s, out_f32 ? "direct_hybrid_kernel_f32" : "direct_hybrid_kernel");
+    if (out_f32)
+        hipLaunchKernelGGL((direct_hybrid_kernel<kS, true>), dim3((uint32_t)tiles), dim3(256), 0, s, d_tones,
+                           d_blocks, d_order, p->d_table_ptrs, n0, count, (void *)out_f32, planes, n_planes,
+                           plane_stride);
+    else
+        hipLaunchKernelGGL((direct_hybrid_kernel<kS, false>), dim3((uint32_t)tiles), dim3(256), 0, s, d_tones,
+                           d_blocks, d_order, p->d_table_ptrs, n0, count, (void *)out_i16, planes, n_planes,
+                           plane_stride);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint32_t grid, hipStream_t s)

@@ -1,0 +1,296 @@
+// Hybrid synthesis of ramped plans: matrix cores for the tones on a line,
+// the direct kernel for the tones that ramp.
+//
+// The additive sum of Eq. (3) splits by tone. Over a row of 1024 samples a tone
+// whose window [a, a+N] misses the row is on one straight phase line, either
+// p0 + F0 n before the window or p1 + F1 n after it (Eq. (8) cases 1 and 3).
+// Such (tone, row) pairs are summed by angle addition on the matrix cores. Only
+// the pairs whose row meets the window run on the direct kernel, with the exact
+// chirp phase. The paper's split of a static buffer plus a dynamic part
+// (Eqs. (5)-(7), the add/subtract of the weighted combination) is the same idea.
+// Here it is taken per row, from the exact line words, so nothing accumulates
+// across calls.
+//
+// Per call (in pieces of at most 2^22 samples) the host classifies every tone
+// against the rows [n0 + 1024 c, n0 + 1024 c + 1023]:
+//  * window outside all rows: one line entry for the whole range;
+//  * window meets some rows, and the rows where the tone is on a line are at
+//    least 1/8 of all rows: "split". Line entries cover the rows before and
+//    after the window. The direct kernel takes the tone only on the other rows.
+//  * otherwise the direct kernel takes the tone on every row.
+// The product writes gz FP32 partial-sum planes. The direct kernel adds them in
+// plane order to its own sum of the ramping tones, then rounds.
+//
+// Results depend on (n0, count) through the row grid. They are deterministic
+// for equal calls, but differ by rounding from the direct method, and from
+// calls over other ranges.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "awg_internal.h"
+
+namespace awg {
+
+namespace {
+
+constexpr uint64_t kRow = kTileSamples;          // product row == direct-kernel tile
+constexpr uint64_t kPiece = 1ull << 22;          // samples per pass (bounds the workspace)
+constexpr int kHybSlots = 4;                     // pinned staging slots in flight
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+awg_status hst(hipError_t e)
+{
+    if (e == hipSuccess) return AWG_OK;
+    return e == hipErrorOutOfMemory ? AWG_E_NOMEM : AWG_E_HIP;
+}
+
+}  // namespace
+
+struct HybridState {
+    std::mutex mu;
+    struct Slot {
+        void *host = nullptr;
+        size_t host_cap = 0;
+        void *dev = nullptr;
+        size_t dev_cap = 0;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    };
+    Slot slots[kHybSlots];
+    int next = 0;
+    void *d_work = nullptr;
+    size_t work_cap = 0;
+    hipEvent_t work_done = nullptr;              // last use of d_work, on whatever stream
+    bool work_used = false;
+    // host scratch kept between calls
+    std::vector<uint32_t> entries;
+    std::vector<int32_t> split, only;
+    std::vector<ToneDev> direct;
+    std::vector<Block> blocks;
+    std::vector<float> cost;
+    std::vector<uint32_t> order;
+};
+
+void hybrid_release(awg_plan *p)
+{
+    HybridState *h = p->hyb;
+    if (!h) return;
+    for (auto &s : h->slots) {
+        if (s.done) (void)hipEventSynchronize(s.done);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.done) (void)hipEventDestroy(s.done);
+    }
+    if (h->work_done) (void)hipEventSynchronize(h->work_done);
+    if (h->d_work) (void)hipFree(h->d_work);
+    if (h->work_done) (void)hipEventDestroy(h->work_done);
+    delete h;
+    p->hyb = nullptr;
+}
+
+size_t hybrid_bytes(const awg_plan *p)
+{
+    const HybridState *h = p->hyb;
+    if (!h) return 0;
+    size_t b = h->work_cap;
+    for (const auto &s : h->slots) b += s.dev_cap;
+    return b;
+}
+
+// Sorts tone positions so that tones sharing shape, window and table sit together
+// (uniform blocks for the direct kernel).
+static void sort_group(const std::vector<ToneDev> &tones, std::vector<int32_t> *idx)
+{
+    std::stable_sort(idx->begin(), idx->end(), [&](int32_t x, int32_t y) {
+        const ToneDev &a = tones[x], &b = tones[y];
+        if (a.shape != b.shape) return a.shape < b.shape;
+        if (a.a != b.a) return a.a < b.a;
+        if (a.n != b.n) return a.n < b.n;
+        return a.table < b.table;
+    });
+}
+
+// Line entries and the direct kernel's tone list for rows [0, rows) from n0.
+static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t rows)
+{
+    h->entries.clear();
+    h->split.clear();
+    h->only.clear();
+    const uint64_t last = n0 + rows * kRow - 1;
+    for (int32_t k = 0; k < p->n_tones; ++k) {
+        const ToneDev &t = p->dev_mirror[k];
+        const uint32_t kk = (uint32_t)k;
+        if (t.shape == AWG_RAMP_NONE || last < t.a) {
+            h->entries.push_back(kk | (kLinePre << kLineShift));
+            continue;
+        }
+        if (n0 > t.a + t.n) {
+            h->entries.push_back(kk | (kLinePost << kLineShift));
+            continue;
+        }
+        // rows ending before a (n0 + 1024c + 1023 < a) and starting after a + N
+        const uint64_t pre_rows = t.a > n0 ? std::min<uint64_t>(rows, (t.a - n0) / kRow) : 0;
+        const uint64_t q = (t.a + t.n - n0) / kRow;
+        const uint64_t post_rows = rows > q + 1 ? rows - (q + 1) : 0;
+        const uint64_t line_rows = pre_rows + post_rows;
+        if (line_rows > 0 && line_rows * 8 >= rows) {
+            if (pre_rows) h->entries.push_back(kk | (kLineSplitPre << kLineShift));
+            if (post_rows) h->entries.push_back(kk | (kLineSplitPost << kLineShift));
+            h->split.push_back(k);
+        } else {
+            h->only.push_back(k);
+        }
+    }
+    sort_group(p->dev_mirror, &h->split);
+    sort_group(p->dev_mirror, &h->only);
+    h->direct.clear();
+    for (int32_t k : h->split) h->direct.push_back(p->dev_mirror[k]);
+    for (int32_t k : h->only) h->direct.push_back(p->dev_mirror[k]);
+}
+
+// Launch order of the direct kernel's tiles, costliest first (a stable sort
+// on an estimate: a tile where a tone's window opens or closes evaluates every
+// sample in closed form, about 3.5 times a tile inside the window; a
+// direct-only tone on its line costs about 0.6; split tones on a line nothing).
+static void tile_order(HybridState *h, uint64_t n0, uint64_t rows, int32_t n_split)
+{
+    h->cost.assign(rows + 1, 0.0f);
+    std::vector<float> &c = h->cost;
+    const uint64_t last = n0 + rows * kRow - 1;
+    float base = 0.0f;                                  // cost on every tile
+    for (size_t i = 0; i < h->direct.size(); ++i) {
+        const ToneDev &t = h->direct[i];
+        const bool split = (int32_t)i < n_split;
+        const uint64_t a = t.a, e = t.a + t.n;
+        // tiles meeting the window: [ca, ce]
+        const uint64_t ca = a <= n0 ? 0 : (a - n0) / kRow;
+        const uint64_t ce = e >= last ? rows - 1 : (e - n0) / kRow;
+        if (!split) {
+            base += 0.6f;
+            c[ca] -= 0.6f;
+            c[ce + 1] += 0.6f;
+        }
+        c[ca] += 1.0f;                                  // in-window cost over [ca, ce]
+        c[ce + 1] -= 1.0f;
+        // tiles where an edge falls inside (closed form per sample)
+        if (a > n0 && (a - n0) % kRow != 0) { c[ca] += 2.5f; c[ca + 1] -= 2.5f; }
+        if (e < last && (e - n0) % kRow != kRow - 1) { c[ce] += 2.5f; c[ce + 1] -= 2.5f; }
+    }
+    float run = base;
+    for (uint64_t r = 0; r < rows; ++r) { run += c[r]; c[r] = run; }
+    h->order.resize(rows);
+    for (uint64_t r = 0; r < rows; ++r) h->order[r] = (uint32_t)r;
+    std::stable_sort(h->order.begin(), h->order.end(), [&](uint32_t x, uint32_t y) { return c[x] > c[y]; });
+}
+
+static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n0, uint64_t count,
+                        int16_t *out_i16, float *out_f32, hipStream_t s)
+{
+    const uint64_t rows = (count + kRow - 1) / kRow;
+    classify(p, h, n0, rows);
+    const int32_t n_entries = (int32_t)h->entries.size();
+    const int32_t n_direct = (int32_t)h->direct.size();
+    build_blocks(h->direct, (int32_t)h->split.size(), &h->blocks);
+    tile_order(h, n0, rows, (int32_t)h->split.size());
+
+    // staging blob: entries | direct tone list | block table | tile order
+    const size_t off_t = align_up(sizeof(uint32_t) * (size_t)n_entries, 256);
+    const size_t off_b = align_up(off_t + sizeof(ToneDev) * (size_t)n_direct, 256);
+    const size_t off_o = align_up(off_b + sizeof(Block) * h->blocks.size(), 256);
+    const size_t total = off_o + sizeof(uint32_t) * rows;
+    // slots are sized for the largest blob this plan can produce, so they are allocated once
+    const size_t cap = align_up(sizeof(uint32_t) * 2 * (size_t)p->n_tones, 256) +
+                       align_up(sizeof(ToneDev) * (size_t)p->n_tones, 256) +
+                       align_up(sizeof(Block) * ((size_t)p->n_tones + 1), 256) + sizeof(uint32_t) * (kPiece / kRow);
+    HybridState::Slot &slot = h->slots[h->next];
+    h->next = (h->next + 1) % kHybSlots;
+    hipError_t e = hipSuccess;
+    if (!slot.done) e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
+    if (e == hipSuccess && slot.used) e = hipEventSynchronize(slot.done);
+    if (e != hipSuccess) return hst(e);
+    slot.used = false;
+    if (slot.host_cap < total) {
+        if (slot.host) (void)hipHostFree(slot.host);
+        slot.host = nullptr;
+        slot.host_cap = 0;
+        e = hipHostMalloc(&slot.host, std::max(cap, total), hipHostMallocDefault);
+        if (e != hipSuccess) return hst(e);
+        slot.host_cap = std::max(cap, total);
+    }
+    if (slot.dev_cap < total) {
+        if (slot.dev) (void)hipFree(slot.dev);
+        slot.dev = nullptr;
+        slot.dev_cap = 0;
+        e = hipMalloc(&slot.dev, std::max(cap, total));
+        if (e != hipSuccess) return hst(e);
+        slot.dev_cap = std::max(cap, total);
+    }
+    char *hb = (char *)slot.host;
+    if (n_entries) std::memcpy(hb, h->entries.data(), sizeof(uint32_t) * (size_t)n_entries);
+    if (n_direct) std::memcpy(hb + off_t, h->direct.data(), sizeof(ToneDev) * (size_t)n_direct);
+    std::memcpy(hb + off_b, h->blocks.data(), sizeof(Block) * h->blocks.size());
+    std::memcpy(hb + off_o, h->order.data(), sizeof(uint32_t) * rows);
+
+    // workspace for the operands and the partial planes
+    const LinesGeom g = lines_geometry(n_entries, count);
+    const bool gemm = n_entries > 0 && g.gz > 0;
+    if (!h->work_done) {
+        e = hipEventCreateWithFlags(&h->work_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hst(e);
+    }
+    if (gemm && h->work_cap < g.work_bytes()) {
+        if (h->work_used) {
+            e = hipEventSynchronize(h->work_done);
+            if (e != hipSuccess) return hst(e);
+        }
+        if (h->d_work) (void)hipFree(h->d_work);
+        h->d_work = nullptr;
+        h->work_cap = 0;
+        const size_t want = g.work_bytes() + g.work_bytes() / 4;      // headroom: entries vary by call
+        e = hipMalloc(&h->d_work, want);
+        if (e != hipSuccess) return hst(e);
+        h->work_cap = want;
+    }
+
+    char *db = (char *)slot.dev;
+    e = hipMemcpyAsync(db, hb, total, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && h->work_used) e = hipStreamWaitEvent(s, h->work_done, 0);
+    if (e == hipSuccess && gemm)
+        e = launch_lines(p, method, g, (const uint32_t *)db, n_entries, n0, count, h->d_work, s);
+    const float *planes = gemm ? (const float *)((char *)h->d_work + 2 * (g.a_bytes + g.b_bytes)) : nullptr;
+    if (e == hipSuccess)
+        e = launch_direct_hybrid(p, (const ToneDev *)(db + off_t), (const Block *)(db + off_b),
+                                 (const uint32_t *)(db + off_o), n0, count, planes, gemm ? g.gz : 0, g.plane,
+                                 out_i16, out_f32, s);
+    if (e == hipSuccess) e = hipEventRecord(h->work_done, s);
+    if (e == hipSuccess) h->work_used = true;
+    if (e == hipSuccess) e = hipEventRecord(slot.done, s);
+    if (e == hipSuccess) slot.used = true;
+    return hst(e);
+}
+
+awg_status hybrid_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,
+                        float *out_f32, hipStream_t s)
+{
+    if (p->n_tones >= (int32_t)(1u << kLineShift)) return AWG_E_UNSUPPORTED;
+    if (!p->hyb) {
+        try { p->hyb = new HybridState(); } catch (...) { return AWG_E_NOMEM; }
+    }
+    HybridState *h = p->hyb;
+    std::lock_guard<std::mutex> lock(h->mu);
+    while (count > 0) {
+        const uint64_t now = count < kPiece ? count : kPiece;
+        awg_status st = piece(p, h, method, n0, now, out_i16, out_f32, s);
+        if (st != AWG_OK) return st;
+        n0 += now;
+        count -= now;
+        if (out_i16) out_i16 += now;
+        if (out_f32) out_f32 += now;
+    }
+    return AWG_OK;
+}
+
+}  // namespace awg

@@ -16,9 +16,17 @@
 // 1 KB: A[kb][rb][lane][e] with row = rb*32 + lane%32 and inner index
 // kb*16 + 8*(lane/32) + e; B likewise with columns. Inner index 2k is the sine
 // (A) / cosine (B) of tone k, 2k+1 the cosine (A) / sine (B).
+//
+// Ramped plans (hybrid path): over a row of M samples a tone whose ramp window
+// misses the row is on one of its two lines (before or after the window), so
+// the same product serves it. The operands are then built from a list of line
+// entries (tone, which line, and the rows the entry covers); a row outside an
+// entry's rows gets a zero amplitude, and the direct kernel adds the tones
+// that ramp inside the row.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -69,9 +77,37 @@ template <> struct Split<__bf16> {
     }
 };
 
-// A operand: one thread per (row c, group g of 4 tones) -> 8 inner values.
+// Line entry of the hybrid path (kLineShift, kLine*): pre / post: the line
+// before / after the window on every row; split-pre: the line before the window
+// on the rows that end before the window opens; split-post: the line after the
+// window on the rows that start after it closes.
+
+// Line (P, F) of entry e on the row [first, first + mcols - 1]; false when the
+// entry does not cover the row. entries == nullptr: entry e is tone e's first line.
+__device__ __forceinline__ bool entry_line(const ToneDev *__restrict__ tones, const uint32_t *__restrict__ entries,
+                                           int32_t e, uint64_t first, uint64_t mcols, ToneDev &td)
+{
+    if (!entries) {
+        td = tones[e];
+        return true;
+    }
+    const uint32_t ent = entries[e];
+    const uint32_t mode = ent >> kLineShift;
+    td = tones[ent & ((1u << kLineShift) - 1)];
+    if (mode & 1u) {                      // a line after the window
+        td.p0 = td.p1;
+        td.f0 = td.f1;
+    }
+    if (mode == kLineSplitPre) return first + (mcols - 1) < td.a;
+    if (mode == kLineSplitPost) return first > td.a + td.n;
+    return true;
+}
+
+// A operand: one thread per (row c, group g of 4 entries) -> 8 inner values.
+// Entries are tones (entries == nullptr) or line entries.
 template <typename T>
-__global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
+__global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ tones,
+                                                    const uint32_t *__restrict__ entries, int32_t n_entries,
                                                     int32_t n_groups, uint64_t n0, uint64_t mcols,
                                                     int32_t rb_pad, T *__restrict__ a_hi, T *__restrict__ a_lo)
 {
@@ -86,8 +122,8 @@ __global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ 
     for (int t = 0; t < 4; ++t) {
         const int k = 4 * g + t;
         float xs = 0.0f, xc = 0.0f;
-        if (k < n_tones) {
-            const ToneDev td = tones[k];
+        ToneDev td;
+        if (k < n_entries && entry_line(tones, entries, k, n, mcols, td)) {
             float s, co;
             word_sincos(td.p0 - kPhaseBias + td.f0 * n, s, co);
             xs = td.amp * s;
@@ -104,9 +140,11 @@ __global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ 
     ((typename Split<T>::vec *)a_lo)[off] = lv;
 }
 
-// B operand: one thread per (column m, group g of 4 tones).
+// B operand: one thread per (column m, group g of 4 entries); the frequency
+// word of the entry's line (its rows do not matter here).
 template <typename T>
-__global__ __launch_bounds__(256) void gen_b_kernel(const ToneDev *__restrict__ tones, int32_t n_tones,
+__global__ __launch_bounds__(256) void gen_b_kernel(const ToneDev *__restrict__ tones,
+                                                    const uint32_t *__restrict__ entries, int32_t n_entries,
                                                     int32_t n_groups, int32_t cb_n, T *__restrict__ b_hi,
                                                     T *__restrict__ b_lo)
 {
@@ -120,9 +158,16 @@ __global__ __launch_bounds__(256) void gen_b_kernel(const ToneDev *__restrict__ 
     for (int t = 0; t < 4; ++t) {
         const int k = 4 * g + t;
         float xc = 0.0f, xs = 0.0f;
-        if (k < n_tones) {
-            const ToneDev td = tones[k];
-            word_sincos(td.f0 * (uint64_t)m, xs, xc);
+        if (k < n_entries) {
+            uint64_t F;
+            if (entries) {
+                const uint32_t ent = entries[k];
+                const ToneDev &td = tones[ent & ((1u << kLineShift) - 1)];
+                F = ((ent >> kLineShift) & 1u) ? td.f1 : td.f0;
+            } else {
+                F = tones[k].f0;
+            }
+            word_sincos(F * (uint64_t)m, xs, xc);
         }
         T h, l;
         Split<T>::run(xc, h, l); hv[2 * t] = h; lv[2 * t] = l;
@@ -168,10 +213,13 @@ constexpr int vmcnt_imm(int v) { return (v & 0xf) | ((v >> 4) << 14) | (0x7 << 4
 // memory into LDS (global_load_lds_dwordx4, lane i -> bytes 16i..16i+15 of a
 // fragment). NST LDS stages, prefetch distance NST-1: block kb+NST-1 is in
 // flight while block kb is multiplied. vmcnt counts the copies in issue order.
+// Split K: the grid's z index z sums k-blocks [z*kb_split, (z+1)*kb_split) and
+// writes its partial sums to plane z of the FP32 output (plane elements apart).
 template <typename T, bool F32OUT, int WR, int WC, int NST>
 __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
     const T *__restrict__ a_hi, const T *__restrict__ a_lo, const T *__restrict__ b_hi, const T *__restrict__ b_lo,
-    int32_t kb_n, int32_t rb_pad, int32_t cb_n, uint64_t mcols, uint64_t count, void *__restrict__ out)
+    int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split, uint64_t plane, uint64_t mcols, uint64_t count,
+    void *__restrict__ out)
 {
     typedef typename Split<T>::vec V;
     constexpr int W = WR * WC;
@@ -188,9 +236,13 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
     // that range in groups of 4 tile rows, column by column: every XCD then
     // works on a compact block of tiles and re-reads fewer operand rows and
     // columns from HBM into its own L2.
-    const uint32_t gx = gridDim.x, gy = gridDim.y, nt = gx * gy;
-    uint32_t b = blockIdx.y * gx + blockIdx.x;
-    if (nt % 8 == 0) b = (b % 8) * (nt / 8) + b / 8;
+    const uint32_t gx = gridDim.x, gy = gridDim.y, nt = gx * gy, nall = nt * gridDim.z;
+    uint32_t b = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+    if (nall % 8 == 0) b = (b % 8) * (nall / 8) + b / 8;
+    const uint32_t z = b / nt;                                  // split-K slice
+    b %= nt;
+    const int32_t kb_begin = (int32_t)z * kb_split;
+    const int32_t kb_cnt = max(0, min(kb_n - kb_begin, kb_split));
     const uint32_t grp = gy < 4 ? gy : 4;
     const uint32_t full = (gy / grp) * grp;                     // rows covered by whole groups
     uint32_t ty, tx;
@@ -210,7 +262,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
     const int opnd = f0 / 8;
     const T *gsrc = opnd == 0 ? a_hi : opnd == 1 ? a_lo : opnd == 2 ? b_hi : b_lo;
     const int64_t kb_stride = (int64_t)(opnd < 2 ? rb_pad : cb_n) * 512;
-    gsrc += ((int64_t)(opnd < 2 ? rb0 : cb0) + (f0 % 8)) * 512 + lane * 8;
+    gsrc += ((int64_t)(opnd < 2 ? rb0 : cb0) + (f0 % 8)) * 512 + lane * 8 + (int64_t)kb_begin * kb_stride;
     auto issue = [&](int kb) {
         const T *g = gsrc + (int64_t)kb * kb_stride;
         char *l = lds + (kb % NST) * kStage + f0 * kFragBytes;
@@ -229,14 +281,14 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
 
 #pragma unroll
     for (int s = 0; s < NST - 1; ++s)
-        if (s < kb_n) issue(s);
-    for (int kb = 0; kb < kb_n; ++kb) {
+        if (s < kb_cnt) issue(s);
+    for (int kb = 0; kb < kb_cnt; ++kb) {
         // own copies of block kb landed, then a bare barrier (no fence: later
         // blocks stay in flight) makes every wave's copies visible
-        if (kb + NST - 2 < kb_n) __builtin_amdgcn_s_waitcnt(vmcnt_imm(F * (NST - 2)));
+        if (kb + NST - 2 < kb_cnt) __builtin_amdgcn_s_waitcnt(vmcnt_imm(F * (NST - 2)));
         else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
         asm volatile("s_barrier" ::: "memory");
-        if (kb + NST - 1 < kb_n) issue(kb + NST - 1);
+        if (kb + NST - 1 < kb_cnt) issue(kb + NST - 1);
         const char *st = lds + (kb % NST) * kStage;
         const V *ah = (const V *)(st + 0 * kOperand) + TI * wr * 64 + lane;
         const V *al = (const V *)(st + 1 * kOperand) + TI * wr * 64 + lane;
@@ -276,7 +328,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
                 const uint64_t row = (uint64_t)(rb0 + TI * wr + i) * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const uint64_t rel = row * mcols + col;
                 if (rel < count) {
-                    if (F32OUT) ((float *)out)[rel] = acc[i][j][v];
+                    if (F32OUT) ((float *)out)[z * plane + rel] = acc[i][j][v];
                     else ((int16_t *)out)[rel] = to_i16(acc[i][j][v]);
                 }
             }
@@ -287,8 +339,8 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
 // Launch one GEMM variant (waves WR x WC, NST LDS stages).
 template <typename T, int WR, int WC, int NST>
 static hipError_t launch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *a_lo, const T *b_hi,
-                              const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, uint64_t mcols,
-                              uint64_t count, int16_t *out_i16, float *out_f32)
+                              const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
+                              uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32)
 {
     constexpr int kLds = NST * 4 * kTileRB * kFragBytes;
     static bool attr_set = false;
@@ -303,10 +355,10 @@ static hipError_t launch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *
     }
     if (out_f32)
         hipLaunchKernelGGL((angle_gemm_kernel<T, true, WR, WC, NST>), grid, dim3(64 * WR * WC), kLds, s, a_hi,
-                           a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, (void *)out_f32);
+                           a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_f32);
     else
         hipLaunchKernelGGL((angle_gemm_kernel<T, false, WR, WC, NST>), grid, dim3(64 * WR * WC), kLds, s, a_hi,
-                           a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, (void *)out_i16);
+                           a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_i16);
     return hipGetLastError();
 }
 
@@ -325,14 +377,14 @@ static int gemm_variant()
 
 template <typename T>
 static hipError_t dispatch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *a_lo, const T *b_hi,
-                                const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, uint64_t mcols,
-                                uint64_t count, int16_t *out_i16, float *out_f32)
+                                const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
+                                uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32)
 {
     switch (gemm_variant()) {
-    case 0: return launch_gemm<T, 2, 2, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
-    case 1: return launch_gemm<T, 2, 2, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
-    case 2: return launch_gemm<T, 2, 4, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
-    default: return launch_gemm<T, 2, 4, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
+    case 0: return launch_gemm<T, 2, 2, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
+    case 1: return launch_gemm<T, 2, 2, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
+    case 2: return launch_gemm<T, 2, 4, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
+    default: return launch_gemm<T, 2, 4, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
     }
 }
 
@@ -376,7 +428,8 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     {
         ProfScope prof(p->ctx, s, f16 ? "gen_a_kernel_f16" : "gen_a_kernel_bf16");
         hipLaunchKernelGGL((gen_a_kernel<T>), dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, s,
-                           p->d_tones, p->n_tones, 2 * kb_n, n0, mcols, rb_pad, a_hi, a_lo);
+                           p->d_tones, (const uint32_t *)nullptr, p->n_tones, 2 * kb_n, n0, mcols, rb_pad, a_hi,
+                           a_lo);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return hipst(e);
@@ -384,7 +437,7 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     if (p->mfma_b_key != b_key) {
         ProfScope prof(p->ctx, s, f16 ? "gen_b_kernel_f16" : "gen_b_kernel_bf16");
         hipLaunchKernelGGL((gen_b_kernel<T>), dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, s,
-                           p->d_tones, p->n_tones, 2 * kb_n, cb_n, b_hi, b_lo);
+                           p->d_tones, (const uint32_t *)nullptr, p->n_tones, 2 * kb_n, cb_n, b_hi, b_lo);
         e = hipGetLastError();
         if (e != hipSuccess) return hipst(e);
         p->mfma_b_key = b_key;
@@ -392,9 +445,74 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     dim3 grid((uint32_t)(cb_n / kTileCB), (uint32_t)(rb_pad / kTileRB));
     {
         ProfScope prof(p->ctx, s, f16 ? "angle_gemm_kernel_f16" : "angle_gemm_kernel_bf16");
-        e = dispatch_gemm<T>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, mcols, count, out_i16, out_f32);
+        e = dispatch_gemm<T>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_n, 0, mcols, count, out_i16,
+                             out_f32);
     }
     return hipst(e);
+}
+
+LinesGeom lines_geometry(int32_t n_entries, uint64_t count)
+{
+    constexpr int32_t kTargetGroups = 256;          // one 8-wave workgroup per CU
+    const uint64_t mcols = kTileSamples;
+    const uint64_t rows = (count + mcols - 1) / mcols;
+    LinesGeom g;
+    g.rb_pad = (int32_t)(((rows + 31) / 32 + kTileRB - 1) / kTileRB * kTileRB);
+    g.cb_n = (int32_t)(mcols / 32);
+    g.kb_n = (n_entries + 7) / 8;
+    const int32_t tiles = (g.rb_pad / kTileRB) * (g.cb_n / kTileCB);
+    int32_t gz = (kTargetGroups + tiles - 1) / tiles;
+    gz = std::max(1, std::min(gz, g.kb_n));
+    g.kb_split = (g.kb_n + gz - 1) / gz;
+    g.gz = g.kb_split > 0 ? (g.kb_n + g.kb_split - 1) / g.kb_split : 0;
+    g.plane = rows * mcols;
+    g.a_bytes = (size_t)g.kb_n * g.rb_pad * kFragBytes;
+    g.b_bytes = (size_t)g.kb_n * g.cb_n * kFragBytes;
+    g.plane_bytes = (size_t)g.gz * g.plane * sizeof(float);
+    return g;
+}
+
+template <typename T>
+static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_t *d_entries, int32_t n_entries,
+                            uint64_t n0, uint64_t count, char *w, hipStream_t s)
+{
+    const bool f16 = std::is_same<T, _Float16>::value;
+    T *b_hi = (T *)w, *b_lo = (T *)(w + g.b_bytes);
+    T *a_hi = (T *)(w + 2 * g.b_bytes), *a_lo = (T *)(w + 2 * g.b_bytes + g.a_bytes);
+    float *planes = (float *)(w + 2 * (g.a_bytes + g.b_bytes));
+    const uint64_t mcols = kTileSamples;
+    const int64_t a_threads = (int64_t)g.rb_pad * 32 * (2 * g.kb_n);
+    const int64_t b_threads = (int64_t)g.cb_n * 32 * (2 * g.kb_n);
+    hipError_t e;
+    {
+        ProfScope prof(p->ctx, s, f16 ? "hyb_gen_a_f16" : "hyb_gen_a_bf16");
+        hipLaunchKernelGGL((gen_a_kernel<T>), dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, s,
+                           p->d_tones, d_entries, n_entries, 2 * g.kb_n, n0, mcols, g.rb_pad, a_hi, a_lo);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    {
+        ProfScope prof(p->ctx, s, f16 ? "hyb_gen_b_f16" : "hyb_gen_b_bf16");
+        hipLaunchKernelGGL((gen_b_kernel<T>), dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, s,
+                           p->d_tones, d_entries, n_entries, 2 * g.kb_n, g.cb_n, b_hi, b_lo);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    dim3 grid((uint32_t)(g.cb_n / kTileCB), (uint32_t)(g.rb_pad / kTileRB), (uint32_t)g.gz);
+    ProfScope prof(p->ctx, s, f16 ? "hyb_gemm_f16" : "hyb_gemm_bf16");
+    return dispatch_gemm<T>(grid, s, a_hi, a_lo, b_hi, b_lo, g.kb_n, g.rb_pad, g.cb_n, g.kb_split, g.plane, mcols,
+                            count, nullptr, planes);
+}
+
+hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, const uint32_t *d_entries,
+                        int32_t n_entries, uint64_t n0, uint64_t count, void *d_work, hipStream_t s)
+{
+    if (g.gz <= 0 || n_entries <= 0) return hipSuccess;
+    if (method == AWG_F_METHOD_MFMA_F16X3)
+        return lines_run<_Float16>(p, g, d_entries, n_entries, n0, count, (char *)d_work, s);
+    if (method == AWG_F_METHOD_MFMA_BF16X3)
+        return lines_run<__bf16>(p, g, d_entries, n_entries, n0, count, (char *)d_work, s);
+    return hipErrorInvalidValue;
 }
 
 awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,

@@ -61,8 +61,8 @@ struct Job {
     size_t off, bytes;           // arena block
     ToneDev *d_tones;
     const uint64_t **d_tabs;
-    uint8_t *d_uniform;
-    int32_t n_tones, slice, is_static;
+    Block *d_blocks;
+    int32_t n_tones, is_static;
     uint64_t n_samples, next_n0;
     uint32_t chunks_total, chunks_done;
     bool in_flight;
@@ -164,7 +164,7 @@ void pool_free(awg_server *s, size_t off, size_t bytes)
 size_t job_bytes(const awg_plan *p)
 {
     return align_up(sizeof(ToneDev) * (size_t)p->n_tones) + align_up(sizeof(uint64_t *) * (p->table_ptrs.size() + 1)) +
-           align_up(p->uniform.size());
+           align_up(sizeof(Block) * p->blocks.size());
 }
 
 // Admit queued jobs in order while a job slot and arena space are available.
@@ -181,9 +181,8 @@ void admit(awg_server *s)
         char *base = s->d_arena + s->pool_off + off;
         j.d_tones = (ToneDev *)base;
         j.d_tabs = (const uint64_t **)(base + align_up(sizeof(ToneDev) * (size_t)pd.plan->n_tones));
-        j.d_uniform = (uint8_t *)((char *)j.d_tabs + align_up(sizeof(uint64_t *) * (pd.plan->table_ptrs.size() + 1)));
+        j.d_blocks = (Block *)((char *)j.d_tabs + align_up(sizeof(uint64_t *) * (pd.plan->table_ptrs.size() + 1)));
         j.n_tones = pd.plan->n_tones;
-        j.slice = pd.plan->slice;
         j.is_static = pd.plan->n_ramped == 0;
         j.n_samples = pd.n_samples;
         j.next_n0 = 0;
@@ -200,8 +199,8 @@ void admit(awg_server *s)
             e = hipMemcpyAsync(j.d_tabs, pd.plan->table_ptrs.data(), sizeof(uint64_t *) * nt,
                                hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(j.d_uniform, pd.plan->uniform.data(), pd.plan->uniform.size(), hipMemcpyHostToDevice,
-                               s->stream);
+            e = hipMemcpyAsync(j.d_blocks, pd.plan->blocks.data(), sizeof(Block) * pd.plan->blocks.size(),
+                               hipMemcpyHostToDevice, s->stream);
         if (e != hipSuccess) { s->error = hipst(e); pool_free(s, off, bytes); break; }
         s->jobs[j.id] = j;
         s->pending.pop_front();
@@ -284,9 +283,9 @@ bool launch_step(awg_server *s)
         b.count = count;
         b.tile_begin = tiles;
         b.n_tones = j.n_tones;
-        b.slice = j.slice;
+        b.pad = 0;
         b.is_static = j.is_static;
-        b.uniform = j.d_uniform;
+        b.blocks = j.d_blocks;
         tiles += (uint32_t)((count + kTileSamples - 1) / kTileSamples);
         st->items.push_back(StepItem{j.id, slot, j.next_n0, count, (uint32_t)(j.next_n0 / s->prm.chunk_len)});
         s->slot_state[slot] = 1;

@@ -204,26 +204,56 @@ ToneDev to_device(const ToneHost &t, uint16_t table)
     return d;
 }
 
-// For wave w and block i of its slice (tones w*slice + 32i .. +31, clipped to
-// the slice and the list): 1 when all those tones have the same shape, window
-// and table, so the kernel can take the block's regime from its first tone.
-void block_flags(const std::vector<ToneDev> &tones, int32_t slice, std::vector<uint8_t> *out)
+// Block table (see Block): maximal runs of tones with equal shape, window and
+// table (not crossing n_split) of at least kMinRun tones become uniform blocks,
+// ceil(L / kBlock) of them rounded up to a multiple of kWaves and sized within
+// one tone of each other; shorter runs are packed into mixed blocks of up to
+// kBlock tones.
+void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vector<Block> *out)
 {
+    constexpr int32_t kMinRun = 8;
     const int32_t n = (int32_t)tones.size();
-    const int32_t nbps = (slice + kBlock - 1) / kBlock;
-    out->assign((size_t)kWaves * nbps, 0);
-    for (int32_t w = 0; w < kWaves; ++w) {
-        const int32_t kb = w * slice, ke = std::min(n, kb + slice);
-        for (int32_t i = 0; i < nbps; ++i) {
-            const int32_t b = kb + i * kBlock, e = std::min(ke, b + kBlock);
-            bool same = b < e;
-            for (int32_t k = b + 1; k < e && same; ++k) {
-                const ToneDev &x = tones[b], &y = tones[k];
-                same = x.shape == y.shape && x.a == y.a && x.n == y.n && x.table == y.table;
+    out->clear();
+    out->push_back(Block{0, 0, 0});
+    auto same = [&](int32_t x, int32_t y) {
+        const ToneDev &a = tones[x], &b = tones[y];
+        return a.shape == b.shape && a.a == b.a && a.n == b.n && a.table == b.table &&
+               ((x < n_split) == (y < n_split));
+    };
+    int32_t mixed_begin = -1, mixed_count = 0;
+    uint16_t mixed_flags = 0;
+    auto flush = [&]() {
+        if (mixed_count > 0) out->push_back(Block{(uint32_t)mixed_begin, (uint16_t)mixed_count, mixed_flags});
+        mixed_begin = -1;
+        mixed_count = 0;
+    };
+    for (int32_t i = 0; i < n;) {
+        int32_t j = i + 1;
+        while (j < n && same(i, j)) ++j;
+        const int32_t L = j - i;
+        const uint16_t split = i < n_split ? kBlockSplit : 0;
+        if (L >= kMinRun) {
+            flush();
+            int32_t nb = (L + kBlock - 1) / kBlock;
+            nb = (nb + kWaves - 1) / kWaves * kWaves;
+            const int32_t base = L / nb, extra = L % nb;
+            int32_t b = i;
+            for (int32_t q = 0; q < nb; ++q) {
+                const int32_t c = base + (q < extra ? 1 : 0);
+                out->push_back(Block{(uint32_t)b, (uint16_t)c, (uint16_t)(kBlockUniform | split)});
+                b += c;
             }
-            (*out)[(size_t)w * nbps + i] = same ? 1 : 0;
+        } else {
+            for (int32_t k = i; k < j; ++k) {
+                if (mixed_count > 0 && (mixed_count == kBlock || mixed_flags != split)) flush();
+                if (mixed_count == 0) { mixed_begin = k; mixed_flags = split; }
+                ++mixed_count;
+            }
         }
+        i = j;
     }
+    flush();
+    (*out)[0].begin = (uint32_t)(out->size() - 1);
 }
 
 }  // namespace awg

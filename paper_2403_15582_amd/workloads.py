@@ -192,6 +192,45 @@ def config5(seed=5, rate_hz=2000.0, seconds=2.0, kmin=50, kmax=2000,
     return jobs
 
 
+def row_edges(seed=12, n0=3 * CHUNK + 12345, rows=70, tail=37, K_static=192, per=6, fs_hz=FS_280):
+    """Ramped tones whose windows sit on the edges of the 1024-sample rows that
+    start at n0 (a window opening on a row's last sample or the next one,
+    closing on a row's first sample or the one before, inside one row, before
+    n0, past the range, over the whole range, entirely before / after it), each
+    edge case carried by ``per`` tones of cycling shapes, plus ``K_static``
+    static tones. The range is n0 .. n0 + 1024 rows + tail (ragged)."""
+    R = 1024
+    count = rows * R + tail
+    specs = [
+        (n0 + 5 * R + R - 1, 10 * R),            # opens on row 5's last sample
+        (n0 + 6 * R, 10 * R - 1),                # opens on row 6's first, closes on row 16's first - 1
+        (n0 + 20 * R - 1, 3 * R + 1),            # closes on row 23's first sample
+        (n0 + 30 * R + 100, 500),                # inside one row
+        (n0 - 5000, 8 * R),                      # opened before the range
+        (n0 + count - 3000, 40000),              # still open after the range
+        (n0 - 10, count + 100),                  # covers the whole range
+        (n0 + 2 * R, count - 3 * R),             # few line rows: direct only
+        (n0 - 30000, 20000),                     # closed before the range
+        (n0 + count + 10, 5000),                 # opens after the range
+        (n0 + 40 * R + 1, 1),                    # one-sample window
+    ]
+    r = _rng(seed)
+    K = K_static + per * len(specs)
+    f0, f1 = _chirp_ends(r, K, 0.05 * fs_hz, 0.45 * fs_hz, 0.02 * fs_hz)
+    t = static_tones(f0, r.uniform(0.2, 1.0, K), r.random(K))
+    shapes = [RAMP_LINEAR, RAMP_COSINE, RAMP_MINJERK]
+    for i, (a, n) in enumerate(specs):
+        for j in range(per):
+            k = K_static + i * per + j
+            t[k]["f_end_hz"] = f1[k]
+            t[k]["ramp"] = shapes[(i + j) % 3]
+            t[k]["ramp_start"] = a
+            t[k]["ramp_len"] = n
+    # interleave the ramped tones among the static ones (device order is sorted anyway)
+    t = t[r.permutation(K)]
+    return Workload("row-edges", fs_hz, 0.0, 0, t, n0, count)
+
+
 def small_mixed(seed=11, K=24, fs_hz=FS_280, n_total=5000, period_log2=0):
     """Small tone set covering every ramp shape and regime (pre / in / post
     window, windows straddling tile edges, rising and falling chirps), for
