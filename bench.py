@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--legs", default="stream,arrays,serve",
                     help="comma list of extra legs to run: stream, arrays, serve")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--arrays-tones", default="5000,10000", help="tone counts of the large-array leg")
+    ap.add_argument("--arrays-methods", default="direct,mfma-f16,mfma-bf16", help="methods of the large-array leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -340,8 +342,8 @@ def main():
         res["streaming"] = streaming_leg(torch, awg, W)
     if "arrays" in legs:
         log("large-array legs ...")
-        res["large_arrays"] = [large_array_leg(torch, awg, W, K, m) for K in (5000, 10000)
-                               for m in ("direct", "mfma-f16", "mfma-bf16")]
+        res["large_arrays"] = [large_array_leg(torch, awg, W, int(K), m) for K in a.arrays_tones.split(",")
+                               for m in a.arrays_methods.split(",")]
     if "serve" in legs:
         log("serving leg ...")
         res["serving"] = serving_leg(W, a.serve_seconds)

@@ -212,6 +212,23 @@ awg_status awg_stream_tell(const awg_plan *plan, uint64_t *n0);
 awg_status awg_synth_f32(awg_plan *plan, uint32_t method, uint64_t n0, uint64_t count,
                          float *d_y, void *hip_stream);
 
+/* Multiplexed output for a multi-channel DAC (the paper's wavetable
+ * multiplexer, fused into synthesis as in its Streaming pathway): samples
+ * n0 .. n0+count-1 of plans[0 .. n_channels-1] (1 <= n_channels <= 4) written
+ * interleaved into d_out, channel c's sample n0 + i at d_out[n_channels * i + c]
+ * (d_out holds n_channels * count int16). Every channel runs the direct kernel,
+ * so its codes are bit-identical to awg_synth_chirp of that plan with the direct
+ * method; one launch covers all channels. A plan may appear more than once.
+ * AWG_E_INVALID for a bad channel count, a NULL or host-only plan, or plans of
+ * different devices; AWG_E_RANGE as awg_synth_chirp. */
+awg_status awg_synth_multiplex(awg_plan *const *plans, int32_t n_channels, uint64_t n0, uint64_t count,
+                               int16_t *d_out, void *hip_stream);
+/* Streaming form: the next count samples of every channel after their common
+ * cursor (all plans' cursors must be equal, else AWG_E_INVALID), multiplexed as
+ * above; then every plan's cursor advances by count. */
+awg_status awg_stream_next_multiplex(awg_plan *const *plans, int32_t n_channels, uint64_t count,
+                                     int16_t *d_out, void *hip_stream, uint64_t *n0_out);
+
 /* Phase words of one tone as the direct kernel generates them (same code path,
  * same sample-to-lane mapping), for exact comparison: d_words[i] = phi(n0 + i). */
 awg_status awg_phase_dump(awg_plan *plan, int32_t tone, uint64_t n0, uint64_t count,

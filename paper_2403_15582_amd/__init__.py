@@ -29,7 +29,8 @@ EXPORTED = [
     "awg_ctx_create", "awg_ctx_destroy", "awg_plan_tones", "awg_plan_destroy",
     "awg_plan_info_get", "awg_plan_words", "awg_ramp_table", "awg_plan_retune",
     "awg_synth_static", "awg_synth_chirp", "awg_stream_next", "awg_stream_seek",
-    "awg_stream_tell", "awg_synth_f32", "awg_phase_dump", "awg_strerror", "awg_version",
+    "awg_stream_tell", "awg_synth_f32", "awg_synth_multiplex", "awg_stream_next_multiplex",
+    "awg_phase_dump", "awg_strerror", "awg_version",
     "awg_profile_enable", "awg_profile_read",
     "awg_server_create", "awg_server_destroy", "awg_server_submit", "awg_server_poll",
     "awg_server_slot", "awg_server_read", "awg_server_release", "awg_server_stats_get",
@@ -135,6 +136,8 @@ def lib():
         "awg_stream_seek": ([_VP, _U64], _I32),
         "awg_stream_tell": ([_VP, ctypes.POINTER(_U64)], _I32),
         "awg_synth_f32": ([_VP, ctypes.c_uint32, _U64, _U64, _VP, _VP], _I32),
+        "awg_synth_multiplex": ([ctypes.POINTER(_VP), _I32, _U64, _U64, _VP, _VP], _I32),
+        "awg_stream_next_multiplex": ([ctypes.POINTER(_VP), _I32, _U64, _VP, _VP, ctypes.POINTER(_U64)], _I32),
         "awg_phase_dump": ([_VP, _I32, _U64, _U64, _VP, _VP], _I32),
         "awg_profile_enable": ([_VP, _I32], _I32),
         "awg_profile_read": ([_VP, ctypes.POINTER(awg_kernel_stat), _I32, ctypes.POINTER(_I32), _I32], _I32),
@@ -263,6 +266,38 @@ def awg_stream_tell(plan):
 def awg_synth_f32(plan, method, n0, count, d_y, stream=0):
     _check(lib().awg_synth_f32(plan, int(method), int(n0), int(count), d_y, stream or None),
            "awg_synth_f32")
+
+
+def _plan_array(plans):
+    arr = (_VP * max(1, len(plans)))()
+    for i, p in enumerate(plans):
+        arr[i] = p
+    return arr
+
+
+def awg_synth_multiplex(plans, n0, count, d_out, stream=0):
+    """plans: list of plan handles (1..4 channels); d_out holds len(plans)*count int16."""
+    _check(lib().awg_synth_multiplex(_plan_array(plans), len(plans), int(n0), int(count), d_out, stream or None),
+           "awg_synth_multiplex")
+
+
+def awg_stream_next_multiplex(plans, count, d_out, stream=0):
+    n0 = _U64()
+    _check(lib().awg_stream_next_multiplex(_plan_array(plans), len(plans), int(count), d_out, stream or None,
+                                           ctypes.byref(n0)), "awg_stream_next_multiplex")
+    return n0.value
+
+
+def multiplex(plans, n0, count, out=None, stream=None):
+    """Channels of `plans` (Plan objects) interleaved into an int16 tensor of
+    shape (count, len(plans)): out[i, c] is channel c's sample n0 + i."""
+    import torch
+    if out is None:
+        out = torch.empty((int(count), len(plans)), dtype=torch.int16, device="cuda:%d" % plans[0].device)
+    assert out.dtype == torch.int16 and out.is_contiguous() and out.numel() >= count * len(plans)
+    awg_synth_multiplex([p.handle for p in plans], n0, count, out.data_ptr(),
+                        (stream or torch.cuda.current_stream()).cuda_stream)
+    return out
 
 
 def awg_phase_dump(plan, tone, n0, count, d_words, stream=0):

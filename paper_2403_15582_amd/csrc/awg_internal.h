@@ -72,7 +72,8 @@ struct BatchItem {
     void *out;               // int16 output of this chunk
     uint64_t n0, count;      // absolute first sample, samples in the chunk
     uint32_t tile_begin;     // first tile of this item in the launch
-    int32_t n_tones, pad;
+    int32_t n_tones;
+    int32_t out_stride;      // output elements between consecutive samples (1: contiguous)
     int32_t is_static;       // 1: no tone has a window
     const Block *blocks;     // the plan's block table
 };
@@ -194,6 +195,10 @@ hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint6
 hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n,
                                 hipStream_t s);
 hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint32_t grid, hipStream_t s);
+// Multiplexed channels: items[c] (c < n, n <= kMaxChannels) each cover the same
+// count samples; one launch, items passed by value.
+constexpr int kMaxChannels = 4;
+hipError_t launch_mux(const BatchItem *items, int32_t n, uint64_t count, hipStream_t s);
 // MFMA static synthesis; out_i16 or out_f32 (exactly one non-null).
 awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count,
                        int16_t *out_i16, float *out_f32, hipStream_t s);

@@ -575,6 +575,55 @@ awg_status awg_stream_tell(const awg_plan *p, uint64_t *n0)
     return AWG_OK;
 }
 
+static awg_status mux_items(awg_plan *const *plans, int32_t n, uint64_t n0, uint64_t count, int16_t *d_out,
+                            BatchItem *items)
+{
+    if (!plans || n < 1 || n > kMaxChannels) return AWG_E_INVALID;
+    for (int32_t c = 0; c < n; ++c) {
+        awg_plan *p = plans[c];
+        if (!p || !p->ctx || p->ctx->device != plans[0]->ctx->device) return AWG_E_INVALID;
+        BatchItem &b = items[c];
+        b.tones = p->d_tones;
+        b.tables = p->d_table_ptrs;
+        b.out = d_out + c;
+        b.n0 = n0;
+        b.count = count;
+        b.tile_begin = 0;
+        b.n_tones = p->n_tones;
+        b.out_stride = n;
+        b.is_static = p->n_ramped == 0;
+        b.blocks = p->d_blocks;
+    }
+    return device_ready(plans[0]);
+}
+
+awg_status awg_synth_multiplex(awg_plan *const *plans, int32_t n_channels, uint64_t n0, uint64_t count,
+                               int16_t *d_out, void *hip_stream)
+{
+    BatchItem items[kMaxChannels];
+    awg_status st = mux_items(plans, n_channels, n0, count, d_out, items);
+    if (st != AWG_OK) return st;
+    if ((st = check_range(n0, count)) != AWG_OK) return st;
+    if (count == 0) return AWG_OK;
+    if (!d_out) return AWG_E_INVALID;
+    ProfScope prof(plans[0]->ctx, (hipStream_t)hip_stream, "mux_kernel");
+    return hip_status(launch_mux(items, n_channels, count, (hipStream_t)hip_stream));
+}
+
+awg_status awg_stream_next_multiplex(awg_plan *const *plans, int32_t n_channels, uint64_t count, int16_t *d_out,
+                                     void *hip_stream, uint64_t *n0_out)
+{
+    if (!plans || n_channels < 1 || n_channels > kMaxChannels || !plans[0]) return AWG_E_INVALID;
+    const uint64_t n0 = plans[0]->cursor;
+    for (int32_t c = 0; c < n_channels; ++c)
+        if (!plans[c] || plans[c]->cursor != n0) return AWG_E_INVALID;
+    awg_status st = awg_synth_multiplex(plans, n_channels, n0, count, d_out, hip_stream);
+    if (st != AWG_OK) return st;
+    for (int32_t c = 0; c < n_channels; ++c) plans[c]->cursor = n0 + count;   // repeated plans: same value
+    if (n0_out) *n0_out = n0;
+    return AWG_OK;
+}
+
 awg_status awg_phase_dump(awg_plan *p, int32_t tone, uint64_t n0, uint64_t count, uint64_t *d_words,
                           void *hip_stream)
 {

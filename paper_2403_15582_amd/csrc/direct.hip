@@ -212,7 +212,7 @@ template <int S, bool F32OUT, bool STATIC, bool HYB = false>
 __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, const Block *__restrict__ blocks,
                                            const uint64_t *const *__restrict__ tables, uint64_t tile0,
                                            uint32_t valid, void *__restrict__ out, float (*part)[kLanes * S],
-                                           const HybridIn &hyb = HybridIn{0, nullptr, 0})
+                                           const HybridIn &hyb = HybridIn{0, nullptr, 0}, uint32_t ostride = 1)
 {
     constexpr int T = kLanes * S;                 // samples per tile
     const uint32_t lane = threadIdx.x & 63u;
@@ -369,8 +369,8 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
         float y = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
         if (HYB && hyb.n_add > 0) y = g[e] + y;
         if (i < valid) {
-            if (F32OUT) ((float *)out)[i] = y;
-            else ((int16_t *)out)[i] = quantise(y);
+            if (F32OUT) ((float *)out)[(size_t)i * ostride] = y;
+            else ((int16_t *)out)[(size_t)i * ostride] = quantise(y);
         }
     }
     __syncthreads();
@@ -436,12 +436,38 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem *__restrict_
         const uint64_t rel = (uint64_t)(t - it.tile_begin) * T;
         const uint64_t left = it.count - rel;
         const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
-        int16_t *o = (int16_t *)it.out + rel;
+        const uint32_t st = (uint32_t)it.out_stride;
+        int16_t *o = (int16_t *)it.out + rel * st;
         if (it.is_static)
-            synth_tile<S, false, true>(it.tones, it.blocks, it.tables, it.n0 + rel, valid, o, part);
+            synth_tile<S, false, true>(it.tones, it.blocks, it.tables, it.n0 + rel, valid, o, part, HybridIn{0, nullptr, 0}, st);
         else
-            synth_tile<S, false, false>(it.tones, it.blocks, it.tables, it.n0 + rel, valid, o, part);
+            synth_tile<S, false, false>(it.tones, it.blocks, it.tables, it.n0 + rel, valid, o, part, HybridIn{0, nullptr, 0}, st);
     }
+}
+
+// Multiplexed output (the paper's wavetable multiplexer fused into synthesis):
+// channel c = blockIdx.y writes sample i of its range to out_c[i * out_stride],
+// with out_c = base + c and out_stride = the channel count, so one buffer holds
+// groups of one sample per channel. Same tile code as the direct kernel.
+struct MuxArgs {
+    BatchItem items[kMaxChannels];
+};
+
+template <int S>
+__global__ __launch_bounds__(256) void mux_kernel(MuxArgs args)
+{
+    constexpr int T = kLanes * S;
+    __shared__ float part[kWaves][T];
+    const BatchItem &it = args.items[blockIdx.y];
+    const uint64_t rel = (uint64_t)blockIdx.x * T;
+    const uint64_t left = it.count - rel;
+    const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
+    const uint32_t st = (uint32_t)it.out_stride;
+    int16_t *o = (int16_t *)it.out + rel * st;
+    if (it.is_static)
+        synth_tile<S, false, true>(it.tones, it.blocks, it.tables, it.n0 + rel, valid, o, part, HybridIn{0, nullptr, 0}, st);
+    else
+        synth_tile<S, false, false>(it.tones, it.blocks, it.tables, it.n0 + rel, valid, o, part, HybridIn{0, nullptr, 0}, st);
 }
 
 template <int S>
@@ -559,6 +585,29 @@ hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint
 {
     hipLaunchKernelGGL(batch_kernel<kS>, dim3(grid), dim3(256), 0, s, d_items, d_header);
     return hipGetLastError();
+}
+
+hipError_t launch_mux(const BatchItem *items, int32_t n, uint64_t count, hipStream_t s)
+{
+    constexpr uint64_t T = kLanes * kS;
+    if (n < 1 || n > kMaxChannels) return hipErrorInvalidValue;
+    MuxArgs args;
+    for (int c = 0; c < n; ++c) args.items[c] = items[c];
+    while (count > 0) {
+        const uint64_t tiles = (count + T - 1) / T;
+        const uint64_t now_tiles = tiles < kMaxTilesPerLaunch ? tiles : kMaxTilesPerLaunch;
+        const uint64_t now = now_tiles * T < count ? now_tiles * T : count;
+        for (int c = 0; c < n; ++c) args.items[c].count = now;
+        hipLaunchKernelGGL(mux_kernel<kS>, dim3((uint32_t)now_tiles, (uint32_t)n), dim3(256), 0, s, args);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        count -= now;
+        for (int c = 0; c < n; ++c) {
+            args.items[c].n0 += now;
+            args.items[c].out = (int16_t *)args.items[c].out + now * (uint64_t)args.items[c].out_stride;
+        }
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n, hipStream_t s)

@@ -283,7 +283,7 @@ bool launch_step(awg_server *s)
         b.count = count;
         b.tile_begin = tiles;
         b.n_tones = j.n_tones;
-        b.pad = 0;
+        b.out_stride = 1;
         b.is_static = j.is_static;
         b.blocks = j.d_blocks;
         tiles += (uint32_t)((count + kTileSamples - 1) / kTileSamples);
