@@ -25,9 +25,16 @@ class _Ramp(ctypes.Structure):
                 ("shape", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+class _Amp(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_uint64), ("m", ctypes.c_uint64),
+                ("a_from", ctypes.c_double), ("a_to", ctypes.c_double),
+                ("shape", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class _Tone(ctypes.Structure):
     _fields_ = [("p0", ctypes.c_uint64), ("f0", ctypes.c_uint64), ("amp", ctypes.c_double),
-                ("first_ramp", ctypes.c_int32), ("n_ramps", ctypes.c_int32)]
+                ("first_ramp", ctypes.c_int32), ("n_ramps", ctypes.c_int32),
+                ("first_amp", ctypes.c_int32), ("n_amps", ctypes.c_int32)]
 
 
 def build(force=True):
@@ -50,15 +57,17 @@ def _load():
         build(force=False)
         lib = ctypes.CDLL(_LIB)
         lib.oracle_synth.argtypes = [ctypes.POINTER(_Tone), ctypes.c_int32, ctypes.POINTER(_Ramp),
-                                     ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.POINTER(_Amp), ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_int32]
         lib.oracle_synth.restype = None
         lib.oracle_phases.argtypes = [ctypes.POINTER(_Tone), ctypes.POINTER(_Ramp), ctypes.c_uint64,
                                       ctypes.c_int64, ctypes.c_void_p]
         lib.oracle_phases.restype = None
         lib.oracle_synth_at.argtypes = [ctypes.POINTER(_Tone), ctypes.c_int32, ctypes.POINTER(_Ramp),
-                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.POINTER(_Amp), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_int32]
+        lib.oracle_amp_at.argtypes = [ctypes.POINTER(_Tone), ctypes.POINTER(_Amp), ctypes.c_uint64]
+        lib.oracle_amp_at.restype = ctypes.c_double
         lib.oracle_synth_at.restype = None
         _lib = lib
     return _lib
@@ -69,13 +78,21 @@ class Packed:
 
     def __init__(self, plan):
         n_ramps = sum(len(t.ramps) for t in plan.tones)
+        n_amps = sum(len(t.amp_ramps) for t in plan.tones)
         self.tones = (_Tone * max(1, len(plan.tones)))()
         self.ramps = (_Ramp * max(1, n_ramps))()
+        self.amps = (_Amp * max(1, n_amps))()
         self.keep = []
         j = 0
+        i = 0
         for k, t in enumerate(plan.tones):
             ct = self.tones[k]
             ct.p0, ct.f0, ct.amp = t.p0, t.f0, t.amp
+            ct.first_amp, ct.n_amps = i, len(t.amp_ramps)
+            for r in t.amp_ramps:
+                ca = self.amps[i]
+                ca.b, ca.m, ca.a_from, ca.a_to, ca.shape = r.b, r.M, r.a_from, r.a_to, r.shape
+                i += 1
             ct.first_ramp, ct.n_ramps = j, len(t.ramps)
             for r in t.ramps:
                 cr = self.ramps[j]
@@ -98,7 +115,7 @@ def synth(plan, n0, count, threads=0, packed=None):
     pk = packed if packed is not None else Packed(plan)
     q = np.empty(int(count), dtype=np.int16)
     y = np.empty(int(count), dtype=np.float64)
-    lib.oracle_synth(pk.tones, pk.n_tones, pk.ramps, int(n0), int(count),
+    lib.oracle_synth(pk.tones, pk.n_tones, pk.ramps, pk.amps, int(n0), int(count),
                      q.ctypes.data, y.ctypes.data, int(threads))
     return q, y
 
@@ -110,7 +127,7 @@ def synth_at(plan, ns, threads=0, packed=None):
     ns = np.ascontiguousarray(ns, dtype=np.uint64)
     q = np.empty(len(ns), dtype=np.int16)
     y = np.empty(len(ns), dtype=np.float64)
-    lib.oracle_synth_at(pk.tones, pk.n_tones, pk.ramps, ns.ctypes.data, len(ns),
+    lib.oracle_synth_at(pk.tones, pk.n_tones, pk.ramps, pk.amps, ns.ctypes.data, len(ns),
                         q.ctypes.data, y.ctypes.data, int(threads))
     return q, y
 
@@ -139,6 +156,14 @@ def sparse_tables(plan, ns):
                 have.update(need)
             r.table = tab
             r.sparse = True
+
+
+def amps_at(plan, k, ns, packed=None):
+    """Amplitude of tone k at the absolute samples ``ns`` from the C evaluator."""
+    lib = _load()
+    pk = packed if packed is not None else Packed(plan)
+    tone = ctypes.pointer(pk.tones[k])
+    return np.array([lib.oracle_amp_at(tone, pk.amps, int(n)) for n in ns], dtype=np.float64)
 
 
 def phases(plan, k, n0, count, packed=None):

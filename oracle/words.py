@@ -189,12 +189,73 @@ class Ramp:
         return (self.coef * self.table_at(d)) >> TABLE_SHIFT
 
 
+def amp_shape(shape, tau):
+    """Normalised amplitude profile s(tau) on [0, 1], s(0) = 0, s(1) = 1.
+
+    The paper lets every dynamic tone carry a time-dependent amplitude a_j[i]
+    (Eq. (5)) without fixing its form; the reading taken here reuses the
+    normalised profiles of the frequency ramps: linear tau, raised cosine
+    (1 - cos(pi tau)) / 2, and minimum jerk 10 tau^3 - 15 tau^4 + 6 tau^5 (the
+    position profile whose integral gives Eq. (8)'s phase).
+    """
+    tau = float(tau)
+    if shape == RAMP_LINEAR:
+        return tau
+    if shape == RAMP_COSINE:
+        return (1.0 - math.cos(math.pi * tau)) / 2.0
+    if shape == RAMP_MINJERK:
+        return tau ** 3 * (10.0 - 15.0 * tau + 6.0 * tau * tau)
+    raise ValueError("bad amplitude ramp shape")
+
+
+class AmpRamp:
+    """One amplitude ramp of a tone: from a_from to a_to over the window [b, b+M]."""
+
+    def __init__(self, b, M, shape, a_from, a_to):
+        if not 1 <= M < (1 << 31):
+            raise ValueError("amplitude ramp length must be in [1, 2**31)")
+        amp_shape(shape, 0.0)                  # validates the shape
+        self.b, self.M, self.shape = int(b), int(M), int(shape)
+        self.a_from, self.a_to = float(a_from), float(a_to)
+
+    def at(self, d):
+        """Amplitude d samples into the window (0 <= d <= M), FP64:
+        a_from (1 - s) + a_to s, exact at both ends."""
+        s = amp_shape(self.shape, Fraction(d, self.M))
+        return self.a_from * (1.0 - s) + self.a_to * s
+
+
 class ToneWords:
     """All words of one tone: the initial line and its ramps, in time order."""
 
     def __init__(self, p0, f0, amp):
         self.p0, self.f0, self.amp = p0, f0, float(amp)
         self.ramps = []
+        self.amp_ramps = []
+
+    def add_amp_ramp(self, b, M, shape, a_to):
+        """Append an amplitude ramp from the tone's current amplitude to a_to."""
+        a_from = self.amp_ramps[-1].a_to if self.amp_ramps else self.amp
+        free_from = self.amp_ramps[-1].b + self.amp_ramps[-1].M if self.amp_ramps else 0
+        if b < free_from:
+            raise ValueError("amplitude ramps of one tone must not overlap")
+        self.amp_ramps.append(AmpRamp(b, M, shape, a_from, a_to))
+
+    def amp_at(self, n):
+        """Amplitude A_k G at absolute sample n (the a_j[i] of Eq. (5))."""
+        n = int(n)
+        r = None
+        for cand in self.amp_ramps:
+            if cand.b <= n:
+                r = cand
+            else:
+                break
+        if r is None:
+            return self.amp
+        d = n - r.b
+        if d <= r.M:
+            return r.at(d)
+        return r.a_to
 
     def current_line(self):
         if self.ramps:
@@ -257,19 +318,25 @@ class Plan:
         f_to = tuning_word(f_end_hz, self.fs_hz, self.period_log2)
         self.tones[k].add_ramp(a, N, shape, f_to, self.table(shape, N))
 
+    def add_amp_ramp(self, k, b, M, shape, amplitude_end):
+        """Ramp tone k's amplitude to ``amplitude_end`` (in units of the gain, as
+        the tone amplitudes) over [b, b+M]; 0 switches the tone off."""
+        self.tones[k].add_amp_ramp(b, M, shape, float(amplitude_end) * self.gain)
+
     def phase_at(self, k, n):
         return self.tones[k].phase_at(n)
 
     def y_at(self, n):
-        """Unquantised sample y[n] = sum_k A_k G sin(2 pi phi_k(n) / 2**64), FP64.
+        """Unquantised sample y[n] = sum_k a_k(n) sin(2 pi phi_k(n) / 2**64), FP64.
 
-        The discretised sum of Eqs. (2)-(3) and (5)-(7); math.fsum makes the
-        sum exactly rounded so the tone order does not matter.
+        The discretised sum of Eqs. (2)-(3) and (5)-(7), a_k(n) = A_k G unless
+        the tone has amplitude ramps; math.fsum makes the sum exactly rounded
+        so the tone order does not matter.
         """
         terms = []
         for tw in self.tones:
             t = to_signed64(tw.phase_at(n)) / TWO64
-            terms.append(tw.amp * math.sin(2.0 * math.pi * t))
+            terms.append(tw.amp_at(n) * math.sin(2.0 * math.pi * t))
         return math.fsum(terms)
 
     def synth_points(self, ns):

@@ -5,6 +5,7 @@ index, a swapped operand, a wrong rounding) or compiles a mutated copy of
 oracle/synth.c, then runs the pin tests that should notice and asserts that at
 least one of them fails. Nothing here touches the library or a GPU.
 """
+import math
 import subprocess
 from fractions import Fraction
 
@@ -18,6 +19,9 @@ WORD_PINS = [pins.test_eq4_bin_error_matches_paper, pins.test_tuning_word_closed
 CHIRP_PINS = [pins.test_linear_chirp_matches_continuous_phase, pins.test_minjerk_matches_eq8_as_printed,
               pins.test_minjerk_end_phase_golden, pins.test_cosine_ramp_matches_continuous_phase,
               pins.test_all_shapes_share_end_phase, pins.test_retune_chain_is_continuous]
+AMP_PINS = [pins.test_amp_ramp_quarter_rate_closed_form, pins.test_amp_profile_values,
+            pins.test_amp_profile_invariants, pins.test_switched_off_tone_leaves_the_others,
+            pins.test_amp_ramp_chain_is_continuous]
 SUM_PINS = [pins.test_quarter_rate_tone_is_exact, pins.test_eighth_rate_tone,
             pins.test_static_tones_match_eq2_in_long_double, pins.test_dirichlet_kernel,
             pins.test_periodicity_with_bin_frequencies, pins.test_mean_power_and_default_gain,
@@ -25,10 +29,21 @@ SUM_PINS = [pins.test_quarter_rate_tone_is_exact, pins.test_eighth_rate_tone,
             pins.test_c_sum_equals_python_bigint]
 
 
+AMP_CASES = [(words.RAMP_LINEAR, 1024, 512, Fraction(1, 2)), (words.RAMP_COSINE, 768, 256, Fraction(1, 4)),
+             (words.RAMP_MINJERK, 1024, 256, Fraction(106, 1024))]
+
+
 def some_pin_fails(tests):
     for t in tests:
         try:
-            if "case" in t.__code__.co_varnames[:t.__code__.co_argcount]:
+            names = t.__code__.co_varnames[:t.__code__.co_argcount]
+            if "frac" in names:
+                for c in AMP_CASES:
+                    t(True, *c)
+            elif names == ("oracle_built", "shape"):
+                for s in (words.RAMP_LINEAR, words.RAMP_COSINE, words.RAMP_MINJERK):
+                    t(True, s)
+            elif "case" in names:
                 for c in range(6):
                     t(True, c)
             elif t.__code__.co_argcount == 1:
@@ -48,6 +63,7 @@ def test_unmutated_oracle_passes_every_pin_used_here(oracle_built):
     assert not some_pin_fails(WORD_PINS)
     assert not some_pin_fails(CHIRP_PINS)
     assert not some_pin_fails(SUM_PINS)
+    assert not some_pin_fails(AMP_PINS)
 
 
 def _floor_round(x):
@@ -134,17 +150,54 @@ def test_post_window_line_mutant_is_caught(monkeypatch, oracle_built):
     assert some_pin_fails(CHIRP_PINS)
 
 
+def _minjerk_amp_wrong(shape, tau):
+    tau = float(tau)
+    if shape == words.RAMP_MINJERK:
+        return tau ** 3 * (10.0 - 15.0 * tau + 5.0 * tau * tau)     # 6 -> 5
+    return ORIG_AMP_SHAPE(shape, tau)
+
+
+def _cosine_amp_wrong(shape, tau):
+    tau = float(tau)
+    if shape == words.RAMP_COSINE:
+        return (1.0 - math.cos(math.pi * tau))                        # dropped / 2
+    return ORIG_AMP_SHAPE(shape, tau)
+
+
+def _amp_ramp_reversed(self, d):
+    s = words.amp_shape(self.shape, Fraction(d, self.M))
+    return self.a_to * (1.0 - s) + self.a_from * s
+
+
+ORIG_AMP_SHAPE = words.amp_shape
+AMP_MUTANTS = {
+    "min-jerk amplitude profile coefficient": ("amp_shape", _minjerk_amp_wrong, words),
+    "raised-cosine amplitude profile without 1/2": ("amp_shape", _cosine_amp_wrong, words),
+    "amplitude ramp runs backwards": ("at", _amp_ramp_reversed, words.AmpRamp),
+}
+
+
+@pytest.mark.parametrize("name", sorted(AMP_MUTANTS))
+def test_amp_mutants_are_caught(monkeypatch, oracle_built, name):
+    attr, fn, owner = AMP_MUTANTS[name]
+    monkeypatch.setattr(owner, attr, fn)
+    assert some_pin_fails(AMP_PINS), name
+
+
 def test_default_gain_mutant_is_caught(monkeypatch, oracle_built):
     monkeypatch.setattr(words, "default_gain", lambda amps: 32767.0 / sum(float(a) ** 2 for a in amps))
     assert some_pin_fails([pins.test_mean_power_and_default_gain])
 
 
 C_MUTANTS = {
-    "sum uses cosine": ("acc += tones[k].amp * sin(two_pi * turns);", "acc += tones[k].amp * cos(two_pi * turns);"),
+    "sum uses cosine": ("acc += oracle_amp_at(&tones[k], amps, n) * sin(two_pi * turns);",
+                        "acc += oracle_amp_at(&tones[k], amps, n) * cos(two_pi * turns);"),
     "turn scale off by 2": ("double turns = (double)(int64_t)w * 0x1p-64;", "double turns = (double)(int64_t)w * 0x1p-63;"),
     "linear term without 1/2": ("return (uint64_t)(prod >> 1);", "return (uint64_t)(prod);"),
     "post-window line uses the start frequency": ("return r->p_after + r->f_after * n;", "return r->p_after + r->f_line * n;"),
     "rounding truncates": ("double r = nearbyint(acc);", "double r = trunc(acc);"),
+    "amplitude held at its start after the ramp": ("if (d > r->m) return r->a_to;", "if (d > r->m) return r->a_from;"),
+    "min-jerk amplitude profile coefficient": ("(10.0 - 15.0 * tau + 6.0 * tau * tau)", "(10.0 - 15.0 * tau + 5.0 * tau * tau)"),
 }
 
 
@@ -162,6 +215,6 @@ def test_c_oracle_mutants_are_caught(monkeypatch, tmp_path, oracle_built, name):
     monkeypatch.setattr(csynth, "_lib", None)
     monkeypatch.setattr(csynth, "build", lambda force=True: str(lib))
     try:
-        assert some_pin_fails(SUM_PINS), name
+        assert some_pin_fails(SUM_PINS + AMP_PINS), name
     finally:
         csynth._lib = None

@@ -417,3 +417,106 @@ def test_brute_force_long_double(oracle_built):
         assert np.max(np.abs(y - ref.astype(np.float64))) < 1e-9
         rq = np.clip(np.rint(ref), -32768, 32767).astype(np.int16)
         assert np.array_equal(q, rq)
+
+
+# ------------------------------------------------------- amplitude ramps (Eq. (5) a_j[i])
+
+def test_amp_ramp_quarter_rate_closed_form(oracle_built):
+    """A quarter-rate cosine (samples 1, 0, -1, 0) of 1000 LSB ramped linearly to 0
+    over [4, 12]: every sample is a hand-computed multiple of 125."""
+    p = words.Plan(FS, 1000.0, 0, one_tone(FS / 4, phase=0.25))
+    p.add_amp_ramp(0, 4, 8, RAMP_LINEAR, 0.0)
+    _, y = csynth.synth(p, 0, 16)
+    want = [1000, 0, -1000, 0, 1000, 0, -750, 0, 500, 0, -250, 0, 0, 0, 0, 0]
+    assert np.max(np.abs(y - np.array(want, dtype=float))) < 1e-9
+    _, yp = p.synth_points(range(16))
+    assert np.max(np.abs(yp - np.array(want, dtype=float))) < 1e-9
+
+
+@pytest.mark.parametrize("shape,M,d,frac", [
+    (RAMP_LINEAR, 1024, 512, Fraction(1, 2)),
+    (RAMP_COSINE, 768, 256, Fraction(1, 4)),        # (1 - cos(pi/3)) / 2
+    (RAMP_COSINE, 1024, 512, Fraction(1, 2)),
+    (RAMP_MINJERK, 1024, 256, Fraction(106, 1024)),  # 10/64 - 15/256 + 6/1024
+    (RAMP_MINJERK, 1024, 512, Fraction(1, 2)),
+    (RAMP_MINJERK, 1024, 768, Fraction(918, 1024)),
+])
+def test_amp_profile_values(oracle_built, shape, M, d, frac):
+    """From 1000 to 0: amplitude 1000 (1 - s); s at these points fixed by hand."""
+    p = words.Plan(FS, 1000.0, 0, one_tone(30e6))
+    p.add_amp_ramp(0, 100, M, shape, 0.0)
+    want = float(1000 * (1 - frac))
+    assert abs(p.tones[0].amp_at(100 + d) - want) < 1e-9
+    assert abs(csynth.amps_at(p, 0, [100 + d])[0] - want) < 1e-9
+
+
+@pytest.mark.parametrize("shape", [RAMP_LINEAR, RAMP_COSINE, RAMP_MINJERK])
+def test_amp_profile_invariants(oracle_built, shape):
+    """Ends exact, s(1 - t) = 1 - s(t), monotone; minimum jerk starts and ends flat."""
+    M = 1000
+    p = words.Plan(FS, 1.0, 0, one_tone(30e6, amp=2.0))
+    p.add_amp_ramp(0, 50, M, shape, 0.5)
+    tw = p.tones[0]
+    ns = np.arange(0, 50 + M + 60)
+    a = csynth.amps_at(p, 0, ns)
+    assert a[0] == 2.0 and a[50] == 2.0 and a[50 + M] == 0.5 and a[-1] == 0.5
+    d = np.arange(M + 1)
+    s = (2.0 - a[50 + d]) / 1.5
+    assert np.max(np.abs(s + s[::-1] - 1.0)) < 1e-12
+    assert np.all(np.diff(s) >= -1e-15)
+    if shape == RAMP_MINJERK:
+        assert s[1] < 1e-7 and 1.0 - s[M - 1] < 1e-7          # s ~ 10 t^3 near the ends
+    else:
+        assert s[1] > 1e-6
+    assert abs(tw.amp_at(50 + M // 2) - csynth.amps_at(p, 0, [50 + M // 2])[0]) < 1e-12
+
+
+def test_switched_off_tone_leaves_the_others(oracle_built):
+    """Ramping a tone to 0 (the rearrangement demo's tones turned off): afterwards the
+    sum is exactly that of the other tones; before the ramp, that of all three."""
+    t = make_tones(3)
+    t["f_start_hz"] = [31e6, 47e6, 88e6]
+    t["f_end_hz"] = t["f_start_hz"]
+    t["amplitude"] = [0.5, 0.9, 0.7]
+    t["phase_turns"] = [0.1, 0.6, 0.3]
+    p = words.Plan(FS, 1000.0, 0, t)
+    p.add_amp_ramp(1, 100, 64, RAMP_COSINE, 0.0)
+    keep = words.Plan(FS, 1000.0, 0, t[[0, 2]])
+    full = words.Plan(FS, 1000.0, 0, t)
+    _, y = csynth.synth(p, 0, 300)
+    _, yk = csynth.synth(keep, 0, 300)
+    _, yf = csynth.synth(full, 0, 300)
+    assert np.array_equal(y[165:], yk[165:])
+    assert np.array_equal(y[:101], yf[:101])
+    assert not np.array_equal(y[101:164], yk[101:164])
+
+
+def test_amp_ramp_chain_is_continuous():
+    p = words.Plan(FS, 10.0, 0, one_tone(30e6, amp=1.0))
+    p.add_amp_ramp(0, 10, 10, RAMP_LINEAR, 0.5)
+    p.add_amp_ramp(0, 20, 20, RAMP_MINJERK, 1.5)        # starts where the first ends
+    tw = p.tones[0]
+    assert tw.amp_at(9) == 10.0 and tw.amp_at(20) == 5.0 and tw.amp_at(40) == 15.0
+    assert tw.amp_at(1000) == 15.0
+    assert abs(tw.amp_at(15) - 7.5) < 1e-12
+    with pytest.raises(ValueError):
+        p.add_amp_ramp(0, 39, 5, RAMP_LINEAR, 0.0)       # overlaps the last window
+    with pytest.raises(ValueError):
+        p.add_amp_ramp(0, 50, 0, RAMP_LINEAR, 0.0)       # empty window
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_c_sum_equals_python_with_amp_ramps(oracle_built, case):
+    """The C and the Python evaluators agree with amplitude and frequency ramps mixed."""
+    t = _tiny_cases()[case]
+    p = words.Plan(FS, 0.0, 0, t, build_tables=True)
+    rng = np.random.default_rng(100 + case)
+    for k in range(len(t)):
+        b = int(rng.integers(0, 20))
+        p.add_amp_ramp(k, b, int(rng.integers(1, 30)), int(rng.integers(1, 4)), float(rng.uniform(0, 1)))
+        if rng.random() < 0.5:
+            p.add_amp_ramp(k, 52, int(rng.integers(1, 10)), int(rng.integers(1, 4)), 0.0)
+    q, y = csynth.synth(p, 0, 64)
+    qp, yp = p.synth_points(range(64))
+    assert np.array_equal(q, qp)
+    assert np.max(np.abs(y - yp)) < 1e-9
