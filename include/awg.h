@@ -165,6 +165,33 @@ awg_status awg_ramp_table(int32_t shape, uint64_t n, uint64_t *out);
 awg_status awg_plan_retune(awg_plan *plan, const awg_retune *events, int32_t n_events,
                            void *hip_stream);
 
+/* An amplitude ramp of one tone (the time-dependent amplitude a_j[i] of Eq. (5);
+ * switching a tone off is a ramp to 0, switching one on a ramp up from a tone
+ * planned with amplitude 0). Over the window [ramp_start, ramp_start + ramp_len]
+ * the tone's amplitude moves from the value it holds (its planned amplitude, or
+ * the end of its previous amplitude ramp) to amplitude_end:
+ *   a(n) = a0 (1 - s) + a1 s,   s = profile((n - ramp_start) / ramp_len),
+ * with profile linear t, raised cosine (1 - cos(pi t)) / 2 or minimum jerk
+ * 10 t^3 - 15 t^4 + 6 t^5; a0 before the window, a1 after it. */
+typedef struct {
+    int32_t tone;
+    int32_t ramp;            /* AWG_RAMP_LINEAR / COSINE / MINJERK: the profile */
+    uint64_t ramp_start;
+    uint64_t ramp_len;       /* 1 <= ramp_len < 2^31 */
+    double amplitude_end;    /* >= 0, in the units of awg_tone.amplitude (scaled by the plan's gain) */
+} awg_amp_ramp;
+
+/* Append amplitude ramps to tones of a plan, in stream order on hip_stream like
+ * awg_plan_retune (frequency windows and amplitude windows of a tone are
+ * independent). A tone keeps one amplitude window on the device; a new one must
+ * not start before the previous one ends. At most one event per tone per call.
+ * The caller keeps the sum within int16 (the gain is fixed at planning).
+ * AWG_E_INVALID for a bad tone, profile or amplitude, AWG_E_RANGE for a window
+ * that starts too early or is too long, AWG_E_UNSUPPORTED for two events on one
+ * tone or more than 16384 events. */
+awg_status awg_plan_amplitude(awg_plan *plan, const awg_amp_ramp *events, int32_t n_events,
+                              void *hip_stream);
+
 /* -------------------------------------------------------------- synthesis */
 
 /* Static pathway: samples n0 .. n0+count-1 of a plan without ramp windows into

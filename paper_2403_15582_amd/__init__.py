@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libawg.so")
 
 EXPORTED = [
     "awg_ctx_create", "awg_ctx_destroy", "awg_plan_tones", "awg_plan_destroy",
-    "awg_plan_info_get", "awg_plan_words", "awg_ramp_table", "awg_plan_retune",
+    "awg_plan_info_get", "awg_plan_words", "awg_ramp_table", "awg_plan_retune", "awg_plan_amplitude",
     "awg_synth_static", "awg_synth_chirp", "awg_stream_next", "awg_stream_seek",
     "awg_stream_tell", "awg_synth_f32", "awg_synth_multiplex", "awg_stream_next_multiplex",
     "awg_phase_dump", "awg_strerror", "awg_version",
@@ -97,6 +97,12 @@ class awg_retune(ctypes.Structure):
                 ("f_end_hz", ctypes.c_double)]
 
 
+class awg_amp_ramp(ctypes.Structure):
+    _fields_ = [("tone", ctypes.c_int32), ("ramp", ctypes.c_int32),
+                ("ramp_start", ctypes.c_uint64), ("ramp_len", ctypes.c_uint64),
+                ("amplitude_end", ctypes.c_double)]
+
+
 _lib = None
 _exiting = False
 _VP = ctypes.c_void_p
@@ -130,6 +136,7 @@ def lib():
         "awg_plan_words": ([_VP, _VP, _VP, _VP, _VP], _I32),
         "awg_ramp_table": ([_I32, _U64, _VP], _I32),
         "awg_plan_retune": ([_VP, ctypes.POINTER(awg_retune), _I32, _VP], _I32),
+        "awg_plan_amplitude": ([_VP, ctypes.POINTER(awg_amp_ramp), _I32, _VP], _I32),
         "awg_synth_static": ([_VP, _U64, _U64, _VP, _VP], _I32),
         "awg_synth_chirp": ([_VP, _U64, _U64, _VP, _VP], _I32),
         "awg_stream_next": ([_VP, _U64, _VP, _VP, ctypes.POINTER(_U64)], _I32),
@@ -236,6 +243,24 @@ def awg_plan_retune(plan, events, stream=0):
     array from retune_array."""
     arr = events if hasattr(events, "n_events") else retune_array(events)
     _check(lib().awg_plan_retune(plan, arr, arr.n_events, stream or None), "awg_plan_retune")
+
+
+def amp_ramp_array(events):
+    """ctypes array of awg_amp_ramp from (tone, ramp, ramp_start, ramp_len,
+    amplitude_end) tuples."""
+    ev = list(events)
+    arr = (awg_amp_ramp * max(1, len(ev)))()
+    for i, (k, shape, a, n, amp) in enumerate(ev):
+        arr[i] = awg_amp_ramp(int(k), int(shape), int(a), int(n), float(amp))
+    arr.n_events = len(ev)
+    return arr
+
+
+def awg_plan_amplitude(plan, events, stream=0):
+    """events: iterable of (tone, ramp, ramp_start, ramp_len, amplitude_end), or
+    an array from amp_ramp_array."""
+    arr = events if hasattr(events, "n_events") else amp_ramp_array(events)
+    _check(lib().awg_plan_amplitude(plan, arr, arr.n_events, stream or None), "awg_plan_amplitude")
 
 
 def awg_synth_static(plan, n0, count, d_out, stream=0):
@@ -456,6 +481,10 @@ class Plan:
 
     def retune(self, events, stream=None):
         awg_plan_retune(self.handle, events, self._stream(stream))
+
+    def amplitude(self, events, stream=None):
+        """Amplitude ramps: (tone, ramp, ramp_start, ramp_len, amplitude_end) each."""
+        awg_plan_amplitude(self.handle, events, self._stream(stream))
 
     def seek(self, n0):
         awg_stream_seek(self.handle, n0)

@@ -28,25 +28,38 @@ constexpr int kWaves = 4;
 constexpr int kLanes = 64;
 constexpr int kBlock = 32;          // largest block
 
-// One tone as the kernels read it (64 bytes, read with scalar loads).
-// Static tones have a = UINT64_MAX, n = 0 (their window never opens).
+// One tone as the kernels read it (96 bytes, read with scalar loads).
+// Tones without a frequency ramp have a = UINT64_MAX, n = 0 (their window never
+// opens) and p1, f1 = p0, f0; without an amplitude ramp ashape = AWG_RAMP_NONE
+// and amp1 = amp.
 struct ToneDev {
     uint64_t p0, f0;     // line before the window: phi = p0 + f0 * n (p0 includes kPhaseBias)
     uint64_t p1, f1;     // line after the window (p1 includes kPhaseBias)
-    uint64_t a, n;       // window [a, a + n]
+    uint64_t a;          // frequency window [a, a + n]
     int64_t coef;        // linear: R; smooth: dF
-    float amp;           // A_k * G
-    uint16_t shape;      // awg_ramp
+    uint32_t n;          // window length, < 2^31
+    float amp;           // A_k * G before the amplitude window
+    uint16_t shape;      // awg_ramp of the frequency window
     uint16_t table;      // index into the plan's table pointer array (smooth shapes)
+    uint16_t ashape;     // awg_ramp profile of the amplitude window (AWG_RAMP_NONE: none)
+    uint16_t pad;
+    uint64_t b;          // amplitude window [b, b + m]
+    uint32_t m;          // its length, < 2^31
+    float amp1;          // A_k * G after the amplitude window
+    uint64_t lo, hi;     // samples outside [lo, hi] are on a line at a constant amplitude
+                         // (lo > hi: no window at all)
 };
-static_assert(sizeof(ToneDev) == 64, "ToneDev must be 64 bytes");
+static_assert(sizeof(ToneDev) == 96, "ToneDev must be 96 bytes");
 
 // Host copy of a tone's state (exact words without the device bias).
 struct ToneHost {
     uint64_t p0, f0, p1, f1, a, n;
     int64_t coef;
     int32_t shape;
-    double amp;          // A_k * G in FP64
+    double amp;          // A_k * G in FP64 (before the amplitude window)
+    int32_t ashape;      // amplitude window profile, AWG_RAMP_NONE if none
+    uint64_t b, m;       // amplitude window [b, b + m]
+    double amp1;         // A_k * G after it
 };
 
 // A block of contiguous tones [begin, begin + count) of a tone list, summed by
@@ -64,6 +77,7 @@ struct Block {
 static_assert(sizeof(Block) == 8, "Block must be 8 bytes");
 constexpr uint16_t kBlockUniform = 1;   // every tone shares the first one's shape, window and table
 constexpr uint16_t kBlockSplit = 2;     // hybrid path: on line tiles the tones are summed elsewhere
+constexpr uint16_t kBlockAmp = 4;       // some tone has an amplitude window
 
 // One chunk of one plan in a batched launch (64 bytes).
 struct BatchItem {

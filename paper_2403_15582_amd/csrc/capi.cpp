@@ -304,6 +304,10 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
                         t.f_end_hz, &h);
         if (st != AWG_OK) break;
         h.amp = t.amplitude * gain;
+        h.ashape = AWG_RAMP_NONE;
+        h.b = UINT64_MAX;
+        h.m = 0;
+        h.amp1 = h.amp;
         uint16_t idx = 0;
         if (smooth(t.ramp)) {
             bool added;
@@ -398,6 +402,10 @@ awg_status awg_plan_words(const awg_plan *p, uint64_t *p0, uint64_t *f0, uint64_
     return AWG_OK;
 }
 
+static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, hipStream_t s);
+
+static bool windowed(const ToneHost &h) { return h.shape != AWG_RAMP_NONE || h.ashape != AWG_RAMP_NONE; }
+
 awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void *hip_stream)
 {
     if (!p || (n_ev > 0 && !ev) || n_ev < 0) return AWG_E_INVALID;
@@ -422,6 +430,10 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
                                    r.f_end_hz, &h);
         if (st != AWG_OK) return st;
         h.amp = cur.amp;
+        h.ashape = cur.ashape;
+        h.b = cur.b;
+        h.m = cur.m;
+        h.amp1 = cur.amp1;
         next[i] = h;
     }
     awg_status st = AWG_OK;
@@ -441,12 +453,61 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
     }
     if (st != AWG_OK) return st;
     p->mfma_b_key = 0;
+    std::vector<int32_t> changed(n_ev);
     for (int32_t i = 0; i < n_ev; ++i) {
         const int32_t k = ev[i].tone;
-        if (p->host[k].shape == AWG_RAMP_NONE) p->n_ramped++;
+        if (!windowed(p->host[k])) p->n_ramped++;
         p->host[k] = next[i];
         p->dev_mirror[p->inv[k]] = to_device(next[i], tidx[i]);
+        changed[i] = k;
     }
+    return push_tones(p, changed.data(), n_ev, (hipStream_t)hip_stream);
+}
+
+awg_status awg_plan_amplitude(awg_plan *p, const awg_amp_ramp *ev, int32_t n_ev, void *hip_stream)
+{
+    if (!p || (n_ev > 0 && !ev) || n_ev < 0) return AWG_E_INVALID;
+    if (n_ev == 0) return AWG_OK;
+    if ((size_t)n_ev > kSlotRecords) return AWG_E_UNSUPPORTED;
+    std::vector<ToneHost> next;
+    try { next.resize(n_ev); } catch (...) { return AWG_E_NOMEM; }
+    for (int32_t i = 0; i < n_ev; ++i) {
+        const awg_amp_ramp &r = ev[i];
+        if (r.tone < 0 || r.tone >= p->n_tones) return AWG_E_INVALID;
+        if (!(r.ramp == AWG_RAMP_LINEAR || smooth(r.ramp))) return AWG_E_INVALID;
+        if (!std::isfinite(r.amplitude_end) || r.amplitude_end < 0.0) return AWG_E_INVALID;
+        for (int32_t j = 0; j < i; ++j)
+            if (ev[j].tone == r.tone) return AWG_E_UNSUPPORTED;   // one window per tone and call
+        if (r.ramp_len == 0 || r.ramp_len >= (1ull << 31)) return AWG_E_RANGE;
+        if (r.ramp_start >= kMaxSample || r.ramp_len >= kMaxSample - r.ramp_start) return AWG_E_RANGE;
+        const ToneHost &cur = p->host[r.tone];
+        const uint64_t free_from = cur.ashape == AWG_RAMP_NONE ? 0 : cur.b + cur.m;
+        if (r.ramp_start < free_from) return AWG_E_RANGE;
+        ToneHost h = cur;
+        h.amp = cur.ashape == AWG_RAMP_NONE ? cur.amp : cur.amp1;     // the amplitude it holds now
+        h.amp1 = r.amplitude_end * p->gain;
+        h.ashape = r.ramp;
+        h.b = r.ramp_start;
+        h.m = r.ramp_len;
+        next[i] = h;
+    }
+    std::vector<int32_t> changed(n_ev);
+    for (int32_t i = 0; i < n_ev; ++i) {
+        const int32_t k = ev[i].tone;
+        if (!windowed(p->host[k])) p->n_ramped++;
+        const uint16_t table = p->dev_mirror[p->inv[k]].table;
+        p->host[k] = next[i];
+        p->dev_mirror[p->inv[k]] = to_device(next[i], table);
+        changed[i] = k;
+    }
+    return push_tones(p, changed.data(), n_ev, (hipStream_t)hip_stream);
+}
+
+// Device copy of the tones changed on the host (caller indices), in stream order:
+// their records go through a pinned slot and a scatter kernel, the rebuilt block
+// table after them.
+static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, hipStream_t s)
+{
     build_blocks(p->dev_mirror, -1, &p->blocks);
     if (!p->ctx) return AWG_OK;
     // stage the new records and scatter them on the stream
@@ -476,11 +537,10 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
     }
     ScatterRecord *rec = (ScatterRecord *)slot.host;
     for (int32_t i = 0; i < n_ev; ++i) {
-        rec[i].index = (uint32_t)p->inv[ev[i].tone];
+        rec[i].index = (uint32_t)p->inv[changed[i]];
         rec[i].pad = 0;
-        rec[i].tone = p->dev_mirror[p->inv[ev[i].tone]];
+        rec[i].tone = p->dev_mirror[p->inv[changed[i]]];
     }
-    hipStream_t s = (hipStream_t)hip_stream;
     void *d_rec = (char *)p->d_scratch + si * sizeof(ScatterRecord) * kSlotRecords;
     e = hipMemcpyAsync(d_rec, rec, sizeof(ScatterRecord) * (size_t)n_ev, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_scatter_tones(p->d_tones, d_rec, n_ev, s);

@@ -185,6 +185,36 @@ __device__ __forceinline__ void linear_run(const ToneDev &t, uint64_t tile0, uin
     }
 }
 
+// Amplitude of tone t at the lane's samples tile0 + j + s (the a_j[i] of
+// Eq. (5)): amp before the amplitude window [b, b+m], amp1 after it, and
+// inside amp (1 - w) + amp1 w with w the window's profile at (n - b) / m
+// (linear, raised cosine, minimum jerk), exact at both ends.
+template <int S>
+__device__ __forceinline__ void amp_values(const ToneDev &t, uint64_t tile0, uint64_t tile_last, uint32_t j,
+                                           float (&av)[S])
+{
+    if (t.ashape == AWG_RAMP_NONE || tile_last < t.b || tile0 > t.b + t.m) {
+        const float c = (t.ashape == AWG_RAMP_NONE || tile_last < t.b) ? t.amp : t.amp1;
+#pragma unroll
+        for (int s = 0; s < S; ++s) av[s] = c;
+        return;
+    }
+    const int64_t m = (int64_t)t.m;
+    const float fm = (float)t.m;
+    const int64_t d0 = (int64_t)(tile0 + j - t.b);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        int64_t d = d0 + s;
+        d = d < 0 ? 0 : (d > m ? m : d);
+        const float tau = (float)(int32_t)d / fm;               // correctly rounded: 0 and 1 exact
+        float w;
+        if (t.ashape == AWG_RAMP_LINEAR) w = tau;
+        else if (t.ashape == AWG_RAMP_COSINE) w = 0.5f - 0.5f * __builtin_amdgcn_cosf(0.5f * tau);
+        else w = tau * tau * tau * __builtin_fmaf(tau, __builtin_fmaf(6.0f, tau, -15.0f), 10.0f);
+        av[s] = __builtin_fmaf(t.amp1, w, t.amp * (1.0f - w));
+    }
+}
+
 __device__ __forceinline__ int16_t quantise(float y)
 {
     float r = __builtin_rintf(y);
@@ -232,7 +262,18 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
         float blk[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) blk[s] = 0.0f;
-        if (!STATIC && (bk.flags & kBlockUniform)) {
+        if (!STATIC && (bk.flags & kBlockAmp)) {
+            // tones with an amplitude window: per-tone regimes, per-sample amplitude
+            for (int k = k0; k < k1; ++k) {
+                const ToneDev t = tones[k];
+                if (split && (tile_last < t.lo || tile0 > t.hi)) continue;
+                float av[S];
+                amp_values<S>(t, tile0, tile_last, j, av);
+                gen_phases<S>(t, tables, tile0, lane, [&](int s, uint64_t ph) {
+                    blk[s] = __builtin_fmaf(av[s], word_sin(ph), blk[s]);
+                });
+            }
+        } else if (!STATIC && (bk.flags & kBlockUniform)) {
             // every tone of the block has the window and shape of tones[k0]
             const ToneDev r = tones[k0];
             const bool pre = tile_last < r.a, post = tile0 > r.a + r.n;
@@ -314,7 +355,7 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
         } else {
             for (int k = k0; k < k1; ++k) {
                 const ToneDev t = tones[k];
-                if (split && (tile_last < t.a || tile0 > t.a + t.n)) continue;
+                if (split && (tile_last < t.lo || tile0 > t.hi)) continue;
                 const float amp = t.amp;
                 gen_phases<S>(t, tables, tile0, lane, [&](int s, uint64_t ph) {
                     blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);

@@ -109,7 +109,10 @@ static void sort_group(const std::vector<ToneDev> &tones, std::vector<int32_t> *
         if (a.shape != b.shape) return a.shape < b.shape;
         if (a.a != b.a) return a.a < b.a;
         if (a.n != b.n) return a.n < b.n;
-        return a.table < b.table;
+        if (a.table != b.table) return a.table < b.table;
+        if (a.ashape != b.ashape) return a.ashape < b.ashape;
+        if (a.b != b.b) return a.b < b.b;
+        return a.m < b.m;
     });
 }
 
@@ -123,17 +126,18 @@ static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t ro
     for (int32_t k = 0; k < p->n_tones; ++k) {
         const ToneDev &t = p->dev_mirror[k];
         const uint32_t kk = (uint32_t)k;
-        if (t.shape == AWG_RAMP_NONE || last < t.a) {
+        // the tone's windows (frequency and amplitude) span [lo, hi]
+        if (t.lo > t.hi || last < t.lo) {
             h->entries.push_back(kk | (kLinePre << kLineShift));
             continue;
         }
-        if (n0 > t.a + t.n) {
+        if (n0 > t.hi) {
             h->entries.push_back(kk | (kLinePost << kLineShift));
             continue;
         }
-        // rows ending before a (n0 + 1024c + 1023 < a) and starting after a + N
-        const uint64_t pre_rows = t.a > n0 ? std::min<uint64_t>(rows, (t.a - n0) / kRow) : 0;
-        const uint64_t q = (t.a + t.n - n0) / kRow;
+        // rows ending before lo (n0 + 1024c + 1023 < lo) and starting after hi
+        const uint64_t pre_rows = t.lo > n0 ? std::min<uint64_t>(rows, (t.lo - n0) / kRow) : 0;
+        const uint64_t q = (t.hi - n0) / kRow;
         const uint64_t post_rows = rows > q + 1 ? rows - (q + 1) : 0;
         const uint64_t line_rows = pre_rows + post_rows;
         if (line_rows > 0 && line_rows * 8 >= rows) {
@@ -164,7 +168,7 @@ static void tile_order(HybridState *h, uint64_t n0, uint64_t rows, int32_t n_spl
     for (size_t i = 0; i < h->direct.size(); ++i) {
         const ToneDev &t = h->direct[i];
         const bool split = (int32_t)i < n_split;
-        const uint64_t a = t.a, e = t.a + t.n;
+        const uint64_t a = t.lo, e = t.hi;
         // tiles meeting the window: [ca, ce]
         const uint64_t ca = a <= n0 ? 0 : (a - n0) / kRow;
         const uint64_t ce = e >= last ? rows - 1 : (e - n0) / kRow;

@@ -78,9 +78,11 @@ template <> struct Split<__bf16> {
 };
 
 // Line entry of the hybrid path (kLineShift, kLine*): pre / post: the line
-// before / after the window on every row; split-pre: the line before the window
-// on the rows that end before the window opens; split-post: the line after the
-// window on the rows that start after it closes.
+// before / after the windows on every row; split-pre: the line before the
+// windows on the rows that end before the first opens; split-post: the line
+// after them on the rows that start after the last closes. A tone's windows
+// (frequency and amplitude) span [lo, hi]; before it the tone is on
+// p0 + f0 n at amplitude amp, after it on p1 + f1 n at amp1.
 
 // Line (P, F) of entry e on the row [first, first + mcols - 1]; false when the
 // entry does not cover the row. entries == nullptr: entry e is tone e's first line.
@@ -94,12 +96,13 @@ __device__ __forceinline__ bool entry_line(const ToneDev *__restrict__ tones, co
     const uint32_t ent = entries[e];
     const uint32_t mode = ent >> kLineShift;
     td = tones[ent & ((1u << kLineShift) - 1)];
-    if (mode & 1u) {                      // a line after the window
+    if (mode & 1u) {                      // the line (and amplitude) after the windows
         td.p0 = td.p1;
         td.f0 = td.f1;
+        td.amp = td.amp1;
     }
-    if (mode == kLineSplitPre) return first + (mcols - 1) < td.a;
-    if (mode == kLineSplitPost) return first > td.a + td.n;
+    if (mode == kLineSplitPre) return first + (mcols - 1) < td.lo;
+    if (mode == kLineSplitPost) return first > td.hi;
     return true;
 }
 

@@ -196,19 +196,28 @@ ToneDev to_device(const ToneHost &t, uint16_t table)
     d.p1 = t.p1 + kPhaseBias;
     d.f1 = t.f1;
     d.a = t.a;
-    d.n = t.n;
+    d.n = (uint32_t)t.n;
     d.coef = t.coef;
     d.amp = (float)t.amp;
     d.shape = (uint16_t)t.shape;
     d.table = table;
+    d.ashape = (uint16_t)t.ashape;
+    d.pad = 0;
+    d.b = t.ashape == AWG_RAMP_NONE ? UINT64_MAX : t.b;
+    d.m = t.ashape == AWG_RAMP_NONE ? 0u : (uint32_t)t.m;
+    d.amp1 = t.ashape == AWG_RAMP_NONE ? d.amp : (float)t.amp1;
+    d.lo = UINT64_MAX;
+    d.hi = 0;
+    if (t.shape != AWG_RAMP_NONE) { d.lo = t.a; d.hi = t.a + t.n; }
+    if (t.ashape != AWG_RAMP_NONE) { d.lo = std::min(d.lo, t.b); d.hi = std::max(d.hi, t.b + t.m); }
     return d;
 }
 
-// Block table (see Block): maximal runs of tones with equal shape, window and
-// table (not crossing n_split) of at least kMinRun tones become uniform blocks,
-// ceil(L / kBlock) of them rounded up to a multiple of kWaves and sized within
-// one tone of each other; shorter runs are packed into mixed blocks of up to
-// kBlock tones.
+// Block table (see Block): maximal runs of tones with equal shape, window,
+// table and amplitude window (not crossing n_split) of at least kMinRun tones
+// become uniform blocks, ceil(L / kBlock) of them rounded up to a multiple of
+// kWaves and sized within one tone of each other; shorter runs are packed into
+// mixed blocks of up to kBlock tones that share their flags (split, amplitude).
 void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vector<Block> *out)
 {
     constexpr int32_t kMinRun = 8;
@@ -217,8 +226,8 @@ void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vecto
     out->push_back(Block{0, 0, 0});
     auto same = [&](int32_t x, int32_t y) {
         const ToneDev &a = tones[x], &b = tones[y];
-        return a.shape == b.shape && a.a == b.a && a.n == b.n && a.table == b.table &&
-               ((x < n_split) == (y < n_split));
+        return a.shape == b.shape && a.a == b.a && a.n == b.n && a.table == b.table && a.ashape == b.ashape &&
+               a.b == b.b && a.m == b.m && ((x < n_split) == (y < n_split));
     };
     int32_t mixed_begin = -1, mixed_count = 0;
     uint16_t mixed_flags = 0;
@@ -231,7 +240,7 @@ void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vecto
         int32_t j = i + 1;
         while (j < n && same(i, j)) ++j;
         const int32_t L = j - i;
-        const uint16_t split = i < n_split ? kBlockSplit : 0;
+        const uint16_t flags = (i < n_split ? kBlockSplit : 0) | (tones[i].ashape != AWG_RAMP_NONE ? kBlockAmp : 0);
         if (L >= kMinRun) {
             flush();
             int32_t nb = (L + kBlock - 1) / kBlock;
@@ -240,13 +249,13 @@ void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vecto
             int32_t b = i;
             for (int32_t q = 0; q < nb; ++q) {
                 const int32_t c = base + (q < extra ? 1 : 0);
-                out->push_back(Block{(uint32_t)b, (uint16_t)c, (uint16_t)(kBlockUniform | split)});
+                out->push_back(Block{(uint32_t)b, (uint16_t)c, (uint16_t)(kBlockUniform | flags)});
                 b += c;
             }
         } else {
             for (int32_t k = i; k < j; ++k) {
-                if (mixed_count > 0 && (mixed_count == kBlock || mixed_flags != split)) flush();
-                if (mixed_count == 0) { mixed_begin = k; mixed_flags = split; }
+                if (mixed_count > 0 && (mixed_count == kBlock || mixed_flags != flags)) flush();
+                if (mixed_count == 0) { mixed_begin = k; mixed_flags = flags; }
                 ++mixed_count;
             }
         }

@@ -231,6 +231,29 @@ def row_edges(seed=12, n0=3 * CHUNK + 12345, rows=70, tail=37, K_static=192, per
     return Workload("row-edges", fs_hz, 0.0, 0, t, n0, count)
 
 
+def rearrangement(seed=14, K=100, off_frac=0.5, fs_hz=FS_280, f_lo=75e6, f_hi=125e6,
+                  t_off=20000, off_len=2800, t_move=30000, move_len=280000, tail=60000):
+    """The rearrangement of the paper's dynamic-pathway demonstration (a
+    stochastically loaded array made defect-free), in the rf domain: K tones on
+    an even grid over [f_lo, f_hi] with Schroeder phases; a seeded off_frac of
+    them are switched off (amplitude ramped to 0, minimum-jerk profile) over
+    [t_off, t_off + off_len]; the remaining tones are then chirped (minimum
+    jerk) over [t_move, t_move + move_len] onto the first grid positions, in
+    order. ``amp_events`` holds (tone, ramp, start, length, amplitude_end),
+    ``retunes`` (tone, start, length, shape, f_end_hz)."""
+    r = _rng(seed)
+    f = f_lo + (np.arange(K) + 0.5) * ((f_hi - f_lo) / K)
+    tones = static_tones(f, np.full(K, 1.0), schroeder_turns(K))
+    off = np.sort(r.choice(K, int(round(off_frac * K)), replace=False))
+    keep = np.setdiff1d(np.arange(K), off)
+    amp_events = [(int(k), RAMP_MINJERK, t_off, off_len, 0.0) for k in off]
+    retunes = [(int(k), t_move, move_len, RAMP_MINJERK, float(f[i])) for i, k in enumerate(keep)]
+    w = Workload("rearrange-%dtone" % K, fs_hz, 0.0, 20, tones, 0, t_move + move_len + tail,
+                 retunes=retunes)
+    w.amp_events = amp_events
+    return w
+
+
 def small_mixed(seed=11, K=24, fs_hz=FS_280, n_total=5000, period_log2=0):
     """Small tone set covering every ramp shape and regime (pre / in / post
     window, windows straddling tile edges, rising and falling chirps), for

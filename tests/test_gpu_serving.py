@@ -58,8 +58,9 @@ def test_admission_by_memory_and_backpressure():
     jobs = _jobs(12, seed=9)
     biggest = max(len(j.tones) for j in jobs)
     ring = 2 * (1 << 20) * 2
-    # room for the ring plus the tone table of about one large job at a time
-    budget = ring + (biggest * 64 + 4096)
+    # room for the ring plus the device tables of about one large job at a time
+    # (96-byte tone records, up to 8 bytes of block table per tone, alignment)
+    budget = ring + (biggest * (96 + 8) + 8192)
     with Server(mem_budget_bytes=budget, max_jobs=8, ring_slots=2) as srv:
         out = srv.run_trace(jobs, collect=range(len(jobs)), time_scale=0.0)
         st = srv.stats()

@@ -194,3 +194,38 @@ def test_retune_words_follow_oracle_chain():
         assert e.value.status == awg.AWG_E_UNSUPPORTED
     finally:
         awg.awg_plan_destroy(plan)
+
+
+def test_amplitude_ramp_validation_and_counts():
+    """awg_plan_amplitude on a host-only plan: argument checks, chaining rules, and the
+    plan counts a tone with an amplitude window as dynamic (no static fast path)."""
+    w = W.config1()
+    plan, _ = _host_plan(w)
+    try:
+        assert awg.awg_plan_info_get(plan)["n_ramped"] == 0
+        L, C, M = awg.RAMP_LINEAR, awg.RAMP_COSINE, awg.RAMP_MINJERK
+        awg.awg_plan_amplitude(plan, [(0, L, 100, 50, 0.0), (1, C, 0, 1, 2.0), (2, M, 5, 1000, 0.5)])
+        assert awg.awg_plan_info_get(plan)["n_ramped"] == 3
+        awg.awg_plan_amplitude(plan, [(0, M, 150, 10, 1.0)])          # starts where the last ended
+        assert awg.awg_plan_info_get(plan)["n_ramped"] == 3
+        bad = [
+            ([(len(w.tones), L, 0, 10, 0.0)], awg.AWG_E_INVALID),      # no such tone
+            ([(5, awg.RAMP_NONE, 0, 10, 0.0)], awg.AWG_E_INVALID),     # no profile
+            ([(5, L, 0, 10, -0.1)], awg.AWG_E_INVALID),                # negative amplitude
+            ([(5, L, 0, 10, float("nan"))], awg.AWG_E_INVALID),
+            ([(5, L, 0, 0, 0.0)], awg.AWG_E_RANGE),                    # empty window
+            ([(5, L, 0, 1 << 31, 0.0)], awg.AWG_E_RANGE),              # too long
+            ([(5, L, (1 << 63) - 5, 10, 0.0)], awg.AWG_E_RANGE),       # past the last sample
+            ([(0, L, 159, 10, 0.0)], awg.AWG_E_RANGE),                 # before the previous end
+            ([(6, L, 0, 10, 0.0), (6, L, 100, 10, 0.0)], awg.AWG_E_UNSUPPORTED),
+        ]
+        for events, status in bad:
+            with pytest.raises(awg.AwgError) as e:
+                awg.awg_plan_amplitude(plan, events)
+            assert e.value.status == status, events
+        assert awg.awg_plan_info_get(plan)["n_ramped"] == 3            # failed calls change nothing
+        with pytest.raises(awg.AwgError) as e:
+            awg.awg_synth_static(plan, 0, 16, 1234)                     # host-only, and no longer static
+        assert e.value.status == awg.AWG_E_INVALID
+    finally:
+        awg.awg_plan_destroy(plan)
