@@ -184,6 +184,31 @@ def test_amp_mutants_are_caught(monkeypatch, oracle_built, name):
     assert some_pin_fails(AMP_PINS), name
 
 
+def _schroeder_sign_flipped(method, f_hz, amps):
+    return [(1.0 - x) % 1.0 for x in ORIG_PHASE_PLAN(method, f_hz, amps)]
+
+
+def _newman_off_by_one(method, f_hz, amps):
+    if method != PH.NEWMAN:
+        return ORIG_PHASE_PLAN(method, f_hz, amps)
+    K = len(f_hz)
+    rank, _ = PH.rank_by_frequency(f_hz)
+    return [float(Fraction(rank[i] + 1, 1) ** 2 / (2 * K) % 1) for i in range(K)]
+
+
+from oracle import phases as PH   # noqa: E402
+ORIG_PHASE_PLAN = PH.phase_plan
+PHASE_PINS = [pins.test_schroeder_equal_amplitudes_reduce_to_textbook_form, pins.test_newman_phases_by_hand,
+              pins.test_schroeder_phases_lower_the_crest_factor]
+
+
+@pytest.mark.parametrize("name,fn", [("Schroeder phases with the wrong sign", _schroeder_sign_flipped),
+                                     ("Newman phases with k^2 for (k-1)^2", _newman_off_by_one)])
+def test_phase_plan_mutants_are_caught(monkeypatch, oracle_built, name, fn):
+    monkeypatch.setattr(PH, "phase_plan", fn)
+    assert some_pin_fails(PHASE_PINS), name
+
+
 def test_default_gain_mutant_is_caught(monkeypatch, oracle_built):
     monkeypatch.setattr(words, "default_gain", lambda amps: 32767.0 / sum(float(a) ** 2 for a in amps))
     assert some_pin_fails([pins.test_mean_power_and_default_gain])

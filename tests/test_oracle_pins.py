@@ -520,3 +520,62 @@ def test_c_sum_equals_python_with_amp_ramps(oracle_built, case):
     qp, yp = p.synth_points(range(64))
     assert np.array_equal(q, qp)
     assert np.max(np.abs(y - yp)) < 1e-9
+
+
+# ------------------------------------------------ crest-factor phases (Theory section)
+
+from oracle import phases as PH   # noqa: E402
+
+
+def test_schroeder_equal_amplitudes_reduce_to_textbook_form():
+    """For equal amplitudes Schroeder's rule is -pi k (k - 1) / K, i.e. -k(k-1)/(2K) turns."""
+    K = 37
+    f = np.linspace(10e6, 50e6, K)[::-1]            # ranks are by frequency, not input order
+    got = PH.phase_plan(PH.SCHROEDER, f, np.ones(K))
+    for i in range(K):
+        k = K - i                                  # rank of input i (frequencies descend)
+        t = Fraction(-k * (k - 1), 2 * K)
+        assert abs(got[i] - float(t - math.floor(t))) < 1e-15
+
+
+def test_newman_phases_by_hand():
+    """K = 4: (k-1)^2 / 8 turns = 0, 1/8, 4/8, 9/8 -> 1/8."""
+    got = PH.phase_plan(PH.NEWMAN, [4e6, 1e6, 3e6, 2e6], None)
+    assert got == [0.125, 0.0, 0.5, 0.125]
+
+
+def test_crest_factor_of_aligned_cosines_is_exact(oracle_built):
+    """All tones in cosine phase meet at n = 0: peak = G sum A, so the crest factor is
+    sum A / sqrt(sum A^2 / 2) exactly (|y| can never exceed G sum A)."""
+    p2 = 12
+    L = 1 << p2
+    rng = np.random.default_rng(7)
+    K = 9
+    t = make_tones(K)
+    t["f_start_hz"] = rng.choice(np.arange(1, L // 2), K, replace=False) * (FS / L)
+    t["f_end_hz"] = t["f_start_hz"]
+    t["amplitude"] = rng.uniform(0.2, 1.0, K)
+    t["phase_turns"] = 0.25
+    p = words.Plan(FS, 100.0, p2, t)
+    _, y = csynth.synth(p, 0, L)
+    want = np.sum(t["amplitude"]) / math.sqrt(np.sum(t["amplitude"] ** 2) / 2)
+    assert abs(PH.crest_factor(y, t["amplitude"], 100.0) - want) < 1e-9
+
+
+def test_schroeder_phases_lower_the_crest_factor(oracle_built):
+    """64 equal tones on consecutive bins: aligned cosines give sqrt(2K) = 11.3;
+    Schroeder's phases bring the peak within 2x the rms (about 1.7 is the
+    classical figure for such multisines)."""
+    p2, K = 12, 64
+    L = 1 << p2
+    t = make_tones(K)
+    t["f_start_hz"] = (np.arange(K) + 100) * (FS / L)
+    t["f_end_hz"] = t["f_start_hz"]
+    t["amplitude"] = 1.0
+    t["phase_turns"] = PH.phase_plan(PH.SCHROEDER, t["f_start_hz"], t["amplitude"])
+    _, y = csynth.synth(words.Plan(FS, 100.0, p2, t), 0, L)
+    cf = PH.crest_factor(y, t["amplitude"], 100.0)
+    assert 1.41 < cf < 2.0, cf
+    t["phase_turns"] = 0.25
+    _, y0 = csynth.synth(words.Plan(FS, 100.0, p2, t), 0, L)
+    assert abs(PH.crest_factor(y0, t["amplitude"], 100.0) - math.sqrt(2 * K)) < 1e-9
