@@ -256,6 +256,32 @@ awg_status awg_synth_multiplex(awg_plan *const *plans, int32_t n_channels, uint6
 awg_status awg_stream_next_multiplex(awg_plan *const *plans, int32_t n_channels, uint64_t count,
                                      int16_t *d_out, void *hip_stream, uint64_t *n0_out);
 
+/* ----------------------------------------------------- crest-factor control */
+
+/* Tone phases set the peak (crest) factor of the static waveform (Theory
+ * section: large crest factors mean rf power spikes that can damage the AOD;
+ * the paper cites Schroeder 1970 without a formula). awg_phase_plan returns
+ * closed-form phases, tones ranked by frequency k = 1..K (equal frequencies in
+ * input order), in turns in [0, 1), ready for awg_tone.phase_turns:
+ *   AWG_PHASES_SCHROEDER  theta_k = -2 pi sum_{l<k} (k - l) p_l,
+ *                         p_l = A_l^2 / sum A^2 (equal amplitudes: -pi k (k-1) / K)
+ *   AWG_PHASES_NEWMAN     theta_k = pi (k - 1)^2 / K (amplitude may be NULL)
+ * Host only. AWG_E_INVALID for n <= 0, NULL arrays, non-finite values, negative
+ * or all-zero amplitudes (Schroeder). */
+#define AWG_PHASES_SCHROEDER 1
+#define AWG_PHASES_NEWMAN    2
+awg_status awg_phase_plan(int32_t method, const double *f_hz, const double *amplitude, int32_t n_tones,
+                          double *phase_turns_out);
+
+/* Peak |y| of a plan's unquantised sum over samples n0 .. n0+count-1, in LSB:
+ * the direct kernel writes y (FP32) into d_scratch (device, count floats,
+ * caller-owned), then a device max reduction writes the peak to *d_peak
+ * (device, one float), both on hip_stream. With one full period of a plan whose
+ * tones sit on distinct bins, peak / (G sqrt(sum A^2 / 2)) is its crest factor.
+ * AWG_E_INVALID for NULL pointers or count = 0; AWG_E_RANGE as awg_synth_chirp. */
+awg_status awg_peak(awg_plan *plan, uint64_t n0, uint64_t count, float *d_scratch, float *d_peak,
+                    void *hip_stream);
+
 /* Phase words of one tone as the direct kernel generates them (same code path,
  * same sample-to-lane mapping), for exact comparison: d_words[i] = phi(n0 + i). */
 awg_status awg_phase_dump(awg_plan *plan, int32_t tone, uint64_t n0, uint64_t count,

@@ -99,11 +99,13 @@ constexpr int kTileSamples = 1024;
 // Geometry of the hybrid path's product over count samples in rows of
 // kTileSamples (one row = one direct-kernel tile): row blocks padded to whole
 // 256-row tiles, 8-entry k-blocks, gz split-K slices of kb_split k-blocks, and
-// gz FP32 planes of `plane` elements. Workspace: B hi, B lo, A hi, A lo, planes.
+// gz FP32 planes of `plane` elements. Workspace: B hi, B lo (each laid out for
+// kb_cap k-blocks, so the B operand keeps its place from call to call), A hi,
+// A lo, planes.
 struct LinesGeom {
-    int32_t kb_n, rb_pad, cb_n, gz, kb_split;
+    int32_t kb_n, kb_cap, rb_pad, cb_n, gz, kb_split;
     uint64_t plane;
-    size_t a_bytes, b_bytes, plane_bytes;
+    size_t a_bytes, b_bytes, plane_bytes;       // b_bytes: one half at kb_cap k-blocks
     size_t work_bytes() const { return 2 * (a_bytes + b_bytes) + plane_bytes; }
 };
 
@@ -208,6 +210,7 @@ hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint6
                              uint64_t *out, hipStream_t s);
 hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n,
                                 hipStream_t s);
+hipError_t launch_peak(const float *d_y, uint64_t count, float *d_peak, hipStream_t s);
 hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint32_t grid, hipStream_t s);
 // Multiplexed channels: items[c] (c < n, n <= kMaxChannels) each cover the same
 // count samples; one launch, items passed by value.
@@ -224,12 +227,14 @@ awg_status hybrid_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t coun
 void hybrid_release(awg_plan *p);
 size_t hybrid_bytes(const awg_plan *p);       // device memory held by the hybrid path
 // Its two launches (mfma.hip, direct.hip). Line entries: bits 0..28 the tone's
-// device position, bits 29..31 the mode (kLineMode*).
+// device position, bits 29..31 the mode (kLine*; kLineNone: no rows, zero amplitude).
 constexpr uint32_t kLineShift = 29;
-enum : uint32_t { kLinePre = 0, kLinePost = 1, kLineSplitPre = 2, kLineSplitPost = 3 };
-LinesGeom lines_geometry(int32_t n_entries, uint64_t count);
+enum : uint32_t { kLinePre = 0, kLinePost = 1, kLineSplitPre = 2, kLineSplitPost = 3, kLineNone = 4 };
+LinesGeom lines_geometry(int32_t n_entries, int32_t max_entries, uint64_t count);
+// d_blocks / n_blocks: the k-blocks whose B operand must be (re)built; all when d_blocks is null.
 hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, const uint32_t *d_entries,
-                        int32_t n_entries, uint64_t n0, uint64_t count, void *d_work, hipStream_t s);
+                        int32_t n_entries, const int32_t *d_blocks, int32_t n_blocks, uint64_t n0,
+                        uint64_t count, void *d_work, hipStream_t s);
 hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks,
                                 const uint32_t *d_order, uint64_t n0, uint64_t count, const float *planes,
                                 int32_t n_planes, uint64_t plane_stride, int16_t *out_i16, float *out_f32,

@@ -684,6 +684,18 @@ awg_status awg_stream_next_multiplex(awg_plan *const *plans, int32_t n_channels,
     return AWG_OK;
 }
 
+awg_status awg_peak(awg_plan *p, uint64_t n0, uint64_t count, float *d_scratch, float *d_peak, void *hip_stream)
+{
+    awg_status st = device_ready(p);
+    if (st != AWG_OK) return st;
+    if (!d_scratch || !d_peak || count == 0) return AWG_E_INVALID;
+    if ((st = check_range(n0, count)) != AWG_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = launch_direct_f32(p, n0, count, d_scratch, s);
+    if (e == hipSuccess) e = launch_peak(d_scratch, count, d_peak, s);
+    return hip_status(e);
+}
+
 awg_status awg_phase_dump(awg_plan *p, int32_t tone, uint64_t n0, uint64_t count, uint64_t *d_words,
                           void *hip_stream)
 {

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "awg_internal.h"
 
 namespace awg {
@@ -625,6 +627,32 @@ hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const
 hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint32_t grid, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_kernel<kS>, dim3(grid), dim3(256), 0, s, d_items, d_header);
+    return hipGetLastError();
+}
+
+// max |y| over y[0 .. count): per-thread grid-stride max, a wave max with
+// cross-lane shuffles, then one atomic max per wave on the float's bit pattern
+// (for non-negative floats the unsigned order is the numeric order).
+__global__ __launch_bounds__(256) void peak_kernel(const float *__restrict__ y, uint64_t count,
+                                                   unsigned int *__restrict__ peak_bits)
+{
+    float m = 0.0f;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(y[i]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(peak_bits, __float_as_uint(m));
+}
+
+__global__ void zero_word_kernel(unsigned int *w) { *w = 0u; }
+
+hipError_t launch_peak(const float *d_y, uint64_t count, float *d_peak, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, s, (unsigned int *)d_peak);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(peak_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, d_y, count, (unsigned int *)d_peak);
     return hipGetLastError();
 }
 

@@ -65,9 +65,15 @@ struct HybridState {
     size_t work_cap = 0;
     hipEvent_t work_done = nullptr;              // last use of d_work, on whatever stream
     bool work_used = false;
+    // B operand cache: the frequency word each entry slot had when its k-block
+    // was last built, for the method b_method; invalid after a reallocation
+    std::vector<uint64_t> b_word;
+    uint32_t b_method = 0;
+    bool b_valid = false;
     // host scratch kept between calls
-    std::vector<uint32_t> entries;
-    std::vector<int32_t> split, only;
+    std::vector<uint32_t> entries, extras;
+    std::vector<int32_t> split, only, dirty;
+    int32_t n_line = 0;
     std::vector<ToneDev> direct;
     std::vector<Block> blocks;
     std::vector<float> cost;
@@ -117,22 +123,32 @@ static void sort_group(const std::vector<ToneDev> &tones, std::vector<int32_t> *
 }
 
 // Line entries and the direct kernel's tone list for rows [0, rows) from n0.
+// Entry slots are stable from call to call: slot k is tone k's first line (or
+// kLineNone when the direct kernel takes the tone on every row), slots up to a
+// multiple of 8 are padding, and the second lines of tones split on both sides
+// follow. A tone's slot then keeps its frequency word, and with it its columns
+// of the B operand, until its line changes.
 static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t rows)
 {
-    h->entries.clear();
+    const int32_t K = p->n_tones;
+    h->entries.assign((size_t)(K + 7) / 8 * 8, kLineNone << kLineShift);
+    h->extras.clear();
     h->split.clear();
     h->only.clear();
+    h->n_line = 0;
     const uint64_t last = n0 + rows * kRow - 1;
-    for (int32_t k = 0; k < p->n_tones; ++k) {
+    for (int32_t k = 0; k < K; ++k) {
         const ToneDev &t = p->dev_mirror[k];
         const uint32_t kk = (uint32_t)k;
         // the tone's windows (frequency and amplitude) span [lo, hi]
         if (t.lo > t.hi || last < t.lo) {
-            h->entries.push_back(kk | (kLinePre << kLineShift));
+            h->entries[k] = kk | (kLinePre << kLineShift);
+            h->n_line++;
             continue;
         }
         if (n0 > t.hi) {
-            h->entries.push_back(kk | (kLinePost << kLineShift));
+            h->entries[k] = kk | (kLinePost << kLineShift);
+            h->n_line++;
             continue;
         }
         // rows ending before lo (n0 + 1024c + 1023 < lo) and starting after hi
@@ -141,13 +157,16 @@ static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t ro
         const uint64_t post_rows = rows > q + 1 ? rows - (q + 1) : 0;
         const uint64_t line_rows = pre_rows + post_rows;
         if (line_rows > 0 && line_rows * 8 >= rows) {
-            if (pre_rows) h->entries.push_back(kk | (kLineSplitPre << kLineShift));
-            if (post_rows) h->entries.push_back(kk | (kLineSplitPost << kLineShift));
+            h->entries[k] = kk | ((pre_rows ? kLineSplitPre : kLineSplitPost) << kLineShift);
+            h->n_line++;
+            if (pre_rows && post_rows) h->extras.push_back(kk | (kLineSplitPost << kLineShift));
             h->split.push_back(k);
         } else {
+            h->entries[k] = kk | (kLineNone << kLineShift);
             h->only.push_back(k);
         }
     }
+    h->entries.insert(h->entries.end(), h->extras.begin(), h->extras.end());
     sort_group(p->dev_mirror, &h->split);
     sort_group(p->dev_mirror, &h->only);
     h->direct.clear();
@@ -190,25 +209,64 @@ static void tile_order(HybridState *h, uint64_t n0, uint64_t rows, int32_t n_spl
     std::stable_sort(h->order.begin(), h->order.end(), [&](uint32_t x, uint32_t y) { return c[x] > c[y]; });
 }
 
+// Frequency word of an entry's line (what the B operand of its slot holds).
+static uint64_t entry_word(const awg_plan *p, uint32_t ent)
+{
+    const ToneDev &t = p->dev_mirror[ent & ((1u << kLineShift) - 1)];
+    return ((ent >> kLineShift) & 1u) ? t.f1 : t.f0;
+}
+
+// k-blocks whose B operand must be rebuilt: those holding an entry with a line
+// whose frequency word differs from the one built last; b_word is updated for
+// them. All of them (dirty empty, return false) when nothing is cached.
+static bool dirty_blocks(const awg_plan *p, HybridState *h, uint32_t method, int32_t kb_n)
+{
+    h->dirty.clear();
+    const int32_t n = (int32_t)h->entries.size();
+    if (!h->b_valid || h->b_method != method) {
+        h->b_word.assign((size_t)kb_n * 8, 0);
+        for (int32_t e = 0; e < n; ++e) h->b_word[e] = entry_word(p, h->entries[e]);
+        h->b_method = method;
+        h->b_valid = true;
+        return false;
+    }
+    if (h->b_word.size() < (size_t)kb_n * 8) h->b_word.resize((size_t)kb_n * 8, 0);
+    for (int32_t kb = 0; kb < kb_n; ++kb) {
+        bool d = false;
+        for (int32_t e = 8 * kb; e < std::min(n, 8 * kb + 8) && !d; ++e)
+            d = (h->entries[e] >> kLineShift) != kLineNone && entry_word(p, h->entries[e]) != h->b_word[e];
+        if (!d) continue;
+        h->dirty.push_back(kb);
+        for (int32_t e = 8 * kb; e < std::min(n, 8 * kb + 8); ++e) h->b_word[e] = entry_word(p, h->entries[e]);
+    }
+    return true;
+}
+
 static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n0, uint64_t count,
                         int16_t *out_i16, float *out_f32, hipStream_t s)
 {
     const uint64_t rows = (count + kRow - 1) / kRow;
     classify(p, h, n0, rows);
     const int32_t n_entries = (int32_t)h->entries.size();
+    const int32_t max_entries = (p->n_tones + 7) / 8 * 8 + p->n_tones;
     const int32_t n_direct = (int32_t)h->direct.size();
     build_blocks(h->direct, (int32_t)h->split.size(), &h->blocks);
     tile_order(h, n0, rows, (int32_t)h->split.size());
+    const LinesGeom g = lines_geometry(n_entries, max_entries, count);
+    const bool gemm = h->n_line > 0 && g.gz > 0;
 
-    // staging blob: entries | direct tone list | block table | tile order
+    // staging blob: entries | direct tone list | block table | tile order | dirty k-blocks
     const size_t off_t = align_up(sizeof(uint32_t) * (size_t)n_entries, 256);
     const size_t off_b = align_up(off_t + sizeof(ToneDev) * (size_t)n_direct, 256);
     const size_t off_o = align_up(off_b + sizeof(Block) * h->blocks.size(), 256);
-    const size_t total = off_o + sizeof(uint32_t) * rows;
+    const size_t off_d = align_up(off_o + sizeof(uint32_t) * rows, 256);
+    const size_t kb_max = ((size_t)max_entries + 7) / 8;
+    const size_t total = off_d + sizeof(int32_t) * kb_max;
     // slots are sized for the largest blob this plan can produce, so they are allocated once
-    const size_t cap = align_up(sizeof(uint32_t) * 2 * (size_t)p->n_tones, 256) +
+    const size_t cap = align_up(sizeof(uint32_t) * (size_t)max_entries, 256) +
                        align_up(sizeof(ToneDev) * (size_t)p->n_tones, 256) +
-                       align_up(sizeof(Block) * ((size_t)p->n_tones + 1), 256) + sizeof(uint32_t) * (kPiece / kRow);
+                       align_up(sizeof(Block) * ((size_t)p->n_tones + 1), 256) +
+                       align_up(sizeof(uint32_t) * (kPiece / kRow), 256) + sizeof(int32_t) * kb_max;
     HybridState::Slot &slot = h->slots[h->next];
     h->next = (h->next + 1) % kHybSlots;
     hipError_t e = hipSuccess;
@@ -239,8 +297,6 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
     std::memcpy(hb + off_o, h->order.data(), sizeof(uint32_t) * rows);
 
     // workspace for the operands and the partial planes
-    const LinesGeom g = lines_geometry(n_entries, count);
-    const bool gemm = n_entries > 0 && g.gz > 0;
     if (!h->work_done) {
         e = hipEventCreateWithFlags(&h->work_done, hipEventDisableTiming);
         if (e != hipSuccess) return hst(e);
@@ -253,17 +309,22 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
         if (h->d_work) (void)hipFree(h->d_work);
         h->d_work = nullptr;
         h->work_cap = 0;
-        const size_t want = g.work_bytes() + g.work_bytes() / 4;      // headroom: entries vary by call
+        const size_t want = g.work_bytes() + g.work_bytes() / 4;      // headroom: rows vary by call
         e = hipMalloc(&h->d_work, want);
         if (e != hipSuccess) return hst(e);
         h->work_cap = want;
+        h->b_valid = false;
     }
+    const bool partial = gemm && dirty_blocks(p, h, method, g.kb_n);
+    if (partial && !h->dirty.empty())
+        std::memcpy(hb + off_d, h->dirty.data(), sizeof(int32_t) * h->dirty.size());
 
     char *db = (char *)slot.dev;
     e = hipMemcpyAsync(db, hb, total, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && h->work_used) e = hipStreamWaitEvent(s, h->work_done, 0);
     if (e == hipSuccess && gemm)
-        e = launch_lines(p, method, g, (const uint32_t *)db, n_entries, n0, count, h->d_work, s);
+        e = launch_lines(p, method, g, (const uint32_t *)db, n_entries, partial ? (const int32_t *)(db + off_d) : nullptr,
+                         partial ? (int32_t)h->dirty.size() : 0, n0, count, h->d_work, s);
     const float *planes = gemm ? (const float *)((char *)h->d_work + 2 * (g.a_bytes + g.b_bytes)) : nullptr;
     if (e == hipSuccess)
         e = launch_direct_hybrid(p, (const ToneDev *)(db + off_t), (const Block *)(db + off_b),

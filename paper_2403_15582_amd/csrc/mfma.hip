@@ -103,7 +103,7 @@ __device__ __forceinline__ bool entry_line(const ToneDev *__restrict__ tones, co
     }
     if (mode == kLineSplitPre) return first + (mcols - 1) < td.lo;
     if (mode == kLineSplitPost) return first > td.hi;
-    return true;
+    return mode != kLineNone;
 }
 
 // A operand: one thread per (row c, group g of 4 entries) -> 8 inner values.
@@ -144,17 +144,19 @@ __global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ 
 }
 
 // B operand: one thread per (column m, group g of 4 entries); the frequency
-// word of the entry's line (its rows do not matter here).
+// word of the entry's line (its rows do not matter here). With kb_list the
+// groups are those of the listed k-blocks only (2 groups per k-block).
 template <typename T>
 __global__ __launch_bounds__(256) void gen_b_kernel(const ToneDev *__restrict__ tones,
                                                     const uint32_t *__restrict__ entries, int32_t n_entries,
                                                     int32_t n_groups, int32_t cb_n, T *__restrict__ b_hi,
-                                                    T *__restrict__ b_lo)
+                                                    T *__restrict__ b_lo, const int32_t *__restrict__ kb_list = nullptr)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cols = (int64_t)cb_n * 32;
     if (gid >= cols * n_groups) return;
-    const int32_t g = (int32_t)(gid / cols);
+    const int32_t gi = (int32_t)(gid / cols);
+    const int32_t g = kb_list ? 2 * kb_list[gi >> 1] + (gi & 1) : gi;
     const int64_t m = gid % cols;
     typename Split<T>::vec hv, lv;
 #pragma unroll
@@ -366,14 +368,15 @@ static hipError_t launch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *
 }
 
 // GEMM variant: 0 = 4 waves / 2 stages, 1 = 4 waves / 3 stages, 2 = 8 waves / 2 stages,
-// 3 = 8 waves / 3 stages. The default is the fastest measured on MI355X; the
-// environment variable AWG_GEMM_VARIANT overrides it for tuning sweeps.
+// 3 = 8 waves / 3 stages, 4 = 8 waves / 4 stages, 5 = 8 waves / 5 stages (160 KB
+// of LDS). The default is the fastest measured on MI355X; the environment
+// variable AWG_GEMM_VARIANT overrides it for tuning sweeps.
 static int gemm_variant()
 {
     static int v = -1;
     if (v < 0) {
         const char *e = getenv("AWG_GEMM_VARIANT");
-        v = (e && e[0] >= '0' && e[0] <= '3') ? e[0] - '0' : 3;
+        v = (e && e[0] >= '0' && e[0] <= '5') ? e[0] - '0' : 3;
     }
     return v;
 }
@@ -387,6 +390,8 @@ static hipError_t dispatch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T
     case 0: return launch_gemm<T, 2, 2, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
     case 1: return launch_gemm<T, 2, 2, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
     case 2: return launch_gemm<T, 2, 4, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
+    case 4: return launch_gemm<T, 2, 4, 4>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
+    case 5: return launch_gemm<T, 2, 4, 5>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
     default: return launch_gemm<T, 2, 4, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
     }
 }
@@ -454,7 +459,7 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     return hipst(e);
 }
 
-LinesGeom lines_geometry(int32_t n_entries, uint64_t count)
+LinesGeom lines_geometry(int32_t n_entries, int32_t max_entries, uint64_t count)
 {
     constexpr int32_t kTargetGroups = 256;          // one 8-wave workgroup per CU
     const uint64_t mcols = kTileSamples;
@@ -463,6 +468,7 @@ LinesGeom lines_geometry(int32_t n_entries, uint64_t count)
     g.rb_pad = (int32_t)(((rows + 31) / 32 + kTileRB - 1) / kTileRB * kTileRB);
     g.cb_n = (int32_t)(mcols / 32);
     g.kb_n = (n_entries + 7) / 8;
+    g.kb_cap = std::max(g.kb_n, (max_entries + 7) / 8);
     const int32_t tiles = (g.rb_pad / kTileRB) * (g.cb_n / kTileCB);
     int32_t gz = (kTargetGroups + tiles - 1) / tiles;
     gz = std::max(1, std::min(gz, g.kb_n));
@@ -470,14 +476,15 @@ LinesGeom lines_geometry(int32_t n_entries, uint64_t count)
     g.gz = g.kb_split > 0 ? (g.kb_n + g.kb_split - 1) / g.kb_split : 0;
     g.plane = rows * mcols;
     g.a_bytes = (size_t)g.kb_n * g.rb_pad * kFragBytes;
-    g.b_bytes = (size_t)g.kb_n * g.cb_n * kFragBytes;
+    g.b_bytes = (size_t)g.kb_cap * g.cb_n * kFragBytes;
     g.plane_bytes = (size_t)g.gz * g.plane * sizeof(float);
     return g;
 }
 
 template <typename T>
 static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_t *d_entries, int32_t n_entries,
-                            uint64_t n0, uint64_t count, char *w, hipStream_t s)
+                            const int32_t *d_blocks, int32_t n_blocks, uint64_t n0, uint64_t count, char *w,
+                            hipStream_t s)
 {
     const bool f16 = std::is_same<T, _Float16>::value;
     T *b_hi = (T *)w, *b_lo = (T *)(w + g.b_bytes);
@@ -485,7 +492,7 @@ static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_
     float *planes = (float *)(w + 2 * (g.a_bytes + g.b_bytes));
     const uint64_t mcols = kTileSamples;
     const int64_t a_threads = (int64_t)g.rb_pad * 32 * (2 * g.kb_n);
-    const int64_t b_threads = (int64_t)g.cb_n * 32 * (2 * g.kb_n);
+    const int64_t b_threads = (int64_t)g.cb_n * 32 * (2 * (d_blocks ? n_blocks : g.kb_n));
     hipError_t e;
     {
         ProfScope prof(p->ctx, s, f16 ? "hyb_gen_a_f16" : "hyb_gen_a_bf16");
@@ -494,10 +501,11 @@ static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    {
+    if (b_threads > 0) {
         ProfScope prof(p->ctx, s, f16 ? "hyb_gen_b_f16" : "hyb_gen_b_bf16");
         hipLaunchKernelGGL((gen_b_kernel<T>), dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, s,
-                           p->d_tones, d_entries, n_entries, 2 * g.kb_n, g.cb_n, b_hi, b_lo);
+                           p->d_tones, d_entries, n_entries, 2 * (d_blocks ? n_blocks : g.kb_n), g.cb_n, b_hi,
+                           b_lo, d_blocks);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -508,13 +516,14 @@ static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_
 }
 
 hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, const uint32_t *d_entries,
-                        int32_t n_entries, uint64_t n0, uint64_t count, void *d_work, hipStream_t s)
+                        int32_t n_entries, const int32_t *d_blocks, int32_t n_blocks, uint64_t n0,
+                        uint64_t count, void *d_work, hipStream_t s)
 {
     if (g.gz <= 0 || n_entries <= 0) return hipSuccess;
     if (method == AWG_F_METHOD_MFMA_F16X3)
-        return lines_run<_Float16>(p, g, d_entries, n_entries, n0, count, (char *)d_work, s);
+        return lines_run<_Float16>(p, g, d_entries, n_entries, d_blocks, n_blocks, n0, count, (char *)d_work, s);
     if (method == AWG_F_METHOD_MFMA_BF16X3)
-        return lines_run<__bf16>(p, g, d_entries, n_entries, n0, count, (char *)d_work, s);
+        return lines_run<__bf16>(p, g, d_entries, n_entries, d_blocks, n_blocks, n0, count, (char *)d_work, s);
     return hipErrorInvalidValue;
 }
 

@@ -229,3 +229,23 @@ def test_amplitude_ramp_validation_and_counts():
         assert e.value.status == awg.AWG_E_INVALID
     finally:
         awg.awg_plan_destroy(plan)
+
+
+def test_phase_plan_matches_oracle():
+    from oracle import phases as PH
+    rng = np.random.default_rng(8)
+    for K in (1, 2, 7, 100, 300):
+        f = rng.uniform(1e6, 100e6, K)
+        f[:K // 3] = f[0]                                      # ties keep input order
+        a = rng.uniform(0.0, 1.0, K)
+        for m in (awg.AWG_PHASES_SCHROEDER, awg.AWG_PHASES_NEWMAN):
+            got = awg.awg_phase_plan(m, f, a)
+            want = np.array(PH.phase_plan(m, f, a))
+            d = np.abs(got - want)
+            d = np.minimum(d, 1.0 - d)                         # distance on the circle
+            assert np.all((got >= 0) & (got < 1)) and d.max() < 1e-12, (K, m, d.max())
+    for bad in [(3, [1e6], [1.0]), (awg.AWG_PHASES_SCHROEDER, [1e6, 2e6], [0.0, 0.0]),
+                (awg.AWG_PHASES_SCHROEDER, [1e6], [-1.0]), (awg.AWG_PHASES_NEWMAN, [float("inf")], None)]:
+        with pytest.raises(awg.AwgError) as e:
+            awg.awg_phase_plan(*bad)
+        assert e.value.status == awg.AWG_E_INVALID
