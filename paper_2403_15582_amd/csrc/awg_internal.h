@@ -168,6 +168,9 @@ struct awg_plan {
     void *d_work;
     size_t d_work_bytes;
     uint64_t mfma_b_key;
+    std::mutex work_mu;                // host-side use of d_work (calls may come from several threads)
+    hipEvent_t work_done = nullptr;    // the last launch that used d_work, on whatever stream
+    bool work_used = false;
     // hybrid path (matrix cores + direct kernel for ramped plans), created on first use
     awg::HybridState *hyb;
 };

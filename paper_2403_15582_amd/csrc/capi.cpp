@@ -123,6 +123,11 @@ void free_plan_device(awg_plan *p)
     if (p->d_blocks) (void)hipFree(p->d_blocks);
     if (p->d_table_ptrs) (void)hipFree(p->d_table_ptrs);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
+    if (p->work_done) {
+        (void)hipEventSynchronize(p->work_done);
+        (void)hipEventDestroy(p->work_done);
+        p->work_done = nullptr;
+    }
     if (p->d_work) (void)hipFree(p->d_work);
     for (auto &s : p->slots) {
         if (s.host) (void)hipHostFree(s.host);

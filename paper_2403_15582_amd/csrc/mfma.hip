@@ -415,7 +415,18 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     const size_t a_bytes = (size_t)kb_n * rb_pad * frag, b_bytes = (size_t)kb_n * cb_n * frag;
     const size_t need = 2 * (a_bytes + b_bytes);
     if (rows > (1ull << 26)) return AWG_E_UNSUPPORTED;
+    // calls on one plan may come from several host threads and streams: one at a
+    // time here, and each stream waits for the previous user of the workspace
+    std::lock_guard<std::mutex> lock(p->work_mu);
+    if (!p->work_done) {
+        hipError_t e = hipEventCreateWithFlags(&p->work_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hipst(e);
+    }
     if (p->d_work_bytes < need) {
+        if (p->work_used) {
+            hipError_t e = hipEventSynchronize(p->work_done);
+            if (e != hipSuccess) return hipst(e);
+        }
         if (p->d_work) (void)hipFree(p->d_work);
         p->d_work = nullptr;
         p->d_work_bytes = 0;
@@ -432,7 +443,8 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     const int64_t a_threads = (int64_t)rb_pad * 32 * (2 * kb_n);
     const int64_t b_threads = (int64_t)cb_n * 32 * (2 * kb_n);
     const bool f16 = sizeof(T) == 2 && std::is_same<T, _Float16>::value;
-    hipError_t e;
+    hipError_t e = p->work_used ? hipStreamWaitEvent(s, p->work_done, 0) : hipSuccess;
+    if (e != hipSuccess) return hipst(e);
     {
         ProfScope prof(p->ctx, s, f16 ? "gen_a_kernel_f16" : "gen_a_kernel_bf16");
         hipLaunchKernelGGL((gen_a_kernel<T>), dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, s,
@@ -456,6 +468,8 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
         e = dispatch_gemm<T>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_n, 0, mcols, count, out_i16,
                              out_f32);
     }
+    if (e == hipSuccess) e = hipEventRecord(p->work_done, s);
+    if (e == hipSuccess) p->work_used = true;
     return hipst(e);
 }
 

@@ -93,3 +93,30 @@ def test_mfma_equals_direct_within_one_lsb_everywhere():
     qo, _ = csynth.synth(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), 0, w.count)
     compare(qa, None, qo, None, "config1 mfma vs oracle (all samples)")
     assert np.max(np.abs(qa.astype(np.int32) - qb.astype(np.int32))) <= 2
+
+
+@pytest.mark.parametrize("ramped", [False, True])
+def test_two_streams_on_one_plan(ramped):
+    """Synthesis calls on one plan from two streams at once (the matrix-core
+    workspace is shared and ordered between them) equal the same calls run one
+    after the other."""
+    torch = need_gpu()
+    w = W.config4(K=600, seconds=0.01) if ramped else W.config1()
+    p = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, BF16)
+    if ramped:
+        p.retune([(k, sh, a, n, f) for k, a, n, sh, f in sorted(w.retunes, key=lambda e: e[1])[:100]])
+    calls = [(0, 1 << 20), (12345, 3 << 18), (1 << 20, 1 << 20), (777, 1 << 19)]
+    say("two streams, ramped=%s" % ramped)
+    ref = [to_np(p.synth_chirp(n0, c)) for n0, c in calls]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = [torch.empty(c, dtype=torch.int16, device="cuda") for _, c in calls]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for i, (n0, c) in enumerate(calls):
+            st = s1 if i % 2 == 0 else s2
+            with torch.cuda.stream(st):
+                p.synth_chirp(n0, c, out=outs[i], stream=st)
+        torch.cuda.synchronize()
+        for i in range(len(calls)):
+            assert np.array_equal(to_np(outs[i]), ref[i]), (rep, i)
