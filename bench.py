@@ -150,7 +150,7 @@ def serving_leg(W, seconds):
             "p50_chunk_ms": st["chunk_latency_p50_ms"], "p99_chunk_ms": st["chunk_latency_p99_ms"],
             "p50_first_chunk_ms": st["first_chunk_latency_p50_ms"],
             "p99_first_chunk_ms": st["first_chunk_latency_p99_ms"],
-            "deadline_misses": st["deadline_misses"], "chunks": st["chunks_done"],
+            "deadline_misses": st["deadline_misses"], "p99_lateness_ms": st["lateness_p99_ms"], "chunks": st["chunks_done"],
             "mean_batch": st["mean_batch"], "max_batch": st["max_batch"], "steps": st["steps"],
             "wall_s": wall,
             "latency_note": "chunk latency = chunk ready - job arrival (host clock); deadline = "

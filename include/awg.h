@@ -342,6 +342,8 @@ typedef struct {
     double first_chunk_latency_p50_ms, first_chunk_latency_p99_ms;
     uint64_t deadline_misses;        /* chunks ready after submit + delay + n0 / fs */
     uint64_t pool_free_bytes;
+    double lateness_p50_ms, lateness_p99_ms;  /* chunk ready - (submit + delay + n0 / fs);
+                                                 negative: ready before it is due */
 } awg_server_stats;
 
 /* Start a server (and its scheduler thread) on ctx's device. AWG_E_INVALID for

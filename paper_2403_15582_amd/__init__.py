@@ -88,7 +88,8 @@ class awg_server_stats(ctypes.Structure):
                                                "device_busy_ms", "wall_ms", "chunk_latency_p50_ms",
                                                "chunk_latency_p99_ms", "first_chunk_latency_p50_ms",
                                                "first_chunk_latency_p99_ms")] + \
-               [("deadline_misses", ctypes.c_uint64), ("pool_free_bytes", ctypes.c_uint64)]
+               [("deadline_misses", ctypes.c_uint64), ("pool_free_bytes", ctypes.c_uint64),
+                ("lateness_p50_ms", ctypes.c_double), ("lateness_p99_ms", ctypes.c_double)]
 
 
 class awg_retune(ctypes.Structure):

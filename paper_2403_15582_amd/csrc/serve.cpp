@@ -124,7 +124,9 @@ struct awg_server {
     uint64_t n_submitted = 0, n_admitted = 0, n_jobs_done = 0, n_chunks = 0, n_steps = 0;
     uint64_t n_items_total = 0, max_batch = 0, deadline_misses = 0;
     double tone_samples = 0, busy_ms = 0, t_first_submit = -1, t_last_ready = 0, audio_s = 0;
-    std::vector<double> lat_chunk, lat_first;
+    // device rate (tone-samples per ms) measured on completed steps, for the step work budget
+    double rate_ts_per_ms = 2e9;
+    std::vector<double> lat_chunk, lat_first, lateness;
 };
 
 namespace {
@@ -218,7 +220,15 @@ void harvest(awg_server *s)
         if (q != hipSuccess) { s->error = hipst(q); st.in_flight = false; continue; }
         const double t = now_ms();
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, st.ev_start, st.ev_done) == hipSuccess) s->busy_ms += ms;
+        if (hipEventElapsedTime(&ms, st.ev_start, st.ev_done) == hipSuccess) {
+            s->busy_ms += ms;
+            double work = 0;
+            for (const StepItem &it : st.items) {
+                auto jt = s->jobs.find(it.job);
+                if (jt != s->jobs.end()) work += (double)jt->second.n_tones * (double)it.count;
+            }
+            if (ms > 0.05f && work > 0) s->rate_ts_per_ms = 0.8 * s->rate_ts_per_ms + 0.2 * (work / ms);
+        }
         for (const StepItem &it : st.items) {
             auto jt = s->jobs.find(it.job);
             if (jt == s->jobs.end()) continue;
@@ -244,6 +254,7 @@ void harvest(awg_server *s)
             if (it.chunk == 0) s->lat_first.push_back(t - j.t_submit);
             const double deadline = j.t_submit + s->prm.playout_delay_ms + 1e3 * (double)it.n0 / j.fs;
             if (t > deadline) s->deadline_misses++;
+            s->lateness.push_back(t - deadline);
             s->t_last_ready = t;
             if (ev.last) {
                 pool_free(s, j.off, j.bytes);
@@ -257,7 +268,12 @@ void harvest(awg_server *s)
     }
 }
 
-// Form and launch one step if a step buffer is free and there is work.
+// Form and launch one step if a step buffer is free and there is work. The
+// admitted jobs with a chunk to do are taken earliest deadline first (the
+// deadline of a job's next chunk: arrival + playout delay + chunk start / fs),
+// and a step stops growing at about a quarter of the playout delay of device
+// work (at least 0.5 ms, at the measured rate), so that a chunk that falls due
+// soon does not wait behind a long step; a step always takes at least one chunk.
 bool launch_step(awg_server *s)
 {
     Step *st = nullptr;
@@ -265,16 +281,28 @@ bool launch_step(awg_server *s)
         if (!c.in_flight) { st = &c; break; }
     if (!st) return false;
     st->items.clear();
-    uint32_t tiles = 0;
-    int32_t slot = 0;
-    const int32_t n_slots = (int32_t)s->slot_state.size();
+    std::vector<std::pair<double, Job *>> cand;
     for (auto &kv : s->jobs) {
         Job &j = kv.second;
         if (j.in_flight || j.next_n0 >= j.n_samples) continue;
+        cand.emplace_back(j.t_submit + s->prm.playout_delay_ms + 1e3 * (double)j.next_n0 / j.fs, &j);
+    }
+    std::stable_sort(cand.begin(), cand.end(),
+                     [](const std::pair<double, Job *> &a, const std::pair<double, Job *> &b) { return a.first < b.first; });
+    const double budget = s->rate_ts_per_ms * std::max(0.5, s->prm.playout_delay_ms / 4.0);
+    double work = 0;
+    uint32_t tiles = 0;
+    int32_t slot = 0;
+    const int32_t n_slots = (int32_t)s->slot_state.size();
+    for (auto &c : cand) {
+        Job &j = *c.second;
         if ((int32_t)st->items.size() >= s->prm.max_jobs) break;
         while (slot < n_slots && s->slot_state[slot] != 0) ++slot;
         if (slot >= n_slots) break;                                    // ring full: back-pressure
         const uint64_t count = std::min<uint64_t>(s->prm.chunk_len, j.n_samples - j.next_n0);
+        const double w = (double)j.n_tones * (double)count;
+        if (!st->items.empty() && work + w > budget) break;
+        work += w;
         BatchItem &b = st->h_items[st->items.size()];
         b.tones = j.d_tones;
         b.tables = j.d_tabs;
@@ -526,6 +554,8 @@ awg_status awg_server_stats_get(awg_server *s, awg_server_stats *o)
     o->first_chunk_latency_p50_ms = percentile(s->lat_first, 50);
     o->first_chunk_latency_p99_ms = percentile(s->lat_first, 99);
     o->deadline_misses = s->deadline_misses;
+    o->lateness_p50_ms = percentile(s->lateness, 50);
+    o->lateness_p99_ms = percentile(s->lateness, 99);
     o->pool_free_bytes = 0;
     for (auto &kv : s->free_blocks) o->pool_free_bytes += kv.second;
     return s->error;

@@ -36,6 +36,9 @@ def test_mix_equals_alone_and_oracle():
     say("stats: steps=%d mean_batch=%.1f max_batch=%d p99 chunk latency %.2f ms"
         % (st["steps"], st["mean_batch"], st["max_batch"], st["chunk_latency_p99_ms"]))
     assert st["jobs_done"] == len(jobs) and st["max_batch"] > 1
+    assert st["lateness_p50_ms"] <= st["lateness_p99_ms"]
+    if st["deadline_misses"] == 0:
+        assert st["lateness_p99_ms"] <= 0.0
     for k in keep:
         solo = _solo(torch, jobs[k])
         assert np.array_equal(mixed[k], solo), k
