@@ -98,8 +98,9 @@ def cpu_baseline(w, q_gpu, seconds):
 
 
 def streaming_leg(torch, awg, W):
-    """Config-3 style chirped stream: per-chunk latency and real-time factor."""
-    w = W.config3(shape="mixed")
+    """1000 tones chirped over 35 ms (mixed linear and cosine), streamed in 2^20-sample
+    chunks: per-chunk latency and real-time factor."""
+    w = W.chirp_35ms(shape="mixed")
     plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2)
     s = torch.cuda.current_stream()
     n_chunks = w.count // w.chunk
@@ -132,10 +133,10 @@ def streaming_leg(torch, awg, W):
 
 
 def serving_leg(W, seconds):
-    """Config-5 style trace in real time: Poisson arrivals of chirp jobs, batched
+    """Serving trace in real time: Poisson arrivals of chirp jobs, batched
     by the library's server; latency, throughput and deadline misses."""
     from paper_2403_15582_amd.serving import Server
-    jobs = W.config5(seconds=seconds)
+    jobs = W.poisson_jobs(seconds=seconds)
     with Server(mem_budget_bytes=1 << 30, max_jobs=512, ring_slots=256, playout_delay_ms=5.0) as srv:
         t0 = time.perf_counter()
         srv.run_trace(jobs, time_scale=1.0, timeout_s=300.0)
@@ -158,12 +159,12 @@ def serving_leg(W, seconds):
 
 
 def large_array_leg(torch, awg, W, K, method="direct"):
-    """Config-4 style stream: K tones, groups of 100 retuned (1 ms linear chirps)
+    """Large-array stream: K tones, groups of 100 retuned (1 ms linear chirps)
     in turn, 2^20-sample chunks over 1 s of output; per-chunk device time. With a
     matrix-core method the chunks take the hybrid path (line tones on the matrix
     cores, ramping tones on the direct kernel); the last 12 chunks run again with
     kernel timing on for the per-kernel split."""
-    w = W.config4(K=K)
+    w = W.array_group_chirps(K=K)
     plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, method_codes(awg)[method])
     events = sorted(w.retunes, key=lambda e: e[1])
     n_chunks = w.count // w.chunk
@@ -282,7 +283,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
         return
-    w = W.config2()
+    w = W.static_period()
     K, L = len(w.tones), w.count
     codes = method_codes(awg)
     # auto: BF16 hi/lo x3, the fastest method that keeps the int16 bar (it issues the

@@ -19,8 +19,8 @@ from .abi_types import (TONE_DTYPE, RAMP_NONE, RAMP_LINEAR, RAMP_COSINE, RAMP_MI
 
 FS_280 = 280e6
 CHUNK = 1 << 20
-CONFIG3_RAMP_LEN = 9_800_000          # 35 ms at 280 MS/s
-CONFIG4_RAMP_LEN = 280_000            # 1 ms at 280 MS/s
+RAMP_35MS = 9_800_000          # 35 ms at 280 MS/s
+RAMP_1MS = 280_000            # 1 ms at 280 MS/s
 
 
 @dataclass
@@ -68,7 +68,7 @@ def static_tones(f_hz, amps, phases):
     return t
 
 
-def config1(seed=1):
+def static_100tone_chunk(seed=1):
     """100 static tones, bins of L=2**20 in 75-125 MHz, A=1/100, one 2**20 chunk."""
     r = _rng(seed)
     lo, hi = 280869, 468114
@@ -77,7 +77,7 @@ def config1(seed=1):
     return Workload("static-100tone-2^20", FS_280, 32767.0, 20, tones, 0, CHUNK)
 
 
-def config2(seed=2, K=1000):
+def static_period(seed=2, K=1000):
     """Static periodic buffer: K tones, bins of L=2**24 in 60-140 MHz (Nyquist bin
     excluded), A ~ U[0.5, 1], Schroeder phases by frequency rank, one period."""
     r = _rng(seed)
@@ -98,7 +98,7 @@ def _chirp_ends(r, n, lo, hi, max_step):
     return f0, f1
 
 
-def config3(seed=3, shape="linear", K=1000, ramp_len=CONFIG3_RAMP_LEN, n_chunks=10):
+def chirp_35ms(seed=3, shape="linear", K=1000, ramp_len=RAMP_35MS, n_chunks=10):
     """K tones chirped from f_start ~ U[75,125] MHz by U[-5,5] MHz over 35 ms.
 
     shape: 'linear', 'cosine', 'minjerk', or 'mixed' (seeded coin per tone between
@@ -123,7 +123,7 @@ def config3(seed=3, shape="linear", K=1000, ramp_len=CONFIG3_RAMP_LEN, n_chunks=
                     n_chunks * CHUNK)
 
 
-def config4(seed=4, K=5000, seconds=1.0, group=100, ramp_len=CONFIG4_RAMP_LEN):
+def array_group_chirps(seed=4, K=5000, seconds=1.0, group=100, ramp_len=RAMP_1MS):
     """Large array: K tones on an even grid over 60-140 MHz, A ~ U[0.5,1],
     Schroeder phases; groups of ``group`` consecutive tones (cycling) chirp one
     after another, each by a seeded 0-2 MHz offset of seeded sign over 1 ms
@@ -164,7 +164,7 @@ class Job:
     tones: np.ndarray
 
 
-def config5(seed=5, rate_hz=2000.0, seconds=2.0, kmin=50, kmax=2000,
+def poisson_jobs(seed=5, rate_hz=2000.0, seconds=2.0, kmin=50, kmax=2000,
             dmin_ms=0.1, dmax_ms=35.0, max_jobs=None):
     """Poisson stream of chirp jobs: K ~ round(exp U[ln kmin, ln kmax]), duration
     ~ U[dmin, dmax] ms, fs 50 or 280 MS/s (fair coin), per-tone linear chirps over

@@ -43,16 +43,16 @@ def test_phase_words_bit_exact_small_mixed():
 def test_phase_words_bit_exact_long_ramps():
     torch = need_gpu()
     for shape in ("linear", "cosine", "minjerk"):
-        w = W.config3(shape=shape, K=8)
+        w = W.chirp_35ms(shape=shape, K=8)
         op = oracle_plan(w, tables=False)
         lp = lib_plan(w)
-        N = W.CONFIG3_RAMP_LEN
+        N = W.RAMP_35MS
         for n0 in [0, 12345, N // 2 - 3, N - 700, N - 1, N + 5, 3 * N]:
             count = 1500
             ns = np.arange(n0, n0 + count)
             csynth.sparse_tables(op, ns)
             pk = csynth.Packed(op)
-            say("phase dump config3/%s n0=%d" % (shape, n0))
+            say("phase dump chirp-35ms/%s n0=%d" % (shape, n0))
             for k in range(len(w.tones)):
                 got = to_np(lp.phase_dump(k, n0, count)).view(np.uint64)
                 torch.cuda.synchronize()
@@ -105,16 +105,16 @@ def test_single_tone_and_quarter_rate():
     assert np.array_equal(q, np.tile(np.array([0, 1000, 0, -1000], dtype=np.int16), 1024))
 
 
-def test_config1_full():
+def test_static_100tone_chunk_full():
     torch = need_gpu()
-    w = W.config1()
+    w = W.static_100tone_chunk()
     lp = lib_plan(w)
-    say("config1 full 2^20 x 100")
+    say("static-100tone-chunk full 2^20 x 100")
     q = to_np(lp.synth_static(0, w.count))
     y = to_np(lp.synth_f32(0, w.count))
     torch.cuda.synchronize()
     qo, yo = csynth.synth(oracle_plan(w), 0, w.count)
-    compare(q, y, qo, yo, "config1")
+    compare(q, y, qo, yo, "static-100tone-chunk")
 
 
 def _sample_points(rng, total, extra=()):
@@ -124,11 +124,11 @@ def _sample_points(rng, total, extra=()):
     return np.array(sorted(n for n in ns if 0 <= n < total), dtype=np.int64)
 
 
-def test_config2_full_direct_sampled_and_periodic():
+def test_static_period_full_direct_sampled_and_periodic():
     torch = need_gpu()
-    w = W.config2()
+    w = W.static_period()
     lp = lib_plan(w)
-    say("config2 full 2^24 x 1000 direct")
+    say("static-period full 2^24 x 1000 direct")
     qd = lp.synth_static(0, w.count)
     yd = lp.synth_f32(0, w.count)
     tail = lp.synth_static(w.count, 1 << 16)          # the next period starts over
@@ -137,15 +137,15 @@ def test_config2_full_direct_sampled_and_periodic():
     assert np.array_equal(to_np(tail), q[:1 << 16])
     ns = _sample_points(np.random.default_rng(21), w.count)
     qo, yo = csynth.synth_at(oracle_plan(w), ns)
-    compare(q[ns], y[ns], qo, yo, "config2 direct (sampled %d)" % len(ns))
+    compare(q[ns], y[ns], qo, yo, "static-period direct (sampled %d)" % len(ns))
 
 
 @pytest.mark.parametrize("shape", ["linear", "cosine", "minjerk", "mixed"])
-def test_config3_streamed_equals_oneshot_and_oracle(shape):
+def test_chirp_35ms_streamed_equals_oneshot_and_oracle(shape):
     torch = need_gpu()
-    w = W.config3(shape=shape)
+    w = W.chirp_35ms(shape=shape)
     lp = lib_plan(w)
-    say("config3/%s streamed 10 x 2^20 x 1000" % shape)
+    say("chirp-35ms/%s streamed 10 x 2^20 x 1000" % shape)
     chunks = []
     for c in range(w.count // w.chunk):
         n0, out = lp.stream_next(w.chunk)
@@ -157,12 +157,12 @@ def test_config3_streamed_equals_oneshot_and_oracle(shape):
     torch.cuda.synchronize()
     assert torch.equal(streamed, oneshot)
     q, yv = to_np(oneshot), to_np(y)
-    N = W.CONFIG3_RAMP_LEN
+    N = W.RAMP_35MS
     ns = _sample_points(np.random.default_rng(31), w.count, range(N - 300, N + 300))
     op = oracle_plan(w, tables=False)
     csynth.sparse_tables(op, ns)
     qo, yo = csynth.synth_at(op, ns)
-    compare(q[ns], yv[ns], qo, yo, "config3/%s (sampled %d)" % (shape, len(ns)))
+    compare(q[ns], yv[ns], qo, yo, "chirp-35ms/%s (sampled %d)" % (shape, len(ns)))
 
 
 def test_irregular_chunks_and_resume_bit_identical():
@@ -185,11 +185,11 @@ def test_irregular_chunks_and_resume_bit_identical():
 
 def test_retune_stream_matches_oracle():
     torch = need_gpu()
-    w = W.config4(K=1000, seconds=0.02, group=100)
+    w = W.array_group_chirps(K=1000, seconds=0.02, group=100)
     lp = lib_plan(w)
     op = oracle_plan(w, tables=False)
     events = sorted(w.retunes, key=lambda e: e[1])
-    say("config4-small retuned stream: %d retunes" % len(events))
+    say("array-small retuned stream: %d retunes" % len(events))
     outs = []
     i = 0
     n_chunks = w.count // w.chunk
@@ -215,21 +215,21 @@ def test_retune_stream_matches_oracle():
     q = to_np(torch.cat(outs))
     torch.cuda.synchronize()
     ns = _sample_points(np.random.default_rng(41), n_chunks * w.chunk,
-                        [e[1] + d for e in events[::37] for d in (-1, 0, 1, 2, 140000, W.CONFIG4_RAMP_LEN)])
+                        [e[1] + d for e in events[::37] for d in (-1, 0, 1, 2, 140000, W.RAMP_1MS)])
     qo, yo = csynth.synth_at(op, ns)
-    compare(q[ns], None, qo, yo, "config4-small (sampled %d)" % len(ns))
+    compare(q[ns], None, qo, yo, "array-small (sampled %d)" % len(ns))
 
 
 @pytest.mark.parametrize("K", [5000, 10000])
-def test_config4_full_second_streamed(K):
+def test_array_group_chirps_full_second_streamed(K):
     """Large array: 1 s at 280 MS/s (268 chunks), groups of 100 tones retuned in turn."""
     torch = need_gpu()
-    w = W.config4(K=K)
+    w = W.array_group_chirps(K=K)
     lp = lib_plan(w)
     op = oracle_plan(w, tables=False)
     events = sorted(w.retunes, key=lambda e: e[1])
     n_chunks = w.count // w.chunk
-    say("config4 K=%d: %d chunks, %d retunes" % (K, n_chunks, len(events)))
+    say("array K=%d: %d chunks, %d retunes" % (K, n_chunks, len(events)))
     rng = np.random.default_rng(K)
     picks = sorted(set([0, 1, 2, n_chunks // 2, n_chunks - 1]) | set(rng.integers(0, n_chunks, 4).tolist()))
     kept = {}
@@ -253,8 +253,8 @@ def test_config4_full_second_streamed(K):
         q = to_np(kept[c])
         base = c * w.chunk
         ns = np.unique(np.concatenate([rng.integers(0, w.chunk, 400), [0, 1, w.chunk - 1]]))
-        ramp_edges = [e[1] - base + d for e in events for d in (-1, 0, 1, W.CONFIG4_RAMP_LEN)
+        ramp_edges = [e[1] - base + d for e in events for d in (-1, 0, 1, W.RAMP_1MS)
                       if 0 <= e[1] - base + d < w.chunk]
         ns = np.unique(np.concatenate([ns, np.array(ramp_edges[:200], dtype=np.int64)]))
         qo, yo = csynth.synth_at(op, ns + base, packed=pk)
-        compare(q[ns], None, qo, yo, "config4 K=%d chunk %d (sampled %d)" % (K, c, len(ns)))
+        compare(q[ns], None, qo, yo, "array K=%d chunk %d (sampled %d)" % (K, c, len(ns)))

@@ -62,17 +62,17 @@ def test_short_request_is_the_direct_kernel():
 
 
 @pytest.mark.parametrize("shape", ["linear", "mixed"])
-def test_config3_inside_windows_identical_to_direct(shape):
+def test_chirp_35ms_inside_windows_identical_to_direct(shape):
     """While every tone ramps over the whole chunk the product has no entries and
     the hybrid launch is the direct kernel on the same list: bit-identical. The
     chunk where the windows close is split and stays within 1 LSB."""
     torch = need_gpu()
-    w = W.config3(shape=shape)
+    w = W.chirp_35ms(shape=shape)
     hp, dp = _plans(w, F16)
-    N = W.CONFIG3_RAMP_LEN
+    N = W.RAMP_35MS
     for c in (0, 4, N // w.chunk):
         n0 = c * w.chunk
-        say("config3/%s chunk %d hybrid vs direct" % (shape, c))
+        say("chirp-35ms/%s chunk %d hybrid vs direct" % (shape, c))
         a = to_np(hp.synth_chirp(n0, w.chunk))
         b = to_np(dp.synth_chirp(n0, w.chunk))
         torch.cuda.synchronize()
@@ -90,22 +90,22 @@ def test_config3_inside_windows_identical_to_direct(shape):
             y = to_np(hp.synth_f32(n0, w.chunk, method=F16))
             torch.cuda.synchronize()
             qo, yo = csynth.synth_at(op, ns)
-            compare(a[ns - n0], y[ns - n0], qo, yo, "config3/%s closing chunk hybrid (sampled %d)" % (shape, len(ns)))
+            compare(a[ns - n0], y[ns - n0], qo, yo, "chirp-35ms/%s closing chunk hybrid (sampled %d)" % (shape, len(ns)))
 
 
 @pytest.mark.parametrize("method", [F16, BF16])
-def test_config4_stream_against_direct_and_oracle(method):
+def test_array_group_chirps_stream_against_direct_and_oracle(method):
     """10,000 tones, a group of 100 retuned every 1 ms: 14 chunks of 2^20 streamed
     with the hybrid and the direct method side by side, every sample compared;
     two chunks also against the oracle, with the unquantised sum."""
     torch = need_gpu()
     K = 10000
-    w = W.config4(K=K, seconds=0.05)
+    w = W.array_group_chirps(K=K, seconds=0.05)
     hp, dp = _plans(w, method)
     op = words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones, build_tables=False)
     events = sorted(w.retunes, key=lambda e: e[1])
     n_chunks = w.count // w.chunk
-    say("config4 K=%d hybrid method=%d: %d chunks, %d retunes" % (K, method, n_chunks, len(events)))
+    say("array K=%d hybrid method=%d: %d chunks, %d retunes" % (K, method, n_chunks, len(events)))
     i = 0
     checks = {3, n_chunks - 1}
     for c in range(n_chunks):
@@ -132,13 +132,13 @@ def test_config4_stream_against_direct_and_oracle(method):
                                            [e[1] - n0 + d for e in events[:: 25] for d in (-1, 0, 1, e[2], e[2] + 1)
                                             if 0 <= e[1] - n0 + d < w.chunk]]))
             qo, yo = csynth.synth_at(op, ns + n0)
-            compare(a[ns], to_np(yh)[ns], qo, yo, "config4 hybrid chunk %d (sampled %d)" % (c, len(ns)))
-    say("config4 hybrid: all %d chunks within %d LSB of the direct method" % (n_chunks, TOL_Q))
+            compare(a[ns], to_np(yh)[ns], qo, yo, "array hybrid chunk %d (sampled %d)" % (c, len(ns)))
+    say("array hybrid: all %d chunks within %d LSB of the direct method" % (n_chunks, TOL_Q))
 
 
 def test_static_plan_chirp_call_uses_matrix_cores():
     torch = need_gpu()
-    w = W.config1()
+    w = W.static_100tone_chunk()
     p = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, F16)
     a = p.synth_chirp(0, w.count)
     b = p.synth_static(0, w.count)

@@ -27,20 +27,20 @@ def _pts(rng, n0, count, extra=()):
 
 
 @pytest.mark.parametrize("method", [F16, BF16])
-def test_config2_full_mfma(method):
+def test_static_period_full_mfma(method):
     torch = need_gpu()
-    w = W.config2()
+    w = W.static_period()
     lp = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, method)
-    say("config2 full 2^24 x 1000 mfma method=%d" % method)
+    say("static-period full 2^24 x 1000 mfma method=%d" % method)
     q = to_np(lp.synth_static(0, w.count))
     y = to_np(lp.synth_f32(0, w.count, method=method))
     torch.cuda.synchronize()
     ns = _pts(np.random.default_rng(51), 0, w.count, range(4090, 4100))
     qo, yo = csynth.synth_at(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), ns)
     compare(q[ns - 0], y[ns] if method == F16 else None, qo, yo,
-            "config2 mfma method=%d (sampled %d)" % (method, len(ns)))
+            "static-period mfma method=%d (sampled %d)" % (method, len(ns)))
     dy = np.abs(y[ns].astype(np.float64) - yo)
-    say("config2 mfma method=%d unquantised max|dy| = %.4f LSB, rms %.5f" %
+    say("static-period mfma method=%d unquantised max|dy| = %.4f LSB, rms %.5f" %
         (method, dy.max(), np.sqrt(np.mean(dy ** 2))))
 
 
@@ -48,7 +48,7 @@ def test_config2_full_mfma(method):
                                       (0, 5000)])
 def test_mfma_ragged_ranges(n0, count):
     torch = need_gpu()
-    w = W.config2(K=333)
+    w = W.static_period(K=333)
     lp = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, F16)
     say("mfma ragged n0=%d count=%d K=333" % (n0, count))
     q = to_np(lp.synth_static(n0, count))
@@ -62,7 +62,7 @@ def test_mfma_ragged_ranges(n0, count):
 def test_mfma_peak_gain():
     """Gain raised so the buffer peaks near 90% of full scale (Schroeder phases)."""
     torch = need_gpu()
-    w = W.config2()
+    w = W.static_period()
     op1 = words.Plan(w.fs_hz, 1.0, w.period_log2, w.tones)
     _, y1 = csynth.synth(op1, 0, 1 << 16)
     gain = 0.9 * 32767.0 / float(np.max(np.abs(y1)))
@@ -84,14 +84,14 @@ def test_mfma_peak_gain():
 
 def test_mfma_equals_direct_within_one_lsb_everywhere():
     torch = need_gpu()
-    w = W.config1()
+    w = W.static_100tone_chunk()
     a = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, F16)
     b = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, awg.AWG_F_METHOD_DIRECT)
     qa = to_np(a.synth_static(0, w.count))
     qb = to_np(b.synth_static(0, w.count))
     torch.cuda.synchronize()
     qo, _ = csynth.synth(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), 0, w.count)
-    compare(qa, None, qo, None, "config1 mfma vs oracle (all samples)")
+    compare(qa, None, qo, None, "static-100tone-chunk mfma vs oracle (all samples)")
     assert np.max(np.abs(qa.astype(np.int32) - qb.astype(np.int32))) <= 2
 
 
@@ -101,7 +101,7 @@ def test_two_streams_on_one_plan(ramped):
     workspace is shared and ordered between them) equal the same calls run one
     after the other."""
     torch = need_gpu()
-    w = W.config4(K=600, seconds=0.01) if ramped else W.config1()
+    w = W.array_group_chirps(K=600, seconds=0.01) if ramped else W.static_100tone_chunk()
     p = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, BF16)
     if ramped:
         p.retune([(k, sh, a, n, f) for k, a, n, sh, f in sorted(w.retunes, key=lambda e: e[1])[:100]])

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _channel_plans():
-    ws = [W.small_mixed(seed=11, n_total=20000), W.config1(), W.small_mixed(seed=13, K=40, n_total=20000)]
+    ws = [W.small_mixed(seed=11, n_total=20000), W.static_100tone_chunk(), W.small_mixed(seed=13, K=40, n_total=20000)]
     return ws, [awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2) for w in ws]
 
 

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _jobs(n, seed=5, dmax_ms=6.0):
-    return W.config5(seed=seed, max_jobs=n, dmax_ms=dmax_ms, kmax=800)
+    return W.poisson_jobs(seed=seed, max_jobs=n, dmax_ms=dmax_ms, kmax=800)
 
 
 def _solo(torch, job):

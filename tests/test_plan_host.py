@@ -58,10 +58,10 @@ def _compare_words(w):
         assert fq[k] == pytest.approx(tw.f0 * w.fs_hz / 2.0 ** 64, rel=1e-15)
 
 
-@pytest.mark.parametrize("maker", [W.config1, W.config2, lambda: W.config3(shape="mixed"),
-                                   lambda: W.config3(shape="minjerk", K=50),
+@pytest.mark.parametrize("maker", [W.static_100tone_chunk, W.static_period, lambda: W.chirp_35ms(shape="mixed"),
+                                   lambda: W.chirp_35ms(shape="minjerk", K=50),
                                    lambda: W.small_mixed(), lambda: W.small_mixed(seed=3, period_log2=16),
-                                   lambda: W.config4(K=5000, seconds=0.01)])
+                                   lambda: W.array_group_chirps(K=5000, seconds=0.01)])
 def test_plan_words_equal_oracle(maker):
     _compare_words(maker())
 
@@ -96,7 +96,7 @@ def test_ramp_tables_equal_oracle(shape, n):
 
 @pytest.mark.parametrize("shape", [awg.RAMP_COSINE, awg.RAMP_MINJERK])
 def test_ramp_table_full_size_samples(shape):
-    n = W.CONFIG3_RAMP_LEN
+    n = W.RAMP_35MS
     lt = awg.awg_ramp_table(shape, n)
     rng = np.random.default_rng(8)
     ds = sorted(set(rng.integers(0, n + 1, 300).tolist()) | {0, 1, n // 2, n - 1, n})
@@ -172,7 +172,7 @@ def test_host_only_plan_rejects_synthesis():
 
 
 def test_retune_words_follow_oracle_chain():
-    w = W.config4(K=300, seconds=0.004, group=100)
+    w = W.array_group_chirps(K=300, seconds=0.004, group=100)
     plan, _ = _host_plan(w)
     op = words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones)
     try:
@@ -199,7 +199,7 @@ def test_retune_words_follow_oracle_chain():
 def test_amplitude_ramp_validation_and_counts():
     """awg_plan_amplitude on a host-only plan: argument checks, chaining rules, and the
     plan counts a tone with an amplitude window as dynamic (no static fast path)."""
-    w = W.config1()
+    w = W.static_100tone_chunk()
     plan, _ = _host_plan(w)
     try:
         assert awg.awg_plan_info_get(plan)["n_ramped"] == 0
