@@ -41,9 +41,12 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--method", default="auto", choices=["auto", "direct", "mfma-f16", "mfma-bf16"])
+    ap.add_argument("--time-every", type=int, default=8,
+                    help="time one launch in N of each kernel with HIP events inside the timed steps "
+                         "(a timed launch costs the stream a few microseconds)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming, serving and large-array legs")
@@ -313,7 +316,7 @@ def main():
                     torch.cuda.synchronize()
             torch.cuda.synchronize()
             awg.awg_profile_read(ctx, reset=True)
-            awg.awg_profile_enable(ctx, True)
+            awg.awg_profile_enable(ctx, max(1, a.time_every))
             ms, wall = timed_steps(torch, step, a.steps, 0)
             awg.awg_profile_enable(ctx, False)
             stats = awg.awg_profile_read(ctx, reset=True)
@@ -334,7 +337,10 @@ def main():
                    "rtf": (L / w.fs_hz) / (ms * 1e-3),
                    "roofline": roofline_for(m, stats, K, L),
                    "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(1, v[0])}
-                               for k, v in stats.items()}}
+                               for k, v in stats.items()},
+                   "kernel_timing": "HIP events recorded by the dispatch of one launch in %d of each "
+                                    "kernel inside the timed steps (launches = timed launches)"
+                                    % max(1, a.time_every)}
         plan.close()
     res["methods"] = per_method
     if not a.no_cpu_baseline:

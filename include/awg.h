@@ -377,7 +377,12 @@ typedef struct {
     double max_ms;
 } awg_kernel_stat;
 
-/* Switch event timing on or off for all calls on plans of ctx (off by default). */
+/* Event timing of the kernels of all calls on plans of ctx (off by default):
+ * enable = 0 switches it off; enable = n >= 1 times one launch in n of each
+ * kernel (the 1st, n+1-th, ... since this call; 1 = every launch). A timed
+ * launch costs the stream some microseconds (the dispatch records its start
+ * and stop events), so sampling keeps the overhead of a long run small.
+ * AWG_E_INVALID for enable < 0. */
 awg_status awg_profile_enable(awg_ctx *ctx, int32_t enable);
 /* Synchronise the recorded events and return up to max_stats per-kernel totals
  * in out (host array); *n_stats receives the number of distinct kernels. With

@@ -383,7 +383,8 @@ def awg_phase_dump(plan, tone, n0, count, d_words, stream=0):
 
 
 def awg_profile_enable(ctx, enable=True):
-    _check(lib().awg_profile_enable(ctx, 1 if enable else 0), "awg_profile_enable")
+    """enable: False / 0 = off, True / 1 = every launch, n = one launch in n per kernel."""
+    _check(lib().awg_profile_enable(ctx, int(enable)), "awg_profile_enable")
 
 
 def awg_profile_read(ctx, reset=False):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -128,9 +129,10 @@ struct ProfTotal { uint64_t launches; double total_ms, max_ms; };
 struct awg_ctx {
     int device;
     std::mutex mu;
-    // kernel timing (awg_profile_*)
-    bool profiling;
+    // kernel timing (awg_profile_*): 0 = off, n = one launch in n of each kernel
+    std::atomic<int32_t> prof_period{0};
     std::mutex prof_mu;
+    std::map<std::string, uint64_t> prof_seen;   // launches per kernel since enable
     std::vector<awg::ProfRecord> prof_pending;
     std::vector<hipEvent_t> prof_pool;
     std::map<std::string, awg::ProfTotal> prof_totals;
@@ -192,16 +194,25 @@ void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vecto
 // Device table H_N of a smooth shape, created once per context (capi.cpp).
 awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d_out);
 
-// Records HIP events around one kernel launch when the context profiles.
+// Per-kernel timing when the context profiles: the scope's kernels are launched
+// through launch() (defined in prof_launch.h, for the HIP sources), which hands
+// the start event to the first launch and the stop event to every launch, so
+// the dispatches themselves take the timestamps (no marker packets between
+// kernels). A scope whose kernel never launched records nothing.
 class ProfScope {
 public:
     ProfScope(awg_ctx *ctx, hipStream_t s, const char *name);
     ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+    template <typename F, typename... Args>
+    void launch(F kernel, dim3 grid, dim3 block, uint32_t shmem, Args... args);
 private:
     awg_ctx *ctx_;
     hipStream_t s_;
     const char *name_;
-    hipEvent_t start_;
+    hipEvent_t start_, stop_;
+    bool launched_;
 };
 
 // Kernel launchers (direct.hip, mfma.hip). Return a HIP error code.
@@ -218,7 +229,7 @@ hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint
 // Multiplexed channels: items[c] (c < n, n <= kMaxChannels) each cover the same
 // count samples; one launch, items passed by value.
 constexpr int kMaxChannels = 4;
-hipError_t launch_mux(const BatchItem *items, int32_t n, uint64_t count, hipStream_t s);
+hipError_t launch_mux(const BatchItem *items, int32_t n, uint64_t count, hipStream_t s, ProfScope &prof);
 // MFMA static synthesis; out_i16 or out_f32 (exactly one non-null).
 awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count,
                        int16_t *out_i16, float *out_f32, hipStream_t s);

@@ -214,7 +214,6 @@ awg_status awg_ctx_create(int device, awg_ctx **out)
     if (!c) return AWG_E_NOMEM;
     c->device = device;
     c->upload_stream = nullptr;
-    c->profiling = false;
     *out = c;
     return AWG_OK;
 }
@@ -672,7 +671,7 @@ awg_status awg_synth_multiplex(awg_plan *const *plans, int32_t n_channels, uint6
     if (count == 0) return AWG_OK;
     if (!d_out) return AWG_E_INVALID;
     ProfScope prof(plans[0]->ctx, (hipStream_t)hip_stream, "mux_kernel");
-    return hip_status(launch_mux(items, n_channels, count, (hipStream_t)hip_stream));
+    return hip_status(launch_mux(items, n_channels, count, (hipStream_t)hip_stream, prof));
 }
 
 awg_status awg_stream_next_multiplex(awg_plan *const *plans, int32_t n_channels, uint64_t count, int16_t *d_out,

@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "awg_internal.h"
+#include "prof_launch.h"
 
 namespace awg {
 
@@ -555,11 +556,11 @@ static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, 
         {
             ProfScope prof(p->ctx, s, F32OUT ? "direct_kernel_f32" : "direct_kernel");
             if (p->n_ramped == 0)
-                hipLaunchKernelGGL((direct_kernel<kS, F32OUT, true>), dim3((uint32_t)now_tiles), dim3(256), 0, s,
-                                   p->d_tones, p->d_blocks, p->d_table_ptrs, n0, now, out);
+                prof.launch(direct_kernel<kS, F32OUT, true>, dim3((uint32_t)now_tiles), dim3(256), 0, p->d_tones,
+                            p->d_blocks, p->d_table_ptrs, n0, now, out);
             else
-                hipLaunchKernelGGL((direct_kernel<kS, F32OUT, false>), dim3((uint32_t)now_tiles), dim3(256), 0,
-                                   s, p->d_tones, p->d_blocks, p->d_table_ptrs, n0, now, out);
+                prof.launch(direct_kernel<kS, F32OUT, false>, dim3((uint32_t)now_tiles), dim3(256), 0, p->d_tones,
+                            p->d_blocks, p->d_table_ptrs, n0, now, out);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return e;
@@ -591,8 +592,8 @@ hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint6
         hipError_t e;
         {
             ProfScope prof(p->ctx, s, "phase_dump_kernel");
-            hipLaunchKernelGGL(phase_dump_kernel<kS>, dim3((uint32_t)now_tiles), dim3(64), 0, s,
-                               p->d_tones, tone, p->d_table_ptrs, n0, now, out);
+            prof.launch(phase_dump_kernel<kS>, dim3((uint32_t)now_tiles), dim3(64), 0, p->d_tones, tone,
+                        p->d_table_ptrs, n0, now, out);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return e;
@@ -614,13 +615,11 @@ hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const
     if (tiles > kMaxTilesPerLaunch) return hipErrorInvalidValue;
     ProfScope prof(p->ctx, s, out_f32 ? "direct_hybrid_kernel_f32" : "direct_hybrid_kernel");
     if (out_f32)
-        hipLaunchKernelGGL((direct_hybrid_kernel<kS, true>), dim3((uint32_t)tiles), dim3(256), 0, s, d_tones,
-                           d_blocks, d_order, p->d_table_ptrs, n0, count, (void *)out_f32, planes, n_planes,
-                           plane_stride);
+        prof.launch(direct_hybrid_kernel<kS, true>, dim3((uint32_t)tiles), dim3(256), 0, d_tones, d_blocks, d_order,
+                    p->d_table_ptrs, n0, count, (void *)out_f32, planes, n_planes, plane_stride);
     else
-        hipLaunchKernelGGL((direct_hybrid_kernel<kS, false>), dim3((uint32_t)tiles), dim3(256), 0, s, d_tones,
-                           d_blocks, d_order, p->d_table_ptrs, n0, count, (void *)out_i16, planes, n_planes,
-                           plane_stride);
+        prof.launch(direct_hybrid_kernel<kS, false>, dim3((uint32_t)tiles), dim3(256), 0, d_tones, d_blocks,
+                    d_order, p->d_table_ptrs, n0, count, (void *)out_i16, planes, n_planes, plane_stride);
     return hipGetLastError();
 }
 
@@ -656,7 +655,7 @@ hipError_t launch_peak(const float *d_y, uint64_t count, float *d_peak, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_mux(const BatchItem *items, int32_t n, uint64_t count, hipStream_t s)
+hipError_t launch_mux(const BatchItem *items, int32_t n, uint64_t count, hipStream_t s, ProfScope &prof)
 {
     constexpr uint64_t T = kLanes * kS;
     if (n < 1 || n > kMaxChannels) return hipErrorInvalidValue;
@@ -667,7 +666,8 @@ hipError_t launch_mux(const BatchItem *items, int32_t n, uint64_t count, hipStre
         const uint64_t now_tiles = tiles < kMaxTilesPerLaunch ? tiles : kMaxTilesPerLaunch;
         const uint64_t now = now_tiles * T < count ? now_tiles * T : count;
         for (int c = 0; c < n; ++c) args.items[c].count = now;
-        hipLaunchKernelGGL(mux_kernel<kS>, dim3((uint32_t)now_tiles, (uint32_t)n), dim3(256), 0, s, args);
+        (void)s;
+        prof.launch(mux_kernel<kS>, dim3((uint32_t)now_tiles, (uint32_t)n), dim3(256), 0, args);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         count -= now;

@@ -31,6 +31,7 @@
 #include <type_traits>
 
 #include "awg_internal.h"
+#include "prof_launch.h"
 
 namespace awg {
 
@@ -216,8 +217,9 @@ constexpr int vmcnt_imm(int v) { return (v & 0xf) | ((v >> 4) << 14) | (0x7 << 4
 // the tile needs 32 fragments (A hi/lo for 8 row blocks, B hi/lo for 8 column
 // blocks, 1 KB each); every wave copies 32/(WR*WC) of them straight from global
 // memory into LDS (global_load_lds_dwordx4, lane i -> bytes 16i..16i+15 of a
-// fragment). NST LDS stages, prefetch distance NST-1: block kb+NST-1 is in
+// fragment), into NST LDS stages, prefetch distance NST-1: block kb+NST-1 is in
 // flight while block kb is multiplied. vmcnt counts the copies in issue order.
+//
 // Split K: the grid's z index z sums k-blocks [z*kb_split, (z+1)*kb_split) and
 // writes its partial sums to plane z of the FP32 output (plane elements apart).
 template <typename T, bool F32OUT, int WR, int WC, int NST>
@@ -284,22 +286,13 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-#pragma unroll
-    for (int s = 0; s < NST - 1; ++s)
-        if (s < kb_cnt) issue(s);
-    for (int kb = 0; kb < kb_cnt; ++kb) {
-        // own copies of block kb landed, then a bare barrier (no fence: later
-        // blocks stay in flight) makes every wave's copies visible
-        if (kb + NST - 2 < kb_cnt) __builtin_amdgcn_s_waitcnt(vmcnt_imm(F * (NST - 2)));
-        else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-        asm volatile("s_barrier" ::: "memory");
-        if (kb + NST - 1 < kb_cnt) issue(kb + NST - 1);
+    // this wave's fragments of block kb: A hi (fa), B hi (fb), B lo (xb), A lo (xa)
+    auto read = [&](int kb, V *fa, V *fb, V *xb, V *xa) {
         const char *st = lds + (kb % NST) * kStage;
         const V *ah = (const V *)(st + 0 * kOperand) + TI * wr * 64 + lane;
         const V *al = (const V *)(st + 1 * kOperand) + TI * wr * 64 + lane;
         const V *bh = (const V *)(st + 2 * kOperand) + TJ * wc * 64 + lane;
         const V *bl = (const V *)(st + 3 * kOperand) + TJ * wc * 64 + lane;
-        V fa[TI], fb[TJ], xa[TI], xb[TJ];
 #pragma unroll
         for (int i = 0; i < TI; ++i) fa[i] = ah[i * 64];
 #pragma unroll
@@ -308,6 +301,9 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
         for (int j = 0; j < TJ; ++j) xb[j] = bl[j * 64];
 #pragma unroll
         for (int i = 0; i < TI; ++i) xa[i] = al[i * 64];
+    };
+    // hi*hi, then hi*lo, then lo*hi
+    auto multiply = [&](const V *fa, const V *fb, const V *xb, const V *xa) {
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -320,6 +316,21 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
         for (int i = 0; i < TI; ++i)
 #pragma unroll
             for (int j = 0; j < TJ; ++j) acc[i][j] = mfma<T>(xa[i], fb[j], acc[i][j]);
+    };
+
+#pragma unroll
+    for (int s = 0; s < NST - 1; ++s)
+        if (s < kb_cnt) issue(s);
+    for (int kb = 0; kb < kb_cnt; ++kb) {
+        // own copies of block kb landed, then a bare barrier (no fence: later
+        // blocks stay in flight) makes every wave's copies visible
+        if (kb + NST - 2 < kb_cnt) __builtin_amdgcn_s_waitcnt(vmcnt_imm(F * (NST - 2)));
+        else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        asm volatile("s_barrier" ::: "memory");
+        if (kb + NST - 1 < kb_cnt) issue(kb + NST - 1);
+        V fa[TI], fb[TJ], xa[TI], xb[TJ];
+        read(kb, fa, fb, xb, xa);
+        multiply(fa, fb, xb, xa);
     }
 
     // epilogue: reg v of lane l in tile (i, j) is row 8(v/4) + 4(l/32) + v%4, column l%32
@@ -343,7 +354,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
 
 // Launch one GEMM variant (waves WR x WC, NST LDS stages).
 template <typename T, int WR, int WC, int NST>
-static hipError_t launch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *a_lo, const T *b_hi,
+static hipError_t launch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T *a_lo, const T *b_hi,
                               const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
                               uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32)
 {
@@ -359,18 +370,17 @@ static hipError_t launch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *
         attr_set = true;
     }
     if (out_f32)
-        hipLaunchKernelGGL((angle_gemm_kernel<T, true, WR, WC, NST>), grid, dim3(64 * WR * WC), kLds, s, a_hi,
-                           a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_f32);
+        prof.launch(angle_gemm_kernel<T, true, WR, WC, NST>, grid, dim3(64 * WR * WC), (uint32_t)kLds, a_hi,
+                    a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_f32);
     else
-        hipLaunchKernelGGL((angle_gemm_kernel<T, false, WR, WC, NST>), grid, dim3(64 * WR * WC), kLds, s, a_hi,
-                           a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_i16);
+        prof.launch(angle_gemm_kernel<T, false, WR, WC, NST>, grid, dim3(64 * WR * WC), (uint32_t)kLds, a_hi,
+                    a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_i16);
     return hipGetLastError();
 }
 
-// GEMM variant: 0 = 4 waves / 2 stages, 1 = 4 waves / 3 stages, 2 = 8 waves / 2 stages,
-// 3 = 8 waves / 3 stages, 4 = 8 waves / 4 stages, 5 = 8 waves / 5 stages (160 KB
-// of LDS). The default is the fastest measured on MI355X; the environment
-// variable AWG_GEMM_VARIANT overrides it for tuning sweeps.
+// GEMM variant (waves, LDS stages): 0 = 4 / 2, 1 = 4 / 3, 2 = 8 / 2, 3 = 8 / 3,
+// 4 = 8 / 4, 5 = 8 / 5 (160 KB of LDS). The default is the fastest measured on
+// MI355X; the environment variable AWG_GEMM_VARIANT overrides it for tuning sweeps.
 static int gemm_variant()
 {
     static int v = -1;
@@ -382,18 +392,22 @@ static int gemm_variant()
 }
 
 template <typename T>
-static hipError_t dispatch_gemm(dim3 grid, hipStream_t s, const T *a_hi, const T *a_lo, const T *b_hi,
+static hipError_t dispatch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T *a_lo, const T *b_hi,
                                 const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
                                 uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32)
 {
+#define AWG_GEMM(WR, WC, NST)                                                                                  \
+    return launch_gemm<T, WR, WC, NST>(grid, prof, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, \
+                                       mcols, count, out_i16, out_f32)
     switch (gemm_variant()) {
-    case 0: return launch_gemm<T, 2, 2, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
-    case 1: return launch_gemm<T, 2, 2, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
-    case 2: return launch_gemm<T, 2, 4, 2>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
-    case 4: return launch_gemm<T, 2, 4, 4>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
-    case 5: return launch_gemm<T, 2, 4, 5>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
-    default: return launch_gemm<T, 2, 4, 3>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, out_i16, out_f32);
+    case 0: AWG_GEMM(2, 2, 2);
+    case 1: AWG_GEMM(2, 2, 3);
+    case 2: AWG_GEMM(2, 4, 2);
+    case 4: AWG_GEMM(2, 4, 4);
+    case 5: AWG_GEMM(2, 4, 5);
+    default: AWG_GEMM(2, 4, 3);
     }
+#undef AWG_GEMM
 }
 
 static awg_status hipst(hipError_t e)
@@ -447,17 +461,16 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     if (e != hipSuccess) return hipst(e);
     {
         ProfScope prof(p->ctx, s, f16 ? "gen_a_kernel_f16" : "gen_a_kernel_bf16");
-        hipLaunchKernelGGL((gen_a_kernel<T>), dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, s,
-                           p->d_tones, (const uint32_t *)nullptr, p->n_tones, 2 * kb_n, n0, mcols, rb_pad, a_hi,
-                           a_lo);
+        prof.launch(gen_a_kernel<T>, dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, p->d_tones,
+                    (const uint32_t *)nullptr, p->n_tones, 2 * kb_n, n0, mcols, rb_pad, a_hi, a_lo);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return hipst(e);
     const uint64_t b_key = (mcols << 8) | (f16 ? 1u : 2u) | ((uint64_t)kb_n << 32);
     if (p->mfma_b_key != b_key) {
         ProfScope prof(p->ctx, s, f16 ? "gen_b_kernel_f16" : "gen_b_kernel_bf16");
-        hipLaunchKernelGGL((gen_b_kernel<T>), dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, s,
-                           p->d_tones, (const uint32_t *)nullptr, p->n_tones, 2 * kb_n, cb_n, b_hi, b_lo);
+        prof.launch(gen_b_kernel<T>, dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, p->d_tones,
+                    (const uint32_t *)nullptr, p->n_tones, 2 * kb_n, cb_n, b_hi, b_lo, (const int32_t *)nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return hipst(e);
         p->mfma_b_key = b_key;
@@ -465,8 +478,8 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     dim3 grid((uint32_t)(cb_n / kTileCB), (uint32_t)(rb_pad / kTileRB));
     {
         ProfScope prof(p->ctx, s, f16 ? "angle_gemm_kernel_f16" : "angle_gemm_kernel_bf16");
-        e = dispatch_gemm<T>(grid, s, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_n, 0, mcols, count, out_i16,
-                             out_f32);
+        e = dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_n, 0, mcols, count,
+                             out_i16, out_f32);
     }
     if (e == hipSuccess) e = hipEventRecord(p->work_done, s);
     if (e == hipSuccess) p->work_used = true;
@@ -510,23 +523,22 @@ static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_
     hipError_t e;
     {
         ProfScope prof(p->ctx, s, f16 ? "hyb_gen_a_f16" : "hyb_gen_a_bf16");
-        hipLaunchKernelGGL((gen_a_kernel<T>), dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, s,
-                           p->d_tones, d_entries, n_entries, 2 * g.kb_n, n0, mcols, g.rb_pad, a_hi, a_lo);
+        prof.launch(gen_a_kernel<T>, dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, p->d_tones,
+                    d_entries, n_entries, 2 * g.kb_n, n0, mcols, g.rb_pad, a_hi, a_lo);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     if (b_threads > 0) {
         ProfScope prof(p->ctx, s, f16 ? "hyb_gen_b_f16" : "hyb_gen_b_bf16");
-        hipLaunchKernelGGL((gen_b_kernel<T>), dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, s,
-                           p->d_tones, d_entries, n_entries, 2 * (d_blocks ? n_blocks : g.kb_n), g.cb_n, b_hi,
-                           b_lo, d_blocks);
+        prof.launch(gen_b_kernel<T>, dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, p->d_tones,
+                    d_entries, n_entries, 2 * (d_blocks ? n_blocks : g.kb_n), g.cb_n, b_hi, b_lo, d_blocks);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     dim3 grid((uint32_t)(g.cb_n / kTileCB), (uint32_t)(g.rb_pad / kTileRB), (uint32_t)g.gz);
     ProfScope prof(p->ctx, s, f16 ? "hyb_gemm_f16" : "hyb_gemm_bf16");
-    return dispatch_gemm<T>(grid, s, a_hi, a_lo, b_hi, b_lo, g.kb_n, g.rb_pad, g.cb_n, g.kb_split, g.plane, mcols,
-                            count, nullptr, planes);
+    return dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, g.kb_n, g.rb_pad, g.cb_n, g.kb_split, g.plane,
+                            mcols, count, nullptr, planes);
 }
 
 hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, const uint32_t *d_entries,

@@ -1,5 +1,6 @@
-// Per-kernel event timing for awg_profile_*: events are recorded on the launch
-// stream right before and after each kernel; totals are accumulated on read.
+// Per-kernel event timing for awg_profile_*: each timed kernel's dispatch
+// records a start and a stop event (hipExtLaunchKernel); one launch in
+// `period` of each kernel is timed; totals are accumulated on read.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -22,12 +23,16 @@ static hipEvent_t take_event(awg_ctx *c)
 }
 
 ProfScope::ProfScope(awg_ctx *ctx, hipStream_t s, const char *name)
-    : ctx_(ctx), s_(s), name_(name), start_(nullptr)
+    : ctx_(ctx), s_(s), name_(name), start_(nullptr), stop_(nullptr), launched_(false)
 {
-    if (!ctx_ || !ctx_->profiling) return;
+    if (!ctx_) return;
+    const int32_t period = ctx_->prof_period.load(std::memory_order_relaxed);
+    if (period <= 0) return;
     std::lock_guard<std::mutex> g(ctx_->prof_mu);
+    if (ctx_->prof_seen[name_]++ % (uint64_t)period != 0) return;
     start_ = take_event(ctx_);
-    if (start_ && hipEventRecord(start_, s_) != hipSuccess) {
+    stop_ = start_ ? take_event(ctx_) : nullptr;
+    if (!stop_ && start_) {
         ctx_->prof_pool.push_back(start_);
         start_ = nullptr;
     }
@@ -35,15 +40,14 @@ ProfScope::ProfScope(awg_ctx *ctx, hipStream_t s, const char *name)
 
 ProfScope::~ProfScope()
 {
-    if (!start_) return;
+    if (!stop_) return;
     std::lock_guard<std::mutex> g(ctx_->prof_mu);
-    hipEvent_t stop = take_event(ctx_);
-    if (!stop || hipEventRecord(stop, s_) != hipSuccess) {
+    if (!launched_) {
         ctx_->prof_pool.push_back(start_);
-        if (stop) ctx_->prof_pool.push_back(stop);
+        ctx_->prof_pool.push_back(stop_);
         return;
     }
-    ctx_->prof_pending.push_back(ProfRecord{name_, start_, stop});
+    ctx_->prof_pending.push_back(ProfRecord{name_, start_, stop_});
 }
 
 }  // namespace awg
@@ -55,8 +59,10 @@ extern "C" {
 awg_status awg_profile_enable(awg_ctx *ctx, int32_t enable)
 {
     if (!ctx) return AWG_E_INVALID;
+    if (enable < 0) return AWG_E_INVALID;
     std::lock_guard<std::mutex> g(ctx->prof_mu);
-    ctx->profiling = enable != 0;
+    ctx->prof_seen.clear();
+    ctx->prof_period.store(enable, std::memory_order_relaxed);
     return AWG_OK;
 }
 
