@@ -108,18 +108,17 @@ __device__ __forceinline__ bool entry_line(const ToneDev *__restrict__ tones, co
 }
 
 // A operand: one thread per (row c, group g of 4 entries) -> 8 inner values.
-// Entries are tones (entries == nullptr) or line entries.
+// Entries are tones (entries == nullptr) or line entries. Grid: (rows / 256,
+// groups from g_base on); the group is the workgroup's y index, so the
+// entries' words are uniform (scalar loads). rows = 32 rb_pad is a multiple of 256.
 template <typename T>
 __global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ tones,
                                                     const uint32_t *__restrict__ entries, int32_t n_entries,
-                                                    int32_t n_groups, uint64_t n0, uint64_t mcols,
-                                                    int32_t rb_pad, T *__restrict__ a_hi, T *__restrict__ a_lo)
+                                                    int32_t g_base, uint64_t n0, uint64_t mcols, int32_t rb_pad,
+                                                    T *__restrict__ a_hi, T *__restrict__ a_lo)
 {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t rows = (int64_t)rb_pad * 32;
-    if (gid >= rows * n_groups) return;
-    const int32_t g = (int32_t)(gid / rows);
-    const int64_t c = gid % rows;
+    const int32_t g = g_base + (int32_t)blockIdx.y;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n = n0 + (uint64_t)c * mcols;
     typename Split<T>::vec hv, lv;
 #pragma unroll
@@ -391,6 +390,16 @@ static int gemm_variant()
     return v;
 }
 
+// A operand of groups [0, n_groups): launches of at most 65535 groups (grid y).
+template <typename T>
+static void launch_gen_a(ProfScope &prof, const ToneDev *tones, const uint32_t *entries, int32_t n_entries,
+                         int32_t n_groups, uint64_t n0, uint64_t mcols, int32_t rb_pad, T *a_hi, T *a_lo)
+{
+    for (int32_t g0 = 0; g0 < n_groups; g0 += 65535)
+        prof.launch(gen_a_kernel<T>, dim3((uint32_t)(rb_pad * 32 / 256), (uint32_t)std::min(65535, n_groups - g0)),
+                    dim3(256), 0, tones, entries, n_entries, g0, n0, mcols, rb_pad, a_hi, a_lo);
+}
+
 template <typename T>
 static hipError_t dispatch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T *a_lo, const T *b_hi,
                                 const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
@@ -454,15 +463,13 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     T *b_hi = (T *)w, *b_lo = (T *)(w + b_bytes);
     T *a_hi = (T *)(w + 2 * b_bytes), *a_lo = (T *)(w + 2 * b_bytes + a_bytes);
     // zero the padding groups of the last k-block (odd group count)
-    const int64_t a_threads = (int64_t)rb_pad * 32 * (2 * kb_n);
     const int64_t b_threads = (int64_t)cb_n * 32 * (2 * kb_n);
     const bool f16 = sizeof(T) == 2 && std::is_same<T, _Float16>::value;
     hipError_t e = p->work_used ? hipStreamWaitEvent(s, p->work_done, 0) : hipSuccess;
     if (e != hipSuccess) return hipst(e);
     {
         ProfScope prof(p->ctx, s, f16 ? "gen_a_kernel_f16" : "gen_a_kernel_bf16");
-        prof.launch(gen_a_kernel<T>, dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, p->d_tones,
-                    (const uint32_t *)nullptr, p->n_tones, 2 * kb_n, n0, mcols, rb_pad, a_hi, a_lo);
+        launch_gen_a<T>(prof, p->d_tones, nullptr, p->n_tones, 2 * kb_n, n0, mcols, rb_pad, a_hi, a_lo);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return hipst(e);
@@ -518,13 +525,11 @@ static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_
     T *a_hi = (T *)(w + 2 * g.b_bytes), *a_lo = (T *)(w + 2 * g.b_bytes + g.a_bytes);
     float *planes = (float *)(w + 2 * (g.a_bytes + g.b_bytes));
     const uint64_t mcols = kTileSamples;
-    const int64_t a_threads = (int64_t)g.rb_pad * 32 * (2 * g.kb_n);
     const int64_t b_threads = (int64_t)g.cb_n * 32 * (2 * (d_blocks ? n_blocks : g.kb_n));
     hipError_t e;
     {
         ProfScope prof(p->ctx, s, f16 ? "hyb_gen_a_f16" : "hyb_gen_a_bf16");
-        prof.launch(gen_a_kernel<T>, dim3((uint32_t)((a_threads + 255) / 256)), dim3(256), 0, p->d_tones,
-                    d_entries, n_entries, 2 * g.kb_n, n0, mcols, g.rb_pad, a_hi, a_lo);
+        launch_gen_a<T>(prof, p->d_tones, d_entries, n_entries, 2 * g.kb_n, n0, mcols, g.rb_pad, a_hi, a_lo);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
