@@ -120,3 +120,24 @@ def test_two_streams_on_one_plan(ramped):
         torch.cuda.synchronize()
         for i in range(len(calls)):
             assert np.array_equal(to_np(outs[i]), ref[i]), (rep, i)
+
+
+def test_mfma_more_groups_than_one_launch():
+    """270,000 tones: the A operand's 67,500 tone groups exceed one launch's grid
+    (65,535 in y), so it is generated in two launches; sampled outputs against
+    the oracle."""
+    torch = need_gpu()
+    K, fs = 270_000, 280e6
+    rng = np.random.default_rng(54)
+    t = W.static_tones(rng.uniform(0.05 * fs, 0.45 * fs, K), rng.uniform(0.5, 1.0, K), rng.random(K))
+    lp = awg.Plan(t, fs, 0.0, 0, F16)
+    n0, count = 7, 1 << 16
+    say("mfma %d tones n0=%d count=%d" % (K, n0, count))
+    y = to_np(lp.synth_f32(n0, count, method=F16))
+    q = to_np(lp.synth_static(n0, count))
+    torch.cuda.synchronize()
+    ns = np.unique(np.concatenate([np.arange(n0, n0 + 40), rng.integers(n0, n0 + count, 300),
+                                   np.arange(n0 + count - 40, n0 + count)]))
+    qo, yo = csynth.synth_at(words.Plan(fs, 0.0, 0, t), ns)
+    compare(q[ns - n0], y[ns - n0], qo, yo, "mfma %d tones (sampled %d)" % (K, len(ns)))
+    lp.close()
