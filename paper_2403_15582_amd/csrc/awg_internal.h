@@ -116,7 +116,7 @@ struct Table {
     int32_t shape;
     uint64_t n;
     uint64_t *d_data;    // device, n + 1 entries
-    bool monotone;       // never decreasing with steps below 2^31 (pointers handed out carry it in bit 0)
+    bool monotone;       // never decreasing with steps below 2^23 (pointers handed out carry it in bit 0)
 };
 
 }  // namespace awg

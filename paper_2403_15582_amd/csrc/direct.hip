@@ -44,7 +44,7 @@ __device__ __forceinline__ uint64_t smooth_term(int64_t dF, uint64_t H)
 }
 
 // Table pointers carry a tag in bit 0: set when the table never decreases and
-// its steps fit 31 bits, which the incremental smooth path relies on.
+// its steps are below 2^23, which the incremental smooth path relies on.
 __device__ __forceinline__ const uint64_t *table_of(const uint64_t *const *tables, uint32_t i)
 {
     return (const uint64_t *)((uintptr_t)tables[i] & ~(uintptr_t)1);
@@ -292,6 +292,8 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
             } else if (tile0 >= r.a && tile_last <= r.a + r.n) {
                 const uint64_t dt = tile0 - r.a;
                 if (r.shape == AWG_RAMP_LINEAR) {
+                    // two tones at a time: two independent phase chains per lane
+#pragma unroll 2
                     for (int k = k0; k < k1; ++k) {
                         const ToneDev t = tones[k];
                         const float amp = t.amp;
@@ -306,10 +308,11 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                     uint64_t hv[S];
 #pragma unroll
                     for (int s = 0; s < S; ++s) hv[s] = H[s];
-                    // successive table differences (non-negative, below 2^31 when tagged)
+                    // successive table differences (non-negative, below 2^23 when tagged)
                     uint32_t dh[S];
 #pragma unroll
                     for (int s = 0; s + 1 < S; ++s) dh[s] = (uint32_t)(hv[s + 1] - hv[s]);
+#pragma unroll 2
                     for (int k = k0; k < k1; ++k) {
                         const uint64_t p0 = tones[k].p0, f0 = tones[k].f0;
                         const int64_t dF = tones[k].coef;
@@ -317,13 +320,23 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                         uint64_t ph = p0 + f0 * tile0 + f0 * (uint64_t)j;
                         if (mono && (dF & 0xffff) == 0) {
                             // dF a multiple of 2^16 (always for bin frequencies): the chirp
-                            // term is exactly m*H with m = dF/2^16, and moves by m*dh per sample
+                            // term is exactly m*H with m = dF/2^16, and moves by m*dh per
+                            // sample. With |m| < 2^47 and dh < 2^23 the product's high word
+                            // gains only the low 32 bits of (m >> 32) * dh, whose factors
+                            // fit the 24-bit multiplier: one 32x32+64 and one 24x24+32
+                            // multiply-add per sample instead of a full 64x32 product.
                             const uint64_t m = (uint64_t)(dF >> 16);
+                            const uint32_t m_lo = (uint32_t)m;
+                            const int32_t m_hi = (int32_t)(m >> 32);            // |m_hi| <= 2^15
                             ph += m * hv[0];
 #pragma unroll
                             for (int s = 0; s < S; ++s) {
                                 blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
-                                if (s + 1 < S) ph += f0 + m * (uint64_t)dh[s];
+                                if (s + 1 < S) {
+                                    const uint64_t lo = (uint64_t)m_lo * dh[s] + f0;
+                                    const uint32_t hi = (uint32_t)(lo >> 32) + (uint32_t)__mul24(m_hi, (int32_t)dh[s]);
+                                    ph += ((uint64_t)hi << 32) | (uint32_t)lo;
+                                }
                             }
                         } else {
 #pragma unroll
