@@ -13,8 +13,9 @@
  * per unit amplitude), rounds half-to-even and saturates to int16 DAC codes.
  *
  * Phases are exact 64-bit fixed-point words (one turn = 2^64); the sinusoid and
- * the sum over tones run in FP32 on the GPU (or FP16 split operands with FP32
- * accumulation on the matrix cores for static tones).
+ * the sum over tones run in FP32 on the GPU, or on the matrix cores by angle
+ * addition with FP16 or BF16 hi/lo split operands and FP32 accumulation (static
+ * tones, and the tones of a ramped plan that are on a line over a row).
  *
  * Conventions for every call:
  *  - All functions return an awg_status; none aborts and no C++ exception
