@@ -160,12 +160,11 @@ struct awg_plan {
     size_t d_table_ptrs_cap;
     uint64_t cursor;
     uint64_t device_bytes;
-    // retune staging: pinned host slots and their completion events
-    struct Slot { void *host; hipEvent_t done; bool used; };
+    // retune staging: pinned coherent host slots (read by the device through
+    // their mapped addresses) and their completion events
+    struct Slot { void *host; void *mapped; hipEvent_t done; bool used; };
     std::vector<Slot> slots;
     size_t next_slot;
-    void *d_scratch;                   // device staging for retune records
-    size_t d_scratch_bytes;
     // MFMA workspace (operands), grown on demand; B operand cached under mfma_b_key
     void *d_work;
     size_t d_work_bytes;
@@ -222,9 +221,20 @@ hipError_t launch_direct_f32(const awg_plan *p, uint64_t n0, uint64_t count, flo
                              hipStream_t s);
 hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint64_t count,
                              uint64_t *out, hipStream_t s);
+// One changed tone for the scatter kernel: its device position and record.
+struct ScatterRecord { uint32_t index; uint32_t pad; ToneDev tone; };
 hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n,
                                 hipStream_t s);
 hipError_t launch_peak(const float *d_y, uint64_t count, float *d_peak, hipStream_t s);
+// Copy `bytes` from pinned host memory (src: its device-mapped address, from a
+// coherent hipHostMalloc allocation) to device memory dst, by a kernel on s: the
+// copy stays on the compute queue in stream order, with no hand-off to a DMA
+// engine. Used for the small per-call uploads (retune records, block tables,
+// hybrid staging, serving work lists).
+hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t s);
+// Pinned, coherent host memory for launch_upload: *host and its device-mapped
+// address *mapped.
+hipError_t alloc_upload_host(size_t bytes, void **host, void **mapped);
 hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint32_t grid, hipStream_t s);
 // Multiplexed channels: items[c] (c < n, n <= kMaxChannels) each cover the same
 // count samples; one launch, items passed by value.

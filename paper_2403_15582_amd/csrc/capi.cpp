@@ -21,8 +21,8 @@ constexpr uint64_t kMaxSample = 1ull << 63;          // n0 + count must stay bel
 constexpr size_t kTablePtrCap = 1024;                 // distinct smooth tables per plan
 constexpr size_t kSlots = 16;                         // retune staging slots
 constexpr size_t kSlotRecords = 16384;                // records per slot
-
-struct ScatterRecord { uint32_t index; uint32_t pad; ToneDev tone; };
+// the block table's offset in a retune slot (after the records, 16-byte aligned)
+constexpr size_t kBlockOffset = (sizeof(ScatterRecord) * kSlotRecords + 15) / 16 * 16;
 
 awg_status hip_status(hipError_t e)
 {
@@ -122,7 +122,6 @@ void free_plan_device(awg_plan *p)
     if (p->d_tones) (void)hipFree(p->d_tones);
     if (p->d_blocks) (void)hipFree(p->d_blocks);
     if (p->d_table_ptrs) (void)hipFree(p->d_table_ptrs);
-    if (p->d_scratch) (void)hipFree(p->d_scratch);
     if (p->work_done) {
         (void)hipEventSynchronize(p->work_done);
         (void)hipEventDestroy(p->work_done);
@@ -130,6 +129,8 @@ void free_plan_device(awg_plan *p)
     }
     if (p->d_work) (void)hipFree(p->d_work);
     for (auto &s : p->slots) {
+        // the device reads the slots in place: their last readers finish first
+        if (s.done && s.used) (void)hipEventSynchronize(s.done);
         if (s.host) (void)hipHostFree(s.host);
         if (s.done) (void)hipEventDestroy(s.done);
     }
@@ -281,8 +282,6 @@ awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg
     p->cursor = 0;
     p->device_bytes = 0;
     p->next_slot = 0;
-    p->d_scratch = nullptr;
-    p->d_scratch_bytes = 0;
     p->d_work = nullptr;
     p->hyb = nullptr;
     p->d_work_bytes = 0;
@@ -390,7 +389,7 @@ awg_status awg_plan_info_get(const awg_plan *p, awg_plan_info *info)
     info->flags = p->params.flags;
     info->period_log2 = p->params.period_log2;
     info->cursor = p->cursor;
-    info->device_bytes = p->device_bytes + p->d_work_bytes + p->d_scratch_bytes + hybrid_bytes(p);
+    info->device_bytes = p->device_bytes + p->d_work_bytes + hybrid_bytes(p);
     return AWG_OK;
 }
 
@@ -509,8 +508,9 @@ awg_status awg_plan_amplitude(awg_plan *p, const awg_amp_ramp *ev, int32_t n_ev,
 }
 
 // Device copy of the tones changed on the host (caller indices), in stream order:
-// their records go through a pinned slot and a scatter kernel, the rebuilt block
-// table after them.
+// their records are written to a pinned slot that the scatter kernel reads in
+// place, and the rebuilt block table is uploaded from the same slot by a kernel
+// (no DMA engine in the chain).
 static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, hipStream_t s)
 {
     build_blocks(p->dev_mirror, -1, &p->blocks);
@@ -521,17 +521,13 @@ static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, 
     if (p->slots.empty()) {
         p->slots.resize(kSlots);
         for (auto &s : p->slots) {
-            s.host = nullptr; s.done = nullptr; s.used = false;
+            s.host = nullptr; s.mapped = nullptr; s.done = nullptr; s.used = false;
         }
         for (auto &s : p->slots) {
-            e = hipHostMalloc(&s.host, sizeof(ScatterRecord) * kSlotRecords + sizeof(Block) * ((size_t)p->n_tones + 1),
-                              hipHostMallocDefault);
+            e = alloc_upload_host(kBlockOffset + sizeof(Block) * ((size_t)p->n_tones + 1), &s.host, &s.mapped);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
             if (e != hipSuccess) return hip_status(e);
         }
-        e = hipMalloc(&p->d_scratch, sizeof(ScatterRecord) * kSlotRecords * kSlots);
-        if (e != hipSuccess) return hip_status(e);
-        p->d_scratch_bytes = sizeof(ScatterRecord) * kSlotRecords * kSlots;
     }
     const size_t si = p->next_slot;
     p->next_slot = (p->next_slot + 1) % kSlots;
@@ -546,14 +542,12 @@ static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, 
         rec[i].pad = 0;
         rec[i].tone = p->dev_mirror[p->inv[changed[i]]];
     }
-    void *d_rec = (char *)p->d_scratch + si * sizeof(ScatterRecord) * kSlotRecords;
-    e = hipMemcpyAsync(d_rec, rec, sizeof(ScatterRecord) * (size_t)n_ev, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_scatter_tones(p->d_tones, d_rec, n_ev, s);
+    e = launch_scatter_tones(p->d_tones, slot.mapped, n_ev, s);
     // the block table follows the records in the same pinned slot
-    Block *blk = (Block *)((char *)slot.host + sizeof(ScatterRecord) * kSlotRecords);
+    Block *blk = (Block *)((char *)slot.host + kBlockOffset);
     const size_t blk_bytes = sizeof(Block) * p->blocks.size();
     std::memcpy(blk, p->blocks.data(), blk_bytes);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->d_blocks, blk, blk_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_upload((const char *)slot.mapped + kBlockOffset, p->d_blocks, blk_bytes, s);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     slot.used = true;
     return hip_status(e);

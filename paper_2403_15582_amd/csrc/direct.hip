@@ -542,8 +542,6 @@ __global__ __launch_bounds__(64) void phase_dump_kernel(const ToneDev *__restric
     });
 }
 
-struct ScatterRecord { uint32_t index; uint32_t pad; ToneDev tone; };
-
 __global__ void scatter_tones_kernel(ToneDev *__restrict__ tones, const ScatterRecord *__restrict__ rec,
                                      int32_t n)
 {
@@ -690,6 +688,43 @@ hipError_t launch_mux(const BatchItem *items, int32_t n, uint64_t count, hipStre
         }
     }
     return hipSuccess;
+}
+
+// Host-to-device copy by a kernel (see launch_upload): 16-byte words with a grid
+// stride, then the tail bytes.
+__global__ __launch_bounds__(256) void upload_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                     uint64_t n16, const uint8_t *__restrict__ src_tail,
+                                                     uint8_t *__restrict__ dst_tail, uint32_t tail)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    if (blockIdx.x == 0 && threadIdx.x < tail) dst_tail[threadIdx.x] = src_tail[threadIdx.x];
+}
+
+hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)src | (uintptr_t)dst) & 15) return hipErrorInvalidValue;
+    const uint64_t n16 = bytes / 16;
+    const uint32_t tail = (uint32_t)(bytes % 16);
+    const uint64_t blocks = std::min<uint64_t>(std::max<uint64_t>((n16 + 255) / 256, 1), 1024);
+    hipLaunchKernelGGL(upload_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16,
+                       (const uint8_t *)src + n16 * 16, (uint8_t *)dst + n16 * 16, tail);
+    return hipGetLastError();
+}
+
+hipError_t alloc_upload_host(size_t bytes, void **host, void **mapped)
+{
+    *host = nullptr;
+    *mapped = nullptr;
+    hipError_t e = hipHostMalloc(host, bytes, hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(mapped, *host, 0);
+    if (e != hipSuccess && *host) {
+        (void)hipHostFree(*host);
+        *host = nullptr;
+        *mapped = nullptr;
+    }
+    return e;
 }
 
 hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n, hipStream_t s)

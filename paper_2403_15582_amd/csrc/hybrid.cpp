@@ -52,7 +52,8 @@ awg_status hst(hipError_t e)
 struct HybridState {
     std::mutex mu;
     struct Slot {
-        void *host = nullptr;
+        void *host = nullptr;          // pinned, coherent (alloc_upload_host)
+        void *mapped = nullptr;        // its device-mapped address
         size_t host_cap = 0;
         void *dev = nullptr;
         size_t dev_cap = 0;
@@ -277,8 +278,9 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
     if (slot.host_cap < total) {
         if (slot.host) (void)hipHostFree(slot.host);
         slot.host = nullptr;
+        slot.mapped = nullptr;
         slot.host_cap = 0;
-        e = hipHostMalloc(&slot.host, std::max(cap, total), hipHostMallocDefault);
+        e = alloc_upload_host(std::max(cap, total), &slot.host, &slot.mapped);
         if (e != hipSuccess) return hst(e);
         slot.host_cap = std::max(cap, total);
     }
@@ -320,7 +322,7 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
         std::memcpy(hb + off_d, h->dirty.data(), sizeof(int32_t) * h->dirty.size());
 
     char *db = (char *)slot.dev;
-    e = hipMemcpyAsync(db, hb, total, hipMemcpyHostToDevice, s);
+    e = launch_upload(slot.mapped, db, total, s);
     if (e == hipSuccess && h->work_used) e = hipStreamWaitEvent(s, h->work_done, 0);
     if (e == hipSuccess && gemm)
         e = launch_lines(p, method, g, (const uint32_t *)db, n_entries, partial ? (const int32_t *)(db + off_d) : nullptr,

@@ -44,17 +44,20 @@ constexpr int kTileCB = 8;            // column blocks per workgroup tile (256 c
 constexpr int kFragBytes = 64 * 16;   // one 32x16 fragment of 16-bit values
 
 // sin and cos of an (unbiased) phase word to about one FP32 ulp: the turn
-// t = hi32 * 2^-32, rounded to FP32, goes through v_sin / v_cos (arguments in
-// turns), and the exact residual word w - t * 2^64 (below 2^39, i.e. under
-// 1e-7 rad) is applied to first order.
+// t = hr * 2^-32, with hr the high word rounded to an FP32 value, goes through
+// v_sin / v_cos (arguments in turns), and the residual word
+// w - hr * 2^32 = (hi - hr) * 2^32 + lo (|hi - hr| <= 128, so under 2^40 and
+// 1e-7 rad) is applied to first order. hr is kept below 2^31 so that it
+// converts to an int32 exactly; the residual is then formed in 32-bit pieces
+// and rounded once (to about 2^15 of 2^64 turn).
 __device__ __forceinline__ void word_sincos(uint64_t w, float &s, float &c)
 {
     const int32_t hi = (int32_t)(uint32_t)(w >> 32);
-    const float hf = (float)hi;                                 // rounded to 24 bits
-    const int64_t hr = (int64_t)hf;                             // exact, |hr| <= 2^31
-    const int64_t res = (int64_t)(w - ((uint64_t)hr << 32));    // exact residual word
+    const float hf = fminf((float)hi, 2147483520.0f);          // rounded to 24 bits, < 2^31
+    const int32_t dh = hi - (int32_t)hf;                        // exact, |dh| <= 128
     const float t = hf * 0x1p-32f;
-    const float d = (float)res * (6.283185307179586f * 0x1p-64f);
+    const float res = __builtin_fmaf((float)dh, 0x1p32f, (float)(uint32_t)w);
+    const float d = res * (6.283185307179586f * 0x1p-64f);
     const float s0 = __builtin_amdgcn_sinf(t), c0 = __builtin_amdgcn_cosf(t);
     s = __builtin_fmaf(d, c0, s0);
     c = __builtin_fmaf(-d, s0, c0);
@@ -108,10 +111,10 @@ __device__ __forceinline__ bool entry_line(const ToneDev *__restrict__ tones, co
 }
 
 // A operand: one thread per (row c, group g of 4 entries) -> 8 inner values.
-// Entries are tones (entries == nullptr) or line entries. Grid: (rows / 256,
+// Entries are tones (ENTRIES false) or line entries. Grid: (rows / 256,
 // groups from g_base on); the group is the workgroup's y index, so the
 // entries' words are uniform (scalar loads). rows = 32 rb_pad is a multiple of 256.
-template <typename T>
+template <typename T, bool ENTRIES>
 __global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ tones,
                                                     const uint32_t *__restrict__ entries, int32_t n_entries,
                                                     int32_t g_base, uint64_t n0, uint64_t mcols, int32_t rb_pad,
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ 
         const int k = 4 * g + t;
         float xs = 0.0f, xc = 0.0f;
         ToneDev td;
-        if (k < n_entries && entry_line(tones, entries, k, n, mcols, td)) {
+        if (k < n_entries && entry_line(tones, ENTRIES ? entries : nullptr, k, n, mcols, td)) {
             float s, co;
             word_sincos(td.p0 - kPhaseBias + td.f0 * n, s, co);
             xs = td.amp * s;
@@ -395,9 +398,15 @@ template <typename T>
 static void launch_gen_a(ProfScope &prof, const ToneDev *tones, const uint32_t *entries, int32_t n_entries,
                          int32_t n_groups, uint64_t n0, uint64_t mcols, int32_t rb_pad, T *a_hi, T *a_lo)
 {
-    for (int32_t g0 = 0; g0 < n_groups; g0 += 65535)
-        prof.launch(gen_a_kernel<T>, dim3((uint32_t)(rb_pad * 32 / 256), (uint32_t)std::min(65535, n_groups - g0)),
-                    dim3(256), 0, tones, entries, n_entries, g0, n0, mcols, rb_pad, a_hi, a_lo);
+    for (int32_t g0 = 0; g0 < n_groups; g0 += 65535) {
+        const dim3 grid((uint32_t)(rb_pad * 32 / 256), (uint32_t)std::min(65535, n_groups - g0));
+        if (entries)
+            prof.launch(gen_a_kernel<T, true>, grid, dim3(256), 0, tones, entries, n_entries, g0, n0, mcols, rb_pad,
+                        a_hi, a_lo);
+        else
+            prof.launch(gen_a_kernel<T, false>, grid, dim3(256), 0, tones, entries, n_entries, g0, n0, mcols, rb_pad,
+                        a_hi, a_lo);
+    }
 }
 
 template <typename T>

@@ -36,6 +36,7 @@ using namespace awg;
 namespace {
 
 constexpr uint32_t kBatchGrid = 2048;   // workgroups of the batched kernel (8 per CU)
+constexpr size_t kItemsOffset = 256;    // work-list items after the 2-word header
 constexpr size_t kAlign = 256;
 
 double now_ms()
@@ -76,8 +77,11 @@ struct Step {
     std::vector<StepItem> items;
     double t_launch = 0;
     hipEvent_t ev_start = nullptr, ev_done = nullptr;
-    BatchItem *h_items = nullptr;   // pinned
-    uint32_t *h_hdr = nullptr;      // pinned
+    // the step's work list: one pinned coherent blob (header at 0, items at
+    // kItemsOffset) that the step graph uploads by a kernel into d_blob
+    void *h_blob = nullptr, *m_blob = nullptr, *d_blob = nullptr;
+    BatchItem *h_items = nullptr;
+    uint32_t *h_hdr = nullptr;
     BatchItem *d_items = nullptr;
     uint32_t *d_hdr = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -358,19 +362,21 @@ void scheduler(awg_server *s)
 awg_status build_step(awg_server *s, Step &st)
 {
     const size_t items_bytes = sizeof(BatchItem) * (size_t)s->prm.max_jobs;
-    hipError_t e = hipHostMalloc((void **)&st.h_items, items_bytes, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&st.h_hdr, 2 * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMalloc((void **)&st.d_items, items_bytes);
-    if (e == hipSuccess) e = hipMalloc((void **)&st.d_hdr, 2 * sizeof(uint32_t));
+    const size_t blob_bytes = kItemsOffset + items_bytes;
+    hipError_t e = alloc_upload_host(blob_bytes, &st.h_blob, &st.m_blob);
+    if (e == hipSuccess) e = hipMalloc(&st.d_blob, blob_bytes);
     if (e == hipSuccess) e = hipEventCreate(&st.ev_start);
     if (e == hipSuccess) e = hipEventCreate(&st.ev_done);
     if (e != hipSuccess) return hipst(e);
-    std::memset(st.h_items, 0, items_bytes);
-    st.h_hdr[0] = st.h_hdr[1] = 0;
-    // the step graph: copy the work list in, then the batched kernel
+    st.h_hdr = (uint32_t *)st.h_blob;
+    st.h_items = (BatchItem *)((char *)st.h_blob + kItemsOffset);
+    st.d_hdr = (uint32_t *)st.d_blob;
+    st.d_items = (BatchItem *)((char *)st.d_blob + kItemsOffset);
+    std::memset(st.h_blob, 0, blob_bytes);
+    // the step graph: upload the work list (a kernel reading the pinned blob, so
+    // the step stays on the compute queue), then the batched kernel
     e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = hipMemcpyAsync(st.d_items, st.h_items, items_bytes, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(st.d_hdr, st.h_hdr, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_upload(st.m_blob, st.d_blob, blob_bytes, s->stream);
     if (e == hipSuccess) e = launch_batch(st.d_items, st.d_hdr, kBatchGrid, s->stream);
     hipError_t e2 = hipStreamEndCapture(s->stream, &st.graph);
     if (e == hipSuccess) e = e2;
@@ -385,10 +391,8 @@ void free_server(awg_server *s)
         if (st.graph) (void)hipGraphDestroy(st.graph);
         if (st.ev_start) (void)hipEventDestroy(st.ev_start);
         if (st.ev_done) (void)hipEventDestroy(st.ev_done);
-        if (st.h_items) (void)hipHostFree(st.h_items);
-        if (st.h_hdr) (void)hipHostFree(st.h_hdr);
-        if (st.d_items) (void)hipFree(st.d_items);
-        if (st.d_hdr) (void)hipFree(st.d_hdr);
+        if (st.h_blob) (void)hipHostFree(st.h_blob);
+        if (st.d_blob) (void)hipFree(st.d_blob);
     }
     for (auto &p : s->pending) awg_plan_destroy(p.plan);
     for (auto &kv : s->jobs) awg_plan_destroy(kv.second.plan);
