@@ -131,6 +131,11 @@ struct awg_server {
     // device rate (tone-samples per ms) measured on completed steps, for the step work budget
     double rate_ts_per_ms = 2e9;
     std::vector<double> lat_chunk, lat_first, lateness;
+    // admission staging: pinned coherent buffers holding a job's tables in their
+    // arena layout, uploaded by a kernel; a buffer is reused once its upload is done
+    struct Stage { void *host = nullptr, *mapped = nullptr; size_t cap = 0; hipEvent_t done = nullptr; bool used = false; };
+    Stage stage[8];
+    int stage_next = 0;
 };
 
 namespace {
@@ -196,17 +201,32 @@ void admit(awg_server *s)
         j.chunks_done = 0;
         j.in_flight = false;
         j.t_first_ready = -1;
-        // words and table pointers into the arena, in stream order before any step using them
-        // (the plan, and so both source arrays, lives until the job's last chunk is done)
-        hipError_t e = hipMemcpyAsync(j.d_tones, pd.plan->dev_mirror.data(), sizeof(ToneDev) * (size_t)j.n_tones,
-                                      hipMemcpyHostToDevice, s->stream);
-        const size_t nt = pd.plan->table_ptrs.size();
-        if (e == hipSuccess && nt > 0)
-            e = hipMemcpyAsync(j.d_tabs, pd.plan->table_ptrs.data(), sizeof(uint64_t *) * nt,
-                               hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(j.d_blocks, pd.plan->blocks.data(), sizeof(Block) * pd.plan->blocks.size(),
-                               hipMemcpyHostToDevice, s->stream);
+        // words, table pointers and block table into the arena, in stream order
+        // before any step using them: laid out in a staging buffer as in the
+        // arena, then one upload kernel
+        awg_server::Stage &sg = s->stage[s->stage_next];
+        s->stage_next = (s->stage_next + 1) % (int)(sizeof(s->stage) / sizeof(s->stage[0]));
+        hipError_t e = hipSuccess;
+        if (!sg.done) e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);
+        if (e == hipSuccess && sg.used) e = hipEventSynchronize(sg.done);
+        if (e == hipSuccess && sg.cap < bytes) {
+            if (sg.host) (void)hipHostFree(sg.host);
+            sg.host = sg.mapped = nullptr;
+            sg.cap = 0;
+            e = alloc_upload_host(std::max<size_t>(bytes, 1 << 16), &sg.host, &sg.mapped);
+            if (e == hipSuccess) sg.cap = std::max<size_t>(bytes, 1 << 16);
+        }
+        if (e == hipSuccess) {
+            sg.used = false;
+            char *h = (char *)sg.host;
+            std::memcpy(h, pd.plan->dev_mirror.data(), sizeof(ToneDev) * (size_t)j.n_tones);
+            const size_t nt = pd.plan->table_ptrs.size();
+            if (nt > 0) std::memcpy(h + ((char *)j.d_tabs - base), pd.plan->table_ptrs.data(), sizeof(uint64_t *) * nt);
+            std::memcpy(h + ((char *)j.d_blocks - base), pd.plan->blocks.data(), sizeof(Block) * pd.plan->blocks.size());
+            e = launch_upload(sg.mapped, base, bytes, s->stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(sg.done, s->stream);
+        if (e == hipSuccess) sg.used = true;
         if (e != hipSuccess) { s->error = hipst(e); pool_free(s, off, bytes); break; }
         s->jobs[j.id] = j;
         s->pending.pop_front();
@@ -396,6 +416,11 @@ void free_server(awg_server *s)
     }
     for (auto &p : s->pending) awg_plan_destroy(p.plan);
     for (auto &kv : s->jobs) awg_plan_destroy(kv.second.plan);
+    for (auto &sg : s->stage) {
+        if (sg.done && sg.used) (void)hipEventSynchronize(sg.done);
+        if (sg.host) (void)hipHostFree(sg.host);
+        if (sg.done) (void)hipEventDestroy(sg.done);
+    }
     if (s->d_arena) (void)hipFree(s->d_arena);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
