@@ -220,6 +220,38 @@ def test_retune_stream_matches_oracle():
     compare(q[ns], None, qo, yo, "array-small (sampled %d)" % len(ns))
 
 
+
+def test_retune_largest_batch():
+    """One retune call of the largest batch (16384 events, a full staging slot that
+    the scatter kernel reads in place) on a 20,000-tone static plan, mixed shapes;
+    the direct and hybrid methods streamed across the windows against the oracle."""
+    torch = need_gpu()
+    K, fs = 20_000, 280e6
+    rng = np.random.default_rng(61)
+    bins = rng.choice(np.arange(60 * 2 ** 20 // 280, 130 * 2 ** 20 // 280), K, replace=False)
+    t = W.static_tones(bins * fs / 2 ** 20, rng.uniform(0.5, 1.0, K), rng.random(K))
+    ks = rng.choice(K, 16384, replace=False)
+    shapes = [awg.RAMP_LINEAR, awg.RAMP_COSINE, awg.RAMP_MINJERK]
+    events = [(int(k), shapes[i % 3], 70_000 + 13 * (i % 997), 50_000 + 7 * (i % 311),
+               float(t["f_start_hz"][k] + rng.uniform(-1e6, 1e6))) for i, k in enumerate(ks)]
+    count = 3 * (1 << 16) + 333
+    op = words.Plan(fs, 0.0, 20, t, build_tables=False)
+    for k, sh, a, n, f in events:
+        op.add_ramp(k, a, n, sh, f)
+    ns = np.unique(np.concatenate([np.arange(0, 50), rng.integers(0, count, 400),
+                                   np.array([70_000, 120_000, 140_000, 160_000, count - 1])]))
+    csynth.sparse_tables(op, ns)
+    qo, yo = csynth.synth_at(op, ns)
+    for method in (awg.AWG_F_METHOD_DIRECT, awg.AWG_F_METHOD_MFMA_BF16X3):
+        lp = awg.Plan(t, fs, 0.0, 20, method)
+        say("retune 16384 events on %d tones, method %d" % (K, method))
+        lp.retune(events)
+        parts = [lp.stream_next(c)[1] for c in (1 << 16, 1 << 16, (1 << 16) + 333)]
+        q = np.concatenate([to_np(x) for x in parts])
+        torch.cuda.synchronize()
+        compare(q[ns], None, qo, yo, "retune 16384 events method %d (sampled %d)" % (method, len(ns)))
+        lp.close()
+
 @pytest.mark.parametrize("K", [5000, 10000])
 def test_array_group_chirps_full_second_streamed(K):
     """Large array: 1 s at 280 MS/s (268 chunks), groups of 100 tones retuned in turn."""
