@@ -79,6 +79,7 @@ static_assert(sizeof(Block) == 8, "Block must be 8 bytes");
 constexpr uint16_t kBlockUniform = 1;   // every tone shares the first one's shape, window and table
 constexpr uint16_t kBlockSplit = 2;     // hybrid path: on line tiles the tones are summed elsewhere
 constexpr uint16_t kBlockAmp = 4;       // some tone has an amplitude window
+constexpr uint16_t kBlockStep16 = 8;    // uniform smooth block: every tone's dF is a multiple of 2^16
 
 // One chunk of one plan in a batched launch (64 bytes).
 struct BatchItem {

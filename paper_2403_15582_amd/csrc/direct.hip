@@ -304,31 +304,39 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                 } else {
                     // the table values of this lane's samples serve every tone of the block
                     const uint64_t *H = table_of(tables, r.table) + dt + j;
-                    const bool mono = table_monotone(tables, r.table);
-                    uint64_t hv[S];
-#pragma unroll
-                    for (int s = 0; s < S; ++s) hv[s] = H[s];
-                    // successive table differences (non-negative, below 2^23 when tagged)
+                    // dF a multiple of 2^16 for every tone of the block (always for bin
+                    // frequencies) and a tagged table: the incremental step below; else
+                    // the full product per sample. One loop or the other per block, so
+                    // the two never hold registers at the same time.
+                    const bool step16 = (bk.flags & kBlockStep16) && table_monotone(tables, r.table);
+                    // the lane's first table value and the successive differences
+                    // (non-negative, below 2^23 when tagged)
+                    const uint64_t hv0 = H[0];
                     uint32_t dh[S];
+                    if (step16) {
+                        uint64_t prev = hv0;
 #pragma unroll
-                    for (int s = 0; s + 1 < S; ++s) dh[s] = (uint32_t)(hv[s + 1] - hv[s]);
+                        for (int s = 0; s + 1 < S; ++s) {
+                            const uint64_t cur = H[s + 1];
+                            dh[s] = (uint32_t)(cur - prev);
+                            prev = cur;
+                        }
+                    }
+                    if (step16) {
+                        // the chirp term is exactly m*H with m = dF/2^16, and moves by m*dh
+                        // per sample. With |m| < 2^47 and dh < 2^23 the product's high word
+                        // gains only the low 32 bits of (m >> 32) * dh, whose factors fit
+                        // the 24-bit multiplier: one 32x32+64 and one 24x24+32 multiply-add
+                        // per sample instead of a full 64x32 product.
 #pragma unroll 2
-                    for (int k = k0; k < k1; ++k) {
-                        const uint64_t p0 = tones[k].p0, f0 = tones[k].f0;
-                        const int64_t dF = tones[k].coef;
-                        const float amp = tones[k].amp;
-                        uint64_t ph = p0 + f0 * tile0 + f0 * (uint64_t)j;
-                        if (mono && (dF & 0xffff) == 0) {
-                            // dF a multiple of 2^16 (always for bin frequencies): the chirp
-                            // term is exactly m*H with m = dF/2^16, and moves by m*dh per
-                            // sample. With |m| < 2^47 and dh < 2^23 the product's high word
-                            // gains only the low 32 bits of (m >> 32) * dh, whose factors
-                            // fit the 24-bit multiplier: one 32x32+64 and one 24x24+32
-                            // multiply-add per sample instead of a full 64x32 product.
+                        for (int k = k0; k < k1; ++k) {
+                            const uint64_t p0 = tones[k].p0, f0 = tones[k].f0;
+                            const int64_t dF = tones[k].coef;
+                            const float amp = tones[k].amp;
                             const uint64_t m = (uint64_t)(dF >> 16);
                             const uint32_t m_lo = (uint32_t)m;
                             const int32_t m_hi = (int32_t)(m >> 32);            // |m_hi| <= 2^15
-                            ph += m * hv[0];
+                            uint64_t ph = p0 + f0 * tile0 + f0 * (uint64_t)j + m * hv0;
 #pragma unroll
                             for (int s = 0; s < S; ++s) {
                                 blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
@@ -338,10 +346,16 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                                     ph += ((uint64_t)hi << 32) | (uint32_t)lo;
                                 }
                             }
-                        } else {
+                        }
+                    } else {
+                        for (int k = k0; k < k1; ++k) {
+                            const uint64_t p0 = tones[k].p0, f0 = tones[k].f0;
+                            const int64_t dF = tones[k].coef;
+                            const float amp = tones[k].amp;
+                            uint64_t ph = p0 + f0 * tile0 + f0 * (uint64_t)j;
 #pragma unroll
                             for (int s = 0; s < S; ++s) {
-                                blk[s] = __builtin_fmaf(amp, word_sin(ph + smooth_term(dF, hv[s])), blk[s]);
+                                blk[s] = __builtin_fmaf(amp, word_sin(ph + smooth_term(dF, H[s])), blk[s]);
                                 ph += f0;
                             }
                         }

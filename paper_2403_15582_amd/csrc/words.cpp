@@ -247,9 +247,13 @@ void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vecto
             nb = (nb + kWaves - 1) / kWaves * kWaves;
             const int32_t base = L / nb, extra = L % nb;
             int32_t b = i;
+            const bool smooth = tones[i].shape == AWG_RAMP_COSINE || tones[i].shape == AWG_RAMP_MINJERK;
             for (int32_t q = 0; q < nb; ++q) {
                 const int32_t c = base + (q < extra ? 1 : 0);
-                out->push_back(Block{(uint32_t)b, (uint16_t)c, (uint16_t)(kBlockUniform | flags)});
+                bool step16 = smooth;
+                for (int32_t k = b; step16 && k < b + c; ++k) step16 = (tones[k].coef & 0xffff) == 0;
+                out->push_back(Block{(uint32_t)b, (uint16_t)c,
+                                     (uint16_t)(kBlockUniform | flags | (step16 ? kBlockStep16 : 0))});
                 b += c;
             }
         } else {
