@@ -437,7 +437,10 @@ static awg_status hipst(hipError_t e)
 template <typename T>
 static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32, hipStream_t s)
 {
-    const uint64_t mcols = count >= (1ull << 20) ? 4096 : 1024;
+    // columns per row: long requests take long rows, so that the per-call A
+    // operand (rows x 2K) stays small while B (2K x columns, cached in the plan)
+    // grows; 2^24 samples make 1024 rows of 16384 (4 x 64 tiles of 256 x 256)
+    const uint64_t mcols = count >= (1ull << 24) ? 16384 : count >= (1ull << 20) ? 4096 : 1024;
     const uint64_t rows = (count + mcols - 1) / mcols;
     const int32_t rb_pad = (int32_t)(((rows + 31) / 32 + kTileRB - 1) / kTileRB * kTileRB);
     const int32_t cb_n = (int32_t)(mcols / 32);

@@ -45,7 +45,7 @@ def test_static_period_full_mfma(method):
 
 
 @pytest.mark.parametrize("n0,count", [(12345, (1 << 20) + 777), (3, 1 << 16), (2 ** 41 + 9, 300000),
-                                      (0, 5000)])
+                                      (0, 5000), (5, (1 << 24) + 1234)])
 def test_mfma_ragged_ranges(n0, count):
     torch = need_gpu()
     w = W.static_period(K=333)
