@@ -94,10 +94,24 @@ def cpu_baseline(w, q_gpu, seconds):
     dt = time.perf_counter() - t0
     ts = len(w.tones) * count
     dq = int(np.max(np.abs(q_gpu[start:start + count].astype(np.int32) - qo.astype(np.int32))))
+    # the same oracle on one core, over a shorter stretch of the same sample (about 2 s)
+    one = int(min(count, max(256, count * 2.0 / max(dt * threads, 1e-6))))
+    t0 = time.perf_counter()
+    csynth.synth(op, start, one, threads=1, packed=pk)
+    dt1 = time.perf_counter() - t0
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": ts / dt, "unit": "tone-samples/s", "cores": threads, "kind": "oracle",
             "sample": "samples [%d, %d) of the %d-sample buffer, all %d tones (%.1f s)"
                       % (start, start + count, w.count, len(w.tones), dt),
-            "max_dq_lsb_vs_gpu": dq}
+            "max_dq_lsb_vs_gpu": dq,
+            "value_one_core": len(w.tones) * one / dt1, "one_core_sample": "samples [%d, %d) (%.1f s)"
+                                                                         % (start, start + one, dt1),
+            "host_cpu": cpu}
 
 
 def streaming_leg(torch, awg, W):
