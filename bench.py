@@ -282,8 +282,8 @@ def roofline_for(method, stats, K, L):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the synthesis on a single "
-              "MI355X (see the sharding notes in DESIGN.md); --gpus %d is not supported" % a.gpus,
+        print("bench.py measures one GPU only: the synthesis runs on a single MI355X; "
+              "--gpus %d is not supported" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
