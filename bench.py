@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--legs", default="stream,arrays,serve",
                     help="comma list of extra legs to run: stream, arrays, serve")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="job arrivals per second of the serving leg")
+    ap.add_argument("--static-tones", type=int, default=1000, help="tones of the static 2^24-sample period")
+    ap.add_argument("--stream-shape", default="mixed", choices=["mixed", "linear", "cosine", "minjerk"],
+                    help="ramp shape of the chirped stream")
     ap.add_argument("--arrays-tones", default="5000,10000", help="tone counts of the large-array leg")
     ap.add_argument("--arrays-methods", default="direct,mfma-f16,mfma-bf16", help="methods of the large-array leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -114,10 +118,10 @@ def cpu_baseline(w, q_gpu, seconds):
             "host_cpu": cpu}
 
 
-def streaming_leg(torch, awg, W):
+def streaming_leg(torch, awg, W, shape="mixed"):
     """1000 tones chirped over 35 ms (mixed linear and cosine), streamed in 2^20-sample
     chunks: per-chunk latency and real-time factor."""
-    w = W.chirp_35ms(shape="mixed")
+    w = W.chirp_35ms(shape=shape)
     plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2)
     s = torch.cuda.current_stream()
     n_chunks = w.count // w.chunk
@@ -149,18 +153,18 @@ def streaming_leg(torch, awg, W):
             "latency_note": "device time per 2^20-sample chunk (hipEvents on the launch stream)"}
 
 
-def serving_leg(W, seconds):
+def serving_leg(W, seconds, rate_hz=2000.0):
     """Serving trace in real time: Poisson arrivals of chirp jobs, batched
     by the library's server; latency, throughput and deadline misses."""
     from paper_2403_15582_amd.serving import Server
-    jobs = W.poisson_jobs(seconds=seconds)
+    jobs = W.poisson_jobs(seconds=seconds, rate_hz=rate_hz)
     with Server(mem_budget_bytes=1 << 30, max_jobs=512, ring_slots=256, playout_delay_ms=5.0) as srv:
         t0 = time.perf_counter()
         srv.run_trace(jobs, time_scale=1.0, timeout_s=300.0)
         wall = time.perf_counter() - t0
         st = srv.stats()
     offered = sum(len(j.tones) * j.n_samples for j in jobs) / seconds
-    return {"workload": "poisson-chirp-jobs-2000/s", "jobs": len(jobs), "arrival_seconds": seconds,
+    return {"workload": "poisson-chirp-jobs-%g/s" % rate_hz, "jobs": len(jobs), "arrival_seconds": seconds,
             "offered_tone_samples_per_s": offered,
             "tone_samples_per_s": st["tone_samples"] / (st["wall_ms"] * 1e-3),
             "device_busy_frac": st["device_busy_ms"] / st["wall_ms"],
@@ -300,7 +304,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
         return
-    w = W.static_period()
+    w = W.static_period(K=a.static_tones)
     K, L = len(w.tones), w.count
     codes = method_codes(awg)
     # auto: BF16 hi/lo x3, the fastest method that keeps the int16 bar (it issues the
@@ -363,14 +367,14 @@ def main():
     legs = set() if a.no_stream else set(x for x in a.legs.split(",") if x)
     if "stream" in legs:
         log("streaming leg ...")
-        res["streaming"] = streaming_leg(torch, awg, W)
+        res["streaming"] = streaming_leg(torch, awg, W, a.stream_shape)
     if "arrays" in legs:
         log("large-array legs ...")
         res["large_arrays"] = [large_array_leg(torch, awg, W, int(K), m) for K in a.arrays_tones.split(",")
                                for m in a.arrays_methods.split(",")]
     if "serve" in legs:
         log("serving leg ...")
-        res["serving"] = serving_leg(W, a.serve_seconds)
+        res["serving"] = serving_leg(W, a.serve_seconds, a.serve_rate)
     print(json.dumps(res), flush=True)
 
 
