@@ -197,6 +197,11 @@ awg_status awg_plan_amplitude(awg_plan *plan, const awg_amp_ramp *events, int32_
 
 /* Static pathway: samples n0 .. n0+count-1 of a plan without ramp windows into
  * d_out (int16, count entries). The method comes from the plan's flags.
+ * The direct method gives each sample independently of the range. The MFMA
+ * methods cut the range into rows from n0 and, for requests with few output
+ * tiles, split the tone sum into slices added in a fixed order afterwards: the
+ * codes depend on (n0, count) within the same error bar, and equal calls give
+ * equal samples.
  * AWG_E_UNSUPPORTED if the plan has ramps; AWG_E_RANGE if n0 + count >= 2^63. */
 awg_status awg_synth_static(awg_plan *plan, uint64_t n0, uint64_t count, int16_t *d_out,
                             void *hip_stream);

@@ -40,6 +40,7 @@ typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int kTileRB = 8;            // row blocks per workgroup tile (256 rows)
+constexpr int32_t kTargetGroups = 256; // workgroups a product should reach (one 8-wave workgroup per CU)
 constexpr int kTileCB = 8;            // column blocks per workgroup tile (256 columns)
 constexpr int kFragBytes = 64 * 16;   // one 32x16 fragment of 16-bit values
 
@@ -434,6 +435,38 @@ static awg_status hipst(hipError_t e)
     return e == hipErrorOutOfMemory ? AWG_E_NOMEM : AWG_E_HIP;
 }
 
+// Split-K products of short requests: sample i is the sum of planes[z * plane
+// + i] over the slices z in order, rounded to int16 (or kept in FP32).
+__global__ __launch_bounds__(256) void plane_sum_kernel(const float *__restrict__ planes, int32_t gz,
+                                                        uint64_t plane, uint64_t count, int16_t *__restrict__ out_i16,
+                                                        float *__restrict__ out_f32)
+{
+    const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= count) return;
+    float y[4];
+    if (i0 + 4 <= count) {
+        const float4 u = *(const float4 *)(planes + i0);
+        y[0] = u.x; y[1] = u.y; y[2] = u.z; y[3] = u.w;
+        for (int32_t z = 1; z < gz; ++z) {
+            const float4 v = *(const float4 *)(planes + (uint64_t)z * plane + i0);
+            y[0] += v.x; y[1] += v.y; y[2] += v.z; y[3] += v.w;
+        }
+    } else {
+        for (int e = 0; e < 4; ++e) {
+            y[e] = 0.0f;
+            if (i0 + e < count) {
+                y[e] = planes[i0 + e];
+                for (int32_t z = 1; z < gz; ++z) y[e] += planes[(uint64_t)z * plane + i0 + e];
+            }
+        }
+    }
+    for (int e = 0; e < 4; ++e) {
+        if (i0 + e >= count) break;
+        if (out_f32) out_f32[i0 + e] = y[e];
+        else out_i16[i0 + e] = to_i16(y[e]);
+    }
+}
+
 template <typename T>
 static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32, hipStream_t s)
 {
@@ -448,7 +481,18 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     const int32_t kb_n = (n_groups + 1) / 2;          // k-blocks of 8 tones (zero-padded)
     const size_t frag = kFragBytes;
     const size_t a_bytes = (size_t)kb_n * rb_pad * frag, b_bytes = (size_t)kb_n * cb_n * frag;
-    const size_t need = 2 * (a_bytes + b_bytes);
+    // short requests have few output tiles: split the inner dimension over up to
+    // kTargetGroups workgroups (FP32 partial planes, summed in slice order after)
+    const int32_t tiles = (rb_pad / kTileRB) * (cb_n / kTileCB);
+    int32_t gz = 1, kb_split = kb_n;
+    if (tiles < kTargetGroups && kb_n > 1) {
+        gz = std::min(kb_n, (kTargetGroups + tiles - 1) / tiles);
+        kb_split = (kb_n + gz - 1) / gz;
+        gz = (kb_n + kb_split - 1) / kb_split;
+    }
+    const uint64_t plane = rows * mcols;
+    const size_t plane_bytes = gz > 1 ? (size_t)gz * plane * sizeof(float) : 0;
+    const size_t need = 2 * (a_bytes + b_bytes) + plane_bytes;
     if (rows > (1ull << 26)) return AWG_E_UNSUPPORTED;
     // calls on one plan may come from several host threads and streams: one at a
     // time here, and each stream waits for the previous user of the workspace
@@ -494,11 +538,22 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
         if (e != hipSuccess) return hipst(e);
         p->mfma_b_key = b_key;
     }
-    dim3 grid((uint32_t)(cb_n / kTileCB), (uint32_t)(rb_pad / kTileRB));
+    dim3 grid((uint32_t)(cb_n / kTileCB), (uint32_t)(rb_pad / kTileRB), (uint32_t)gz);
+    float *planes = (float *)(w + 2 * (a_bytes + b_bytes));
     {
         ProfScope prof(p->ctx, s, f16 ? "angle_gemm_kernel_f16" : "angle_gemm_kernel_bf16");
-        e = dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_n, 0, mcols, count,
-                             out_i16, out_f32);
+        if (gz == 1)
+            e = dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_n, 0, mcols, count,
+                                 out_i16, out_f32);
+        else
+            e = dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols,
+                                 count, nullptr, planes);
+    }
+    if (e == hipSuccess && gz > 1) {
+        ProfScope prof(p->ctx, s, "plane_sum_kernel");
+        prof.launch(plane_sum_kernel, dim3((uint32_t)((count + 1023) / 1024)), dim3(256), 0, (const float *)planes,
+                    gz, plane, count, out_i16, out_f32);
+        e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(p->work_done, s);
     if (e == hipSuccess) p->work_used = true;
@@ -507,7 +562,6 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
 
 LinesGeom lines_geometry(int32_t n_entries, int32_t max_entries, uint64_t count)
 {
-    constexpr int32_t kTargetGroups = 256;          // one 8-wave workgroup per CU
     const uint64_t mcols = kTileSamples;
     const uint64_t rows = (count + mcols - 1) / mcols;
     LinesGeom g;

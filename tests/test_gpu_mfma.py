@@ -141,3 +141,24 @@ def test_mfma_more_groups_than_one_launch():
     qo, yo = csynth.synth_at(words.Plan(fs, 0.0, 0, t), ns)
     compare(q[ns - n0], y[ns - n0], qo, yo, "mfma %d tones (sampled %d)" % (K, len(ns)))
     lp.close()
+
+
+@pytest.mark.parametrize("method", [F16, BF16])
+@pytest.mark.parametrize("n0,count", [(7, 1 << 16), (1 << 33, (1 << 18) + 3), (99, (1 << 20) + 5),
+                                      (0, 1 << 22)])
+def test_mfma_short_requests_split_k(method, n0, count):
+    """Requests with fewer output tiles than compute units sum their tones in
+    slices (FP32 planes added in order): same bar as the one-slice product."""
+    torch = need_gpu()
+    w = W.static_period()
+    lp = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, method)
+    say("mfma split-K n0=%d count=%d method=%d" % (n0, count, method))
+    q = to_np(lp.synth_static(n0, count))
+    y = to_np(lp.synth_f32(n0, count, method=method))
+    q2 = to_np(lp.synth_static(n0, count))
+    torch.cuda.synchronize()
+    assert np.array_equal(q, q2), "repeated call differs"
+    ns = _pts(np.random.default_rng(53), n0, count)
+    qo, yo = csynth.synth_at(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), ns)
+    compare(q[ns - n0], y[ns - n0] if method == F16 else None, qo, yo,
+            "mfma split-K n0=%d count=%d method=%d" % (n0, count, method))
