@@ -16,6 +16,7 @@ Also reported:
                 int16 error of the GPU result on that sample
   streaming     a chirped stream (1000 tones, 35 ms linear/cosine ramps, 2^20-sample
                 chunks): per-chunk latency p50/p99 and real-time factor
+  short_requests  static calls of 2^16 .. 2^22 samples on each method (wall clock)
 Prints one JSON line.
 """
 import argparse
@@ -50,8 +51,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming, serving and large-array legs")
-    ap.add_argument("--legs", default="stream,arrays,serve",
-                    help="comma list of extra legs to run: stream, arrays, serve")
+    ap.add_argument("--legs", default="stream,arrays,serve,short",
+                    help="comma list of extra legs to run: stream, arrays, serve, short")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="job arrivals per second of the serving leg")
     ap.add_argument("--static-tones", type=int, default=1000, help="tones of the static 2^24-sample period")
@@ -283,6 +284,33 @@ def roofline_for(method, stats, K, L):
                     "issues 3x that on the matrix cores (issued_*)"}
 
 
+def short_requests_leg(torch, awg, w, codes, reps=20):
+    """Static requests shorter than the 2^24-sample period (2^16 .. 2^22 samples from
+    a moving n0) on each method: wall clock per call, streams of back-to-back calls."""
+    K = len(w.tones)
+    rows = []
+    for lg in (16, 18, 20, 22):
+        count = 1 << lg
+        out = torch.empty(count, dtype=torch.int16, device="cuda")
+        row = {"samples": count}
+        for m in ("direct", "mfma-bf16", "mfma-f16"):
+            plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, codes[m])
+            for i in range(5):
+                plan.synth_static(i * count, count, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(reps):
+                plan.synth_static((5 + i) * count, count, out=out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            row[m] = {"ms_per_call": ms, "tone_samples_per_s": K * count / (ms * 1e-3)}
+            plan.close()
+        log("short %8d samples: direct %.3f  bf16 %.3f  f16 %.3f ms" % (
+            count, row["direct"]["ms_per_call"], row["mfma-bf16"]["ms_per_call"], row["mfma-f16"]["ms_per_call"]))
+        rows.append(row)
+    return {"tones": K, "timing": "host wall clock over %d back-to-back calls per size" % reps, "rows": rows}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -372,6 +400,9 @@ def main():
         log("large-array legs ...")
         res["large_arrays"] = [large_array_leg(torch, awg, W, int(K), m) for K in a.arrays_tones.split(",")
                                for m in a.arrays_methods.split(",")]
+    if "short" in legs:
+        log("short-request leg ...")
+        res["short_requests"] = short_requests_leg(torch, awg, w, codes)
     if "serve" in legs:
         log("serving leg ...")
         res["serving"] = serving_leg(W, a.serve_seconds, a.serve_rate)
