@@ -89,16 +89,26 @@ __device__ __forceinline__ void edge_run(const ToneDev &t, const uint64_t *const
     int64_t d = (int64_t)(n - t.a);                    // |d| < 2^62 for valid inputs
     const int64_t N = (int64_t)t.n;
     if (t.shape == AWG_RAMP_LINEAR) {
-        const uint64_t R = (uint64_t)t.coef, h = (uint64_t)(t.coef >> 1), Rh = R - h;
+        // sample s lies before the window for s < s_lo and inside it for
+        // s_lo <= s < s_hi (32-bit thresholds: the per-sample tests compare
+        // against the unrolled constant s)
+        const int32_t s_lo = (int32_t)(d >= 0 ? 0 : (-d >= S ? S : -d));
+        const int32_t s_hi = (int32_t)(d >= N ? 0 : (N - d >= S ? S : N - d));
+        const uint64_t R = (uint64_t)t.coef, h = (uint64_t)(t.coef >> 1), r = R & 1u;
+        // in-window increment f0 + R d + floor(R/2) (d even) or f0 + R d + R - floor(R/2)
+        // (d odd), carried along for every d (it is only taken inside the window);
+        // it moves by R + r from an even d and by R - r from an odd one
+        uint64_t inc = t.f0 + R * (uint64_t)d + ((d & 1) ? R - h : h);
+        const uint64_t De = R + r, Do = R - r;
+        const uint64_t D0 = (d & 1) ? Do : De, D1 = (d & 1) ? De : Do;   // steps after even / odd s
         uint64_t ph = phase_general(t, tables, n);
-        uint64_t Rd = R * (uint64_t)d;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             f(s, ph);
-            const uint64_t in = t.f0 + Rd + ((d & 1) ? Rh : h);
-            ph += d < 0 ? t.f0 : (d < N ? in : t.f1);
-            ++d;
-            Rd += R;
+            if (s + 1 < S) {
+                ph += s < s_lo ? t.f0 : (s < s_hi ? inc : t.f1);
+                inc += (s & 1) ? D1 : D0;
+            }
         }
     } else {
         const uint64_t *H = table_of(tables, t.table);
@@ -362,6 +372,9 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                     }
                 }
             } else {
+                // a window edge inside the tile: the slowest tiles of a launch, so
+                // two tones at a time for two independent chains per lane
+#pragma unroll 2
                 for (int k = k0; k < k1; ++k) {
                     const ToneDev t = tones[k];
                     const float amp = t.amp;
