@@ -371,6 +371,47 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                         }
                     }
                 }
+            } else if (r.shape != AWG_RAMP_LINEAR && (bk.flags & kBlockStep16) && table_monotone(tables, r.table)) {
+                // a smooth window's edge inside the tile, every dF a multiple of 2^16:
+                // the word is line(d) + m H[clamp(d, 0, N)] with the line p0 + f0 n up
+                // to the window's end and the post-window line after it, so it moves
+                // by f0 (d < N) or f1, plus m times the step of the clamped table
+                // (zero outside the window). The clamped table values of the lane's
+                // samples serve every tone of the block.
+                const uint64_t n = tile0 + j;
+                const int64_t d0 = (int64_t)(n - r.a), N = (int64_t)r.n;
+                const int32_t s_hi = (int32_t)(d0 >= N ? 0 : (N - d0 >= S ? S : N - d0));
+                const uint64_t *H = table_of(tables, r.table);
+                auto at = [&](int64_t d) { return H[d < 0 ? 0 : (d < N ? d : N)]; };
+                const uint64_t hv0 = at(d0);
+                uint32_t dh[S];
+                uint64_t prev = hv0;
+#pragma unroll
+                for (int s = 0; s + 1 < S; ++s) {
+                    const uint64_t cur = at(d0 + s + 1);
+                    dh[s] = (uint32_t)(cur - prev);
+                    prev = cur;
+                }
+                // two tones at a time: the edge tiles finish last
+#pragma unroll 2
+                for (int k = k0; k < k1; ++k) {
+                    const uint64_t p0 = tones[k].p0, f0 = tones[k].f0, f1 = tones[k].f1;
+                    const int64_t dF = tones[k].coef;
+                    const float amp = tones[k].amp;
+                    const uint64_t m = (uint64_t)(dF >> 16);
+                    const uint32_t m_lo = (uint32_t)m;
+                    const int32_t m_hi = (int32_t)(m >> 32);            // |m_hi| <= 2^15
+                    uint64_t ph = (d0 < N ? p0 + f0 * n : p0 + f0 * (r.a + r.n) + f1 * (uint64_t)(d0 - N)) + m * hv0;
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+                        if (s + 1 < S) {
+                            const uint64_t lo = (uint64_t)m_lo * dh[s] + (s < s_hi ? f0 : f1);
+                            const uint32_t hi = (uint32_t)(lo >> 32) + (uint32_t)__mul24(m_hi, (int32_t)dh[s]);
+                            ph += ((uint64_t)hi << 32) | (uint32_t)lo;
+                        }
+                    }
+                }
             } else {
                 // a window edge inside the tile: the slowest tiles of a launch, so
                 // two tones at a time for two independent chains per lane

@@ -254,6 +254,34 @@ def rearrangement(seed=14, K=100, off_frac=0.5, fs_hz=FS_280, f_lo=75e6, f_hi=12
     return w
 
 
+def edge_blocks(seed=15, group=8, fs_hz=FS_280):
+    """Groups of ``group`` tones sharing one window and shape (so the kernels
+    take a group's regime once per 1024-sample tile), with window edges at
+    chosen offsets inside tiles (first sample, second, just before and after a
+    lane's 16 samples, the last sample) and windows of 1 sample up to several
+    tiles; each (offset, length) pair is carried by one linear, one
+    raised-cosine and one minimum-jerk group. Bin frequencies (L = 2^20), so
+    every frequency step is a multiple of 2^16 of the word."""
+    offsets = [0, 1, 7, 15, 16, 17, 500, 1023]
+    lens = [1, 2, 5, 15, 16, 17, 1000, 3000]
+    specs = [(1024 * (2 + 3 * i) + off, n) for i, (off, n) in enumerate(zip(offsets, lens))]
+    shapes = [RAMP_LINEAR, RAMP_COSINE, RAMP_MINJERK]
+    r = _rng(seed)
+    K = len(specs) * len(shapes) * group
+    f0, f1 = _chirp_ends(r, K, 0.05 * fs_hz, 0.45 * fs_hz, 0.02 * fs_hz)
+    t = static_tones(f0, r.uniform(0.2, 1.0, K), r.random(K))
+    t["f_end_hz"] = f1
+    k = 0
+    for a, n in specs:
+        for sh in shapes:
+            for _ in range(group):
+                t[k]["ramp"] = sh
+                t[k]["ramp_start"] = a
+                t[k]["ramp_len"] = n
+                k += 1
+    return Workload("edge-blocks", fs_hz, 0.0, 20, t, 0, 1024 * (2 + 3 * len(specs)) + 333)
+
+
 def small_mixed(seed=11, K=24, fs_hz=FS_280, n_total=5000, period_log2=0):
     """Small tone set covering every ramp shape and regime (pre / in / post
     window, windows straddling tile edges, rising and falling chirps), for

@@ -75,6 +75,24 @@ def test_small_mixed_int16_and_f32(n0, count):
     compare(q, y, qo, yo, "small_mixed n0=%d count=%d" % (n0, count))
 
 
+@pytest.mark.parametrize("n0,count", [(0, None), (2000, 9000), (1024 * 7 + 15, 1024 * 5 + 3)])
+def test_window_edges_in_shared_blocks(n0, count):
+    """Groups of tones sharing a window whose edges fall at every awkward
+    offset inside a tile (linear, raised-cosine and minimum-jerk groups with
+    bin frequencies), every sample against the oracle."""
+    torch = need_gpu()
+    w = W.edge_blocks()
+    count = w.count - n0 if count is None else count
+    op = oracle_plan(w)
+    lp = lib_plan(w)
+    say("edge_blocks int16/f32 n0=%d count=%d" % (n0, count))
+    q = to_np(lp.synth_chirp(n0, count))
+    y = to_np(lp.synth_f32(n0, count))
+    torch.cuda.synchronize()
+    qo, yo = csynth.synth(op, n0, count)
+    compare(q, y, qo, yo, "edge_blocks n0=%d count=%d" % (n0, count))
+
+
 def test_count_zero_and_errors():
     torch = need_gpu()
     w = W.small_mixed()
