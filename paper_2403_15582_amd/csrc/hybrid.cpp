@@ -268,9 +268,25 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
                        align_up(sizeof(ToneDev) * (size_t)p->n_tones, 256) +
                        align_up(sizeof(Block) * ((size_t)p->n_tones + 1), 256) +
                        align_up(sizeof(uint32_t) * (kPiece / kRow), 256) + sizeof(int32_t) * kb_max;
+    hipError_t e = hipSuccess;
+    // the first call sets up every slot, so that the calls after it (the next
+    // chunks of a stream) do not each pay for a pinned allocation
+    if (!h->slots[0].host) {
+        for (auto &sl : h->slots) {
+            if (!sl.done) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+            if (e == hipSuccess && !sl.host) {
+                e = alloc_upload_host(std::max(cap, total), &sl.host, &sl.mapped);
+                if (e == hipSuccess) sl.host_cap = std::max(cap, total);
+            }
+            if (e == hipSuccess && !sl.dev) {
+                e = hipMalloc(&sl.dev, std::max(cap, total));
+                if (e == hipSuccess) sl.dev_cap = std::max(cap, total);
+            }
+            if (e != hipSuccess) return hst(e);
+        }
+    }
     HybridState::Slot &slot = h->slots[h->next];
     h->next = (h->next + 1) % kHybSlots;
-    hipError_t e = hipSuccess;
     if (!slot.done) e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
     if (e == hipSuccess && slot.used) e = hipEventSynchronize(slot.done);
     if (e != hipSuccess) return hst(e);

@@ -38,6 +38,7 @@ namespace {
 constexpr uint32_t kBatchGrid = 2048;   // workgroups of the batched kernel (8 per CU)
 constexpr size_t kItemsOffset = 256;    // work-list items after the 2-word header
 constexpr size_t kAlign = 256;
+constexpr size_t kStageInit = 512 * 1024;   // admission staging buffer set up at creation (~5000 tones)
 
 double now_ms()
 {
@@ -457,6 +458,14 @@ awg_status awg_server_create(awg_ctx *ctx, const awg_server_params *prm, awg_ser
     for (auto &st : s->steps) {
         awg_status rs = build_step(s, st);
         if (rs != AWG_OK) { free_server(s); return rs; }
+    }
+    // admission staging buffers up front: the scheduler then allocates pinned
+    // memory only for a job larger than any before it
+    for (auto &sg : s->stage) {
+        e = alloc_upload_host(kStageInit, &sg.host, &sg.mapped);
+        if (e == hipSuccess) sg.cap = kStageInit;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);
+        if (e != hipSuccess) { free_server(s); return hipst(e); }
     }
     s->th = std::thread(scheduler, s);
     *out = s;
