@@ -184,7 +184,7 @@ def large_array_leg(torch, awg, W, K, method="direct"):
     """Large-array stream: K tones, groups of 100 retuned (1 ms linear chirps)
     in turn, 2^20-sample chunks over 1 s of output; per-chunk device time. With a
     matrix-core method the chunks take the hybrid path (line tones on the matrix
-    cores, ramping tones on the direct kernel); the last 12 chunks run again with
+    cores, ramping tones on the direct kernel); the last 11 chunks run again with
     kernel timing on for the per-kernel split."""
     w = W.array_group_chirps(K=K)
     plan = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, method_codes(awg)[method])
@@ -220,11 +220,16 @@ def large_array_leg(torch, awg, W, K, method="direct"):
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     chunk_s = w.chunk / w.fs_hz
     # per-kernel split: the last 12 chunks again (within one retune cycle, so the
-    # tones still hold the windows those chunks were streamed with)
+    # tones still hold the windows those chunks were streamed with); the first of
+    # them runs untimed, since it rebuilds the B operand for lines that changed
+    # since the stream's last chunk
     ctx = awg.context(0)
+    first = max(0, n_chunks - 12)
+    plan.synth_chirp(first * w.chunk, w.chunk, out=buf[first % 2])
+    torch.cuda.synchronize()
     awg.awg_profile_read(ctx, reset=True)
     awg.awg_profile_enable(ctx, True)
-    for c in range(max(0, n_chunks - 12), n_chunks):
+    for c in range(first + 1, n_chunks):
         plan.synth_chirp(c * w.chunk, w.chunk, out=buf[c % 2])
     torch.cuda.synchronize()
     awg.awg_profile_enable(ctx, False)
