@@ -166,6 +166,10 @@ struct awg_plan {
     struct Slot { void *host; void *mapped; hipEvent_t done; bool used; };
     std::vector<Slot> slots;
     size_t next_slot;
+    // duplicate-tone check of one retune or amplitude call: ev_stamp[tone] ==
+    // ev_gen marks a tone already named in the call being validated
+    std::vector<uint32_t> ev_stamp;
+    uint32_t ev_gen;
     // MFMA workspace (operands), grown on demand; B operand cached under mfma_b_key
     void *d_work;
     size_t d_work_bytes;

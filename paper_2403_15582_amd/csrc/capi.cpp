@@ -20,9 +20,7 @@ constexpr uint64_t kHybridMin = 1ull << 16;           // shortest request for th
 constexpr uint64_t kMaxSample = 1ull << 63;          // n0 + count must stay below
 constexpr size_t kTablePtrCap = 1024;                 // distinct smooth tables per plan
 constexpr size_t kSlots = 16;                         // retune staging slots
-constexpr size_t kSlotRecords = 16384;                // records per slot
-// the block table's offset in a retune slot (after the records, 16-byte aligned)
-constexpr size_t kBlockOffset = (sizeof(ScatterRecord) * kSlotRecords + 15) / 16 * 16;
+constexpr size_t kSlotRecords = 16384;                // events per call (records per slot)
 
 awg_status hip_status(hipError_t e)
 {
@@ -149,6 +147,35 @@ awg_status device_ready(awg_plan *p)
     if (!p->ctx) return AWG_E_INVALID;
     hipError_t e = hipSetDevice(p->ctx->device);
     return hip_status(e);
+}
+
+// The block table's offset in a retune slot: after the records of one call
+// (at most one per tone, at most kSlotRecords), 16-byte aligned.
+size_t slot_block_offset(const awg_plan *p)
+{
+    const size_t recs = std::min(kSlotRecords, (size_t)p->n_tones);
+    return (sizeof(ScatterRecord) * recs + 15) / 16 * 16;
+}
+
+// Starts the duplicate-tone check of one event list.
+void begin_event_check(awg_plan *p)
+{
+    if (p->ev_stamp.size() != (size_t)p->n_tones) {
+        p->ev_stamp.assign((size_t)p->n_tones, 0);
+        p->ev_gen = 0;
+    }
+    if (++p->ev_gen == 0) {                      // wrapped: clear the stamps
+        std::fill(p->ev_stamp.begin(), p->ev_stamp.end(), 0);
+        p->ev_gen = 1;
+    }
+}
+
+// True when tone t was already named since begin_event_check.
+bool seen_tone(awg_plan *p, int32_t t)
+{
+    if (p->ev_stamp[t] == p->ev_gen) return true;
+    p->ev_stamp[t] = p->ev_gen;
+    return false;
 }
 
 }  // namespace
@@ -416,6 +443,7 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
     if (n_ev == 0) return AWG_OK;
     if ((size_t)n_ev > kSlotRecords) return AWG_E_UNSUPPORTED;
     // validate all events first so that a failing call changes nothing
+    try { begin_event_check(p); } catch (...) { return AWG_E_NOMEM; }
     std::vector<ToneHost> next;
     std::vector<uint16_t> tidx;
     try { next.resize(n_ev); tidx.resize(n_ev); } catch (...) { return AWG_E_NOMEM; }
@@ -424,8 +452,7 @@ awg_status awg_plan_retune(awg_plan *p, const awg_retune *ev, int32_t n_ev, void
         if (r.tone < 0 || r.tone >= p->n_tones) return AWG_E_INVALID;
         if (!(r.ramp == AWG_RAMP_LINEAR || smooth(r.ramp))) return AWG_E_INVALID;
         if (!std::isfinite(r.f_end_hz)) return AWG_E_INVALID;
-        for (int32_t j = 0; j < i; ++j)
-            if (ev[j].tone == r.tone) return AWG_E_UNSUPPORTED;   // one window per tone and call
+        if (seen_tone(p, r.tone)) return AWG_E_UNSUPPORTED;    // one window per tone and call
         const ToneHost &cur = p->host[r.tone];
         const uint64_t free_from = cur.shape == AWG_RAMP_NONE ? 0 : cur.a + cur.n;
         if (r.ramp_start < free_from) return AWG_E_RANGE;
@@ -473,6 +500,7 @@ awg_status awg_plan_amplitude(awg_plan *p, const awg_amp_ramp *ev, int32_t n_ev,
     if (!p || (n_ev > 0 && !ev) || n_ev < 0) return AWG_E_INVALID;
     if (n_ev == 0) return AWG_OK;
     if ((size_t)n_ev > kSlotRecords) return AWG_E_UNSUPPORTED;
+    try { begin_event_check(p); } catch (...) { return AWG_E_NOMEM; }
     std::vector<ToneHost> next;
     try { next.resize(n_ev); } catch (...) { return AWG_E_NOMEM; }
     for (int32_t i = 0; i < n_ev; ++i) {
@@ -480,8 +508,7 @@ awg_status awg_plan_amplitude(awg_plan *p, const awg_amp_ramp *ev, int32_t n_ev,
         if (r.tone < 0 || r.tone >= p->n_tones) return AWG_E_INVALID;
         if (!(r.ramp == AWG_RAMP_LINEAR || smooth(r.ramp))) return AWG_E_INVALID;
         if (!std::isfinite(r.amplitude_end) || r.amplitude_end < 0.0) return AWG_E_INVALID;
-        for (int32_t j = 0; j < i; ++j)
-            if (ev[j].tone == r.tone) return AWG_E_UNSUPPORTED;   // one window per tone and call
+        if (seen_tone(p, r.tone)) return AWG_E_UNSUPPORTED;    // one window per tone and call
         if (r.ramp_len == 0 || r.ramp_len >= (1ull << 31)) return AWG_E_RANGE;
         if (r.ramp_start >= kMaxSample || r.ramp_len >= kMaxSample - r.ramp_start) return AWG_E_RANGE;
         const ToneHost &cur = p->host[r.tone];
@@ -524,7 +551,7 @@ static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, 
             s.host = nullptr; s.mapped = nullptr; s.done = nullptr; s.used = false;
         }
         for (auto &s : p->slots) {
-            e = alloc_upload_host(kBlockOffset + sizeof(Block) * ((size_t)p->n_tones + 1), &s.host, &s.mapped);
+            e = alloc_upload_host(slot_block_offset(p) + sizeof(Block) * ((size_t)p->n_tones + 1), &s.host, &s.mapped);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
             if (e != hipSuccess) return hip_status(e);
         }
@@ -544,10 +571,10 @@ static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, 
     }
     e = launch_scatter_tones(p->d_tones, slot.mapped, n_ev, s);
     // the block table follows the records in the same pinned slot
-    Block *blk = (Block *)((char *)slot.host + kBlockOffset);
+    Block *blk = (Block *)((char *)slot.host + slot_block_offset(p));
     const size_t blk_bytes = sizeof(Block) * p->blocks.size();
     std::memcpy(blk, p->blocks.data(), blk_bytes);
-    if (e == hipSuccess) e = launch_upload((const char *)slot.mapped + kBlockOffset, p->d_blocks, blk_bytes, s);
+    if (e == hipSuccess) e = launch_upload((const char *)slot.mapped + slot_block_offset(p), p->d_blocks, blk_bytes, s);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     slot.used = true;
     return hip_status(e);

@@ -224,6 +224,15 @@ def test_amplitude_ramp_validation_and_counts():
                 awg.awg_plan_amplitude(plan, events)
             assert e.value.status == status, events
         assert awg.awg_plan_info_get(plan)["n_ramped"] == 3            # failed calls change nothing
+        # a tone named twice in a failed call can be named once in the next one,
+        # and a duplicate at the end of a long list is still found
+        awg.awg_plan_amplitude(plan, [(6, L, 0, 10, 0.0)])
+        many = [(k, L, 1000, 10, 0.5) for k in range(7, len(w.tones))]
+        with pytest.raises(awg.AwgError) as e:
+            awg.awg_plan_amplitude(plan, many + [(len(w.tones) - 1, L, 5000, 10, 0.5)])
+        assert e.value.status == awg.AWG_E_UNSUPPORTED
+        awg.awg_plan_amplitude(plan, many)
+        assert awg.awg_plan_info_get(plan)["n_ramped"] == 4 + len(many)
         with pytest.raises(awg.AwgError) as e:
             awg.awg_synth_static(plan, 0, 16, 1234)                     # host-only, and no longer static
         assert e.value.status == awg.AWG_E_INVALID
