@@ -49,6 +49,26 @@ def test_row_edges_every_sample_against_oracle(method):
     assert np.array_equal(q, q2)
 
 
+@pytest.mark.parametrize("method", [F16, BF16])
+def test_edge_blocks_hybrid_every_sample(method):
+    """Groups of tones sharing a window (linear, raised cosine, minimum jerk; bin
+    frequencies) with edges at every awkward offset inside a row: the ramping
+    rows on the direct kernel's block-wise edge steps, the rest on the product."""
+    torch = need_gpu()
+    w = W.edge_blocks()
+    hp, dp = _plans(w, method)
+    n0, count = 5, 80000
+    say("edge-blocks hybrid method=%d n0=%d count=%d" % (method, n0, count))
+    q = to_np(hp.synth_chirp(n0, count))
+    y = to_np(hp.synth_f32(n0, count, method=method))
+    qd = to_np(dp.synth_chirp(n0, count))
+    torch.cuda.synchronize()
+    op = words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones)
+    qo, yo = csynth.synth(op, n0, count)
+    compare(q, y, qo, yo, "edge-blocks hybrid method=%d" % method)
+    assert int(np.abs(q.astype(np.int32) - qd).max()) <= TOL_Q
+
+
 def test_short_request_is_the_direct_kernel():
     torch = need_gpu()
     w = W.row_edges()
