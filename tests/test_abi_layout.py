@@ -58,3 +58,15 @@ def test_struct_layouts_match_the_header(tmp_path):
     # every field of the C struct is mirrored: the last offset plus its size is the size
     last = TONE_DTYPE.names[-1]
     assert TONE_DTYPE.fields[last][1] + TONE_DTYPE.fields[last][0].itemsize == TONE_DTYPE.itemsize
+
+
+def test_plain_c_consumer_compiles_and_links(tmp_path):
+    """tests/c/abi_consumer.c builds as strict C99 against include/awg.h and links
+    libawg.so (the GPU test runs it)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("build_consumer", os.path.join(ROOT, "tests", "c", "build_consumer.py"))
+    bc = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bc)
+    exe = bc.build(str(tmp_path / "abi_consumer"))
+    out = subprocess.run(["ldd", exe], check=True, capture_output=True, text=True).stdout
+    assert "libawg.so" in out and "not found" not in out
