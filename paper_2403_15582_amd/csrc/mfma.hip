@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 #include <type_traits>
 
 #include "awg_internal.h"
@@ -362,15 +363,25 @@ static hipError_t launch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T
                               uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32)
 {
     constexpr int kLds = NST * 4 * kTileRB * kFragBytes;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)angle_gemm_kernel<T, true, WR, WC, NST>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLds);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)angle_gemm_kernel<T, false, WR, WC, NST>,
+    // the dynamic LDS limit is raised once per device (calls may come from
+    // several host threads and contexts on several devices)
+    static std::mutex mu;
+    static uint64_t set_mask = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        const uint64_t bit = dev < 64 ? 1ull << dev : 0;
+        if (!bit || !(set_mask & bit)) {
+            e = hipFuncSetAttribute((const void *)angle_gemm_kernel<T, true, WR, WC, NST>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, kLds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void *)angle_gemm_kernel<T, false, WR, WC, NST>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLds);
+            if (e != hipSuccess) return e;
+            set_mask |= bit;
+        }
     }
     if (out_f32)
         prof.launch(angle_gemm_kernel<T, true, WR, WC, NST>, grid, dim3(64 * WR * WC), (uint32_t)kLds, a_hi,
@@ -386,11 +397,10 @@ static hipError_t launch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T
 // MI355X; the environment variable AWG_GEMM_VARIANT overrides it for tuning sweeps.
 static int gemm_variant()
 {
-    static int v = -1;
-    if (v < 0) {
+    static const int v = [] {
         const char *e = getenv("AWG_GEMM_VARIANT");
-        v = (e && e[0] >= '0' && e[0] <= '5') ? e[0] - '0' : 3;
-    }
+        return (e && e[0] >= '0' && e[0] <= '5') ? e[0] - '0' : 3;
+    }();
     return v;
 }
 
