@@ -387,8 +387,9 @@ typedef struct {
  * enable = 0 switches it off; enable = n >= 1 times one launch in n of each
  * kernel (the 1st, n+1-th, ... since this call; 1 = every launch). A timed
  * launch costs the stream some microseconds (the dispatch records its start
- * and stop events), so sampling keeps the overhead of a long run small.
- * AWG_E_INVALID for enable < 0. */
+ * and stop events), so sampling keeps the overhead of a long run small. At
+ * most 65,536 timed launches are held until the next awg_profile_read; later
+ * ones run untimed. AWG_E_INVALID for enable < 0. */
 awg_status awg_profile_enable(awg_ctx *ctx, int32_t enable);
 /* Synchronise the recorded events and return up to max_stats per-kernel totals
  * in out (host array); *n_stats receives the number of distinct kernels. With

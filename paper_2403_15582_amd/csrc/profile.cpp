@@ -10,6 +10,10 @@
 
 namespace awg {
 
+// timed launches held between two reads; later launches go untimed until the
+// next awg_profile_read folds the held ones into the totals
+constexpr size_t kMaxPending = 65536;
+
 static hipEvent_t take_event(awg_ctx *c)
 {
     hipEvent_t e = nullptr;
@@ -30,6 +34,7 @@ ProfScope::ProfScope(awg_ctx *ctx, hipStream_t s, const char *name)
     if (period <= 0) return;
     std::lock_guard<std::mutex> g(ctx_->prof_mu);
     if (ctx_->prof_seen[name_]++ % (uint64_t)period != 0) return;
+    if (ctx_->prof_pending.size() >= kMaxPending) return;
     start_ = take_event(ctx_);
     stop_ = start_ ? take_event(ctx_) : nullptr;
     if (!stop_ && start_) {
