@@ -201,7 +201,8 @@ awg_status awg_plan_amplitude(awg_plan *plan, const awg_amp_ramp *events, int32_
  * methods cut the range into rows from n0 and, for requests with few output
  * tiles, split the tone sum into slices added in a fixed order afterwards: the
  * codes depend on (n0, count) within the same error bar, and equal calls give
- * equal samples.
+ * equal samples. They take a long range in pieces of 2^28 samples, which bounds
+ * their per-call workspace.
  * AWG_E_UNSUPPORTED if the plan has ramps; AWG_E_RANGE if n0 + count >= 2^63. */
 awg_status awg_synth_static(awg_plan *plan, uint64_t n0, uint64_t count, int16_t *d_out,
                             void *hip_stream);

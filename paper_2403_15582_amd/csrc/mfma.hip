@@ -643,9 +643,20 @@ awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count
                                : launch_direct_i16(p, n0, count, out_i16, s);
         return hipst(e);
     }
-    if (method == AWG_F_METHOD_MFMA_F16X3) return run<_Float16>(p, n0, count, out_i16, out_f32, s);
-    if (method == AWG_F_METHOD_MFMA_BF16X3) return run<__bf16>(p, n0, count, out_i16, out_f32, s);
-    return AWG_E_INVALID;
+    if (method != AWG_F_METHOD_MFMA_F16X3 && method != AWG_F_METHOD_MFMA_BF16X3) return AWG_E_INVALID;
+    // pieces of at most 2^28 samples bound the per-call operand (16384 rows)
+    constexpr uint64_t kPiece = 1ull << 28;
+    while (count > 0) {
+        const uint64_t now = count < kPiece ? count : kPiece;
+        const awg_status st = method == AWG_F_METHOD_MFMA_F16X3 ? run<_Float16>(p, n0, now, out_i16, out_f32, s)
+                                                                : run<__bf16>(p, n0, now, out_i16, out_f32, s);
+        if (st != AWG_OK) return st;
+        n0 += now;
+        count -= now;
+        if (out_i16) out_i16 += now;
+        if (out_f32) out_f32 += now;
+    }
+    return AWG_OK;
 }
 
 }  // namespace awg

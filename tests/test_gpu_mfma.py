@@ -162,3 +162,23 @@ def test_mfma_short_requests_split_k(method, n0, count):
     qo, yo = csynth.synth_at(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), ns)
     compare(q[ns - n0], y[ns - n0] if method == F16 else None, qo, yo,
             "mfma split-K n0=%d count=%d method=%d" % (n0, count, method))
+
+
+def test_mfma_request_longer_than_one_piece():
+    """2^28 + 4097 samples: the static matrix-core path runs in pieces of 2^28
+    samples; sampled codes on both sides of the piece boundary and at the ends."""
+    torch = need_gpu()
+    w = W.static_period(K=333)
+    lp = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, BF16)
+    n0, count = 1000, (1 << 28) + 4097
+    say("mfma two pieces n0=%d count=%d" % (n0, count))
+    q = lp.synth_static(n0, count)
+    torch.cuda.synchronize()
+    edge = n0 + (1 << 28)
+    ns = np.unique(np.concatenate([np.arange(n0, n0 + 200), np.arange(edge - 300, edge + 300),
+                                   np.arange(n0 + count - 200, n0 + count),
+                                   np.random.default_rng(55).integers(n0, n0 + count, 2000)]))
+    qs = q[torch.from_numpy(ns - n0).to(q.device)].cpu().numpy()
+    del q
+    qo, yo = csynth.synth_at(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), ns)
+    compare(qs, None, qo, yo, "mfma two pieces (sampled %d)" % len(ns))
