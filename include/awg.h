@@ -21,7 +21,10 @@
  *  - All functions return an awg_status; none aborts and no C++ exception
  *    crosses this boundary.
  *  - "d_" pointers are device pointers on the context's device, owned by the
- *    caller; all other pointers are host pointers, owned by the caller.
+ *    caller; all other pointers are host pointers, owned by the caller. The
+ *    synthesis calls check their output buffers first: AWG_E_INVALID for host
+ *    memory, memory of another device, or a range that runs past the end of
+ *    the allocation it starts in (when the runtime reports that allocation).
  *  - hip_stream is a hipStream_t (NULL = the legacy default stream). Synthesis
  *    calls only enqueue work; results are valid once the stream has synchronised.
  *  - A plan may be used from several threads for awg_synth_* calls (they only

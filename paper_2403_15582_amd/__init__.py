@@ -322,7 +322,8 @@ def multiplex(plans, n0, count, out=None, stream=None):
     import torch
     if out is None:
         out = torch.empty((int(count), len(plans)), dtype=torch.int16, device="cuda:%d" % plans[0].device)
-    assert out.dtype == torch.int16 and out.is_contiguous() and out.numel() >= count * len(plans)
+    if out.dtype != torch.int16 or not out.is_contiguous() or out.numel() < count * len(plans):
+        raise ValueError("out must be a contiguous int16 tensor of at least %d elements" % (count * len(plans)))
     awg_synth_multiplex([p.handle for p in plans], n0, count, out.data_ptr(),
                         (stream or torch.cuda.current_stream()).cuda_stream)
     return out
@@ -493,8 +494,13 @@ class Plan:
     def _out(self, count, dtype, out):
         import torch
         if out is None:
-            out = torch.empty(int(count), dtype=dtype, device="cuda:%d" % self.device)
-        assert out.dtype == dtype and out.is_contiguous() and out.numel() >= count
+            return torch.empty(int(count), dtype=dtype, device="cuda:%d" % self.device)
+        # the kernels write through out.data_ptr(): it must be device memory of
+        # this plan's device, of the right type, contiguous and large enough
+        if out.device.type != "cuda" or (out.device.index or 0) != self.device:
+            raise ValueError("out must be a tensor on cuda:%d, not %s" % (self.device, out.device))
+        if out.dtype != dtype or not out.is_contiguous() or out.numel() < count:
+            raise ValueError("out must be a contiguous %s tensor of at least %d elements" % (dtype, count))
         return out
 
     @staticmethod

@@ -141,6 +141,33 @@ awg_status check_range(uint64_t n0, uint64_t count)
     return AWG_OK;
 }
 
+// An output buffer must be device (or managed) memory of the plan's device, and
+// [d, d + count * elem) must lie inside one allocation when the runtime can say
+// which (a host pointer here would make the kernels fault). Runtime errors of
+// the queries are cleared so that they do not surface at a later launch.
+awg_status check_out(const awg_plan *p, const void *d, uint64_t count, size_t elem)
+{
+    if (!d) return AWG_E_INVALID;
+    if (count > SIZE_MAX / elem) return AWG_E_INVALID;
+    const size_t bytes = (size_t)count * elem;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, d) != hipSuccess) {
+        (void)hipGetLastError();
+        return AWG_E_INVALID;
+    }
+    const bool managed = a.type == hipMemoryTypeManaged || a.isManaged;
+    if (!managed && (a.type != hipMemoryTypeDevice || a.device != p->ctx->device)) return AWG_E_INVALID;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)d) == hipSuccess) {
+        const size_t off = (size_t)((const char *)d - (const char *)base);
+        if ((const char *)d < (const char *)base || off > size || bytes > size - off) return AWG_E_INVALID;
+    } else {
+        (void)hipGetLastError();
+    }
+    return AWG_OK;
+}
+
 awg_status device_ready(awg_plan *p)
 {
     if (!p) return AWG_E_INVALID;
@@ -599,7 +626,7 @@ awg_status awg_synth_chirp(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d_
     if (st != AWG_OK) return st;
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
-    if (!d_out) return AWG_E_INVALID;
+    if ((st = check_out(p, d_out, count, sizeof(int16_t))) != AWG_OK) return st;
     return synth_any(p, p->params.flags & AWG_F_METHOD_MASK, n0, count, d_out, nullptr, (hipStream_t)hip_stream);
 }
 
@@ -610,7 +637,7 @@ awg_status awg_synth_static(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d
     if (p->n_ramped > 0) return AWG_E_UNSUPPORTED;
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
-    if (!d_out) return AWG_E_INVALID;
+    if ((st = check_out(p, d_out, count, sizeof(int16_t))) != AWG_OK) return st;
     const uint32_t method = p->params.flags & AWG_F_METHOD_MASK;
     if (method == AWG_F_METHOD_DIRECT)
         return hip_status(launch_direct_i16(p, n0, count, d_out, (hipStream_t)hip_stream));
@@ -625,7 +652,7 @@ awg_status awg_synth_f32(awg_plan *p, uint32_t method, uint64_t n0, uint64_t cou
     if (method > AWG_F_METHOD_MFMA_BF16X3) return AWG_E_INVALID;
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
-    if (!d_y) return AWG_E_INVALID;
+    if ((st = check_out(p, d_y, count, sizeof(float))) != AWG_OK) return st;
     return synth_any(p, method, n0, count, nullptr, d_y, (hipStream_t)hip_stream);
 }
 
@@ -636,7 +663,7 @@ awg_status awg_stream_next(awg_plan *p, uint64_t count, int16_t *d_out, void *hi
     const uint64_t n0 = p->cursor;
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count > 0) {
-        if (!d_out) return AWG_E_INVALID;
+        if ((st = check_out(p, d_out, count, sizeof(int16_t))) != AWG_OK) return st;
         st = synth_any(p, p->params.flags & AWG_F_METHOD_MASK, n0, count, d_out, nullptr,
                        (hipStream_t)hip_stream);
         if (st != AWG_OK) return st;
@@ -691,7 +718,8 @@ awg_status awg_synth_multiplex(awg_plan *const *plans, int32_t n_channels, uint6
     if (st != AWG_OK) return st;
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
-    if (!d_out) return AWG_E_INVALID;
+    if (count > UINT64_MAX / (uint64_t)n_channels) return AWG_E_INVALID;
+    if ((st = check_out(plans[0], d_out, count * (uint64_t)n_channels, sizeof(int16_t))) != AWG_OK) return st;
     ProfScope prof(plans[0]->ctx, (hipStream_t)hip_stream, "mux_kernel");
     return hip_status(launch_mux(items, n_channels, count, (hipStream_t)hip_stream, prof));
 }
@@ -716,6 +744,8 @@ awg_status awg_peak(awg_plan *p, uint64_t n0, uint64_t count, float *d_scratch, 
     if (st != AWG_OK) return st;
     if (!d_scratch || !d_peak || count == 0) return AWG_E_INVALID;
     if ((st = check_range(n0, count)) != AWG_OK) return st;
+    if ((st = check_out(p, d_scratch, count, sizeof(float))) != AWG_OK) return st;
+    if ((st = check_out(p, d_peak, 1, sizeof(float))) != AWG_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = launch_direct_f32(p, n0, count, d_scratch, s);
     if (e == hipSuccess) e = launch_peak(d_scratch, count, d_peak, s);
@@ -730,7 +760,7 @@ awg_status awg_phase_dump(awg_plan *p, int32_t tone, uint64_t n0, uint64_t count
     if (tone < 0 || tone >= p->n_tones) return AWG_E_INVALID;
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
-    if (!d_words) return AWG_E_INVALID;
+    if ((st = check_out(p, d_words, count, sizeof(uint64_t))) != AWG_OK) return st;
     return hip_status(launch_phase_dump(p, p->inv[tone], n0, count, d_words, (hipStream_t)hip_stream));
 }
 

@@ -93,6 +93,28 @@ def test_window_edges_in_shared_blocks(n0, count):
     compare(q, y, qo, yo, "edge_blocks n0=%d count=%d" % (n0, count))
 
 
+def test_output_buffer_checks():
+    """Synthesis into pinned host memory is refused before any launch (were it
+    not, the kernel would only write mapped host memory), and a device buffer
+    passes at any offset inside its allocation."""
+    torch = need_gpu()
+    w = W.small_mixed()
+    lp = lib_plan(w)
+    host = torch.zeros(4096, dtype=torch.int16).pin_memory()
+    for call in (lambda: awg.awg_synth_chirp(lp.handle, 0, 4096, host.data_ptr()),
+                 lambda: awg.awg_stream_next(lp.handle, 4096, host.data_ptr())):
+        with pytest.raises(awg.AwgError) as e:
+            call()
+        assert e.value.status == awg.AWG_E_INVALID
+    torch.cuda.synchronize()
+    assert int(host.abs().max()) == 0
+    dev = torch.zeros(8192, dtype=torch.int16, device="cuda")
+    awg.awg_synth_chirp(lp.handle, 0, 4096, dev.data_ptr() + 2 * 4096)
+    q = to_np(lp.synth_chirp(0, 4096))
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(dev[4096:]), q) and int(dev[:4096].abs().max()) == 0
+
+
 def test_count_zero_and_errors():
     torch = need_gpu()
     w = W.small_mixed()
