@@ -29,6 +29,12 @@
  *    calls only enqueue work; results are valid once the stream has synchronised.
  *  - A plan may be used from several threads for awg_synth_* calls (they only
  *    read it); awg_stream_* and awg_plan_retune need one caller at a time.
+ *  - awg_synth_static and awg_synth_chirp with the direct method, and
+ *    awg_synth_static with a matrix-core method once the same call has run
+ *    outside capture (which sets up the plan's workspace), may be captured into
+ *    a HIP graph: they enqueue kernels and event records/waits only (no memset,
+ *    no allocation). A replay uses the plan's workspace as the captured call
+ *    did, so it must not overlap other matrix-core calls on the same plan.
  */
 #ifndef AWG_H
 #define AWG_H

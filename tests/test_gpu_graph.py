@@ -1,0 +1,41 @@
+"""Synthesis calls captured into a HIP graph (torch.cuda.graph) and replayed:
+every replay, with eager work and synchronisations between replays, must give
+the eager call's codes. The direct method launches kernels only; the static
+matrix-core path also orders its workspace with an event, which is recorded
+into the graph."""
+import numpy as np
+import pytest
+
+import paper_2403_15582_amd as awg
+from paper_2403_15582_amd import workloads as W
+
+from gpu_common import need_gpu, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("method", [awg.AWG_F_METHOD_DIRECT, awg.AWG_F_METHOD_MFMA_BF16X3])
+def test_captured_static_synthesis_replays(method):
+    torch = need_gpu()
+    w = W.static_100tone_chunk()
+    p = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, method)
+    n0, count = 777, w.count
+    say("graph capture of awg_synth_static, method=%d" % method)
+    ref = to_np(p.synth_static(n0, count))          # eager call (also sets up the workspace)
+    out = torch.zeros(count, dtype=torch.int16, device="cuda")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        p.synth_static(n0, count, out=out, stream=s)
+    torch.cuda.synchronize()
+    other = torch.empty(count, dtype=torch.int16, device="cuda")
+    for rep in range(4):
+        out.zero_()
+        p.synth_static(12345 + rep, count, out=other)   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(out), ref), rep
+    del g
+    p.close()
