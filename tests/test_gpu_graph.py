@@ -39,3 +39,28 @@ def test_captured_static_synthesis_replays(method):
         assert np.array_equal(to_np(out), ref), rep
     del g
     p.close()
+
+
+def test_captured_chirp_synthesis_replays():
+    torch = need_gpu()
+    w = W.small_mixed(n_total=20000)
+    p = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2)
+    n0, count = 3, 20000
+    say("graph capture of awg_synth_chirp (direct), ramped plan")
+    ref = to_np(p.synth_chirp(n0, count))
+    out = torch.zeros(count, dtype=torch.int16, device="cuda")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        p.synth_chirp(n0, count, out=out, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.zero_()
+        p.synth_chirp(500 + rep, count)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(out), ref), rep
+    del g
+    p.close()
