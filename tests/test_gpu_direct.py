@@ -330,3 +330,36 @@ def test_array_group_chirps_full_second_streamed(K):
         ns = np.unique(np.concatenate([ns, np.array(ramp_edges[:200], dtype=np.int64)]))
         qo, yo = csynth.synth_at(op, ns + base, packed=pk)
         compare(q[ns], None, qo, yo, "array K=%d chunk %d (sampled %d)" % (K, c, len(ns)))
+
+
+def test_direct_many_tones_mixed_windows():
+    """120,000 tones (a tenth of them chirped, windows of seeded starts and 40
+    lengths with every shape) through the direct kernel over a ragged range:
+    sampled codes and sums against the oracle, and the range split in two calls
+    gives the same codes."""
+    torch = need_gpu()
+    K, fs = 120_000, 280e6
+    rng = np.random.default_rng(56)
+    f0 = rng.uniform(0.05 * fs, 0.45 * fs, K)
+    t = W.static_tones(f0, rng.uniform(0.2, 1.0, K), rng.random(K))
+    ramped = rng.random(K) < 0.1
+    t["f_end_hz"] = np.where(ramped, np.clip(f0 + rng.uniform(-1e6, 1e6, K), 0.05 * fs, 0.45 * fs), f0)
+    t["ramp"] = np.where(ramped, rng.integers(1, 4, K), 0)
+    t["ramp_start"] = np.where(ramped, rng.integers(0, 6000, K), 0)
+    lens = rng.integers(1, 5000, 40)                      # 40 lengths: at most 80 smooth tables
+    t["ramp_len"] = np.where(ramped, lens[rng.integers(0, 40, K)], 0)
+    lp = awg.Plan(t, fs, 0.0, 20)
+    n0, count = 1234, 9000 + 77
+    say("direct %d tones n0=%d count=%d" % (K, n0, count))
+    q = to_np(lp.synth_chirp(n0, count))
+    y = to_np(lp.synth_f32(n0, count))
+    a = to_np(lp.synth_chirp(n0, 4096))
+    b = to_np(lp.synth_chirp(n0 + 4096, count - 4096))
+    torch.cuda.synchronize()
+    assert np.array_equal(np.concatenate([a, b]), q)
+    ns = np.unique(np.concatenate([np.arange(n0, n0 + 50), np.arange(n0 + count - 50, n0 + count),
+                                   rng.integers(n0, n0 + count, 150)]))
+    op = words.Plan(fs, 0.0, 20, t, build_tables=False)
+    csynth.sparse_tables(op, ns)
+    qo, yo = csynth.synth_at(op, ns)
+    compare(q[ns - n0], y[ns - n0], qo, yo, "direct %d tones (sampled %d)" % (K, len(ns)))
