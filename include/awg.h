@@ -143,7 +143,9 @@ void awg_ctx_destroy(awg_ctx *ctx);
  * and > 0, gain < 0 or not finite, non-finite tone fields, amplitude < 0,
  * unknown ramp, reserved != 0, period_log2 == 1 or > 63, f not in (0, fs/2),
  * all amplitudes 0 with gain 0; AWG_E_RANGE for a bin on 0 or L/2, ramp_len 0 or
- * >= 2^31, ramp_start + ramp_len >= 2^63; AWG_E_NOMEM / AWG_E_HIP on upload. */
+ * >= 2^31, ramp_start + ramp_len >= 2^63; AWG_E_UNSUPPORTED when the smooth
+ * ramps need more than 1024 distinct tables (shape, length) in one plan;
+ * AWG_E_NOMEM / AWG_E_HIP on upload. */
 awg_status awg_plan_tones(awg_ctx *ctx, const awg_plan_params *params, const awg_tone *tones,
                           int32_t n_tones, awg_plan **out, double *f_quantised_hz);
 void awg_plan_destroy(awg_plan *plan);
@@ -171,7 +173,8 @@ awg_status awg_ramp_table(int32_t shape, uint64_t n, uint64_t *out);
  * longer reproducible from this plan. At most one event per tone per call.
  * AWG_E_INVALID for a bad tone index or shape, AWG_E_RANGE for a window that
  * starts before the tone's previous window ends or is too long,
- * AWG_E_UNSUPPORTED for two events on one tone or more than 16384 events. */
+ * AWG_E_UNSUPPORTED for two events on one tone, more than 16384 events, or a
+ * plan that would need more than 1024 distinct smooth tables. */
 awg_status awg_plan_retune(awg_plan *plan, const awg_retune *events, int32_t n_events,
                            void *hip_stream);
 
