@@ -258,3 +258,23 @@ def test_phase_plan_matches_oracle():
         with pytest.raises(awg.AwgError) as e:
             awg.awg_phase_plan(*bad)
         assert e.value.status == awg.AWG_E_INVALID
+
+
+def test_smooth_table_limit():
+    """A plan holds at most 1024 distinct smooth ramp tables (shape, length):
+    1024 distinct lengths plan, 1025 are refused with AWG_E_UNSUPPORTED; linear
+    ramps need no table and are not counted."""
+    def tones(n_smooth, n_linear=0):
+        K = n_smooth + n_linear
+        t = np.zeros(K, dtype=awg.abi_types.TONE_DTYPE)
+        t["f_start_hz"] = 50e6
+        t["f_end_hz"] = 51e6
+        t["amplitude"] = 1.0
+        t["ramp"] = [awg.RAMP_COSINE] * n_smooth + [awg.RAMP_LINEAR] * n_linear
+        t["ramp_len"] = np.arange(1, K + 1)
+        return t
+    plan, _ = awg.awg_plan_tones(None, 280e6, 0.0, 0, 0, tones(1024, 50))
+    awg.awg_plan_destroy(plan)
+    with pytest.raises(awg.AwgError) as e:
+        awg.awg_plan_tones(None, 280e6, 0.0, 0, 0, tones(1025))
+    assert e.value.status == awg.AWG_E_UNSUPPORTED
