@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming, serving and large-array legs")
     ap.add_argument("--legs", default="stream,arrays,serve,short",
                     help="comma list of extra legs to run: stream, arrays, serve, short")
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of Poisson arrivals of the serving leg")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="job arrivals per second of the serving leg")
     ap.add_argument("--static-tones", type=int, default=1000, help="tones of the static 2^24-sample period")
     ap.add_argument("--stream-shape", default="mixed", choices=["mixed", "linear", "cosine", "minjerk"],
