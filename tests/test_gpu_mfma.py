@@ -182,3 +182,45 @@ def test_mfma_request_longer_than_one_piece():
     del q
     qo, yo = csynth.synth_at(words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones), ns)
     compare(qs, None, qo, yo, "mfma two pieces (sampled %d)" % len(ns))
+
+
+def test_calls_from_several_host_threads():
+    """Four host threads, each on its own stream, call the same plan (static
+    matrix-core path and its shared workspace; hybrid path on a ramped plan) at
+    once; every output equals the same call made alone."""
+    import threading
+    torch = need_gpu()
+    ws = W.static_100tone_chunk()
+    wr = W.array_group_chirps(K=600, seconds=0.01)
+    ps = awg.Plan(ws.tones, ws.fs_hz, ws.gain_lsb, ws.period_log2, BF16)
+    pr = awg.Plan(wr.tones, wr.fs_hz, wr.gain_lsb, wr.period_log2, BF16)
+    pr.retune([(k, sh, a, n, f) for k, a, n, sh, f in sorted(wr.retunes, key=lambda e: e[1])[:100]])
+    calls = [(ps, 0, 1 << 20), (ps, 777, 3 << 18), (pr, 0, 1 << 20), (pr, 4096, 1 << 19)]
+    say("4 host threads x 6 calls on shared plans")
+    ref = [to_np(p.synth_chirp(n0, c)) for p, n0, c in calls]
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(i):
+        try:
+            p, n0, c = calls[i]
+            st = torch.cuda.Stream()
+            out = torch.empty(c, dtype=torch.int16, device="cuda")
+            for _ in range(6):
+                with torch.cuda.stream(st):
+                    p.synth_chirp(n0, c, out=out, stream=st)
+                st.synchronize()
+                if not np.array_equal(to_np(out), ref[i]):
+                    errors.append(i)
+        except Exception as e:           # reported below
+            errors.append(repr(e))
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(len(calls))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in th)
+    assert not errors, errors
+    ps.close()
+    pr.close()
