@@ -357,6 +357,7 @@ typedef struct {
     double audio_seconds;            /* synthesised output duration, sum over jobs */
     double device_busy_ms;           /* device time of all steps */
     double wall_ms;                  /* first submit to last chunk ready */
+    /* percentiles cover the most recent 1,048,576 chunks */
     double chunk_latency_p50_ms, chunk_latency_p99_ms;            /* chunk ready - job submit */
     double first_chunk_latency_p50_ms, first_chunk_latency_p99_ms;
     uint64_t deadline_misses;        /* chunks ready after submit + delay + n0 / fs */

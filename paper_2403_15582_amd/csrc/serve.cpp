@@ -39,6 +39,7 @@ constexpr uint32_t kBatchGrid = 2048;   // workgroups of the batched kernel (8 p
 constexpr size_t kItemsOffset = 256;    // work-list items after the 2-word header
 constexpr size_t kAlign = 256;
 constexpr size_t kStageInit = 512 * 1024;   // admission staging buffer set up at creation (~5000 tones)
+constexpr size_t kStatWindow = 1u << 20;    // chunks whose latencies the percentiles cover
 
 double now_ms()
 {
@@ -131,7 +132,17 @@ struct awg_server {
     double tone_samples = 0, busy_ms = 0, t_first_submit = -1, t_last_ready = 0, audio_s = 0;
     // device rate (tone-samples per ms) measured on completed steps, for the step work budget
     double rate_ts_per_ms = 2e9;
-    std::vector<double> lat_chunk, lat_first, lateness;
+    // latency samples of the most recent kStatWindow chunks (rings, oldest overwritten)
+    struct Ring {
+        std::vector<double> v;
+        size_t next = 0;
+        void add(double x)
+        {
+            if (v.size() < kStatWindow) v.push_back(x);
+            else { v[next] = x; next = (next + 1) % kStatWindow; }
+        }
+    };
+    Ring lat_chunk, lat_first, lateness;
     // admission staging: pinned coherent buffers holding a job's tables in their
     // arena layout, uploaded by a kernel; a buffer is reused once its upload is done
     struct Stage { void *host = nullptr, *mapped = nullptr; size_t cap = 0; hipEvent_t done = nullptr; bool used = false; };
@@ -275,11 +286,11 @@ void harvest(awg_server *s)
             s->n_chunks++;
             s->tone_samples += (double)j.n_tones * (double)it.count;
             s->audio_s += (double)it.count / j.fs;
-            s->lat_chunk.push_back(t - j.t_submit);
-            if (it.chunk == 0) s->lat_first.push_back(t - j.t_submit);
+            s->lat_chunk.add(t - j.t_submit);
+            if (it.chunk == 0) s->lat_first.add(t - j.t_submit);
             const double deadline = j.t_submit + s->prm.playout_delay_ms + 1e3 * (double)it.n0 / j.fs;
             if (t > deadline) s->deadline_misses++;
-            s->lateness.push_back(t - deadline);
+            s->lateness.add(t - deadline);
             s->t_last_ready = t;
             if (ev.last) {
                 pool_free(s, j.off, j.bytes);
@@ -587,13 +598,13 @@ awg_status awg_server_stats_get(awg_server *s, awg_server_stats *o)
     o->audio_seconds = s->audio_s;
     o->device_busy_ms = s->busy_ms;
     o->wall_ms = s->t_first_submit >= 0 ? s->t_last_ready - s->t_first_submit : 0.0;
-    o->chunk_latency_p50_ms = percentile(s->lat_chunk, 50);
-    o->chunk_latency_p99_ms = percentile(s->lat_chunk, 99);
-    o->first_chunk_latency_p50_ms = percentile(s->lat_first, 50);
-    o->first_chunk_latency_p99_ms = percentile(s->lat_first, 99);
+    o->chunk_latency_p50_ms = percentile(s->lat_chunk.v, 50);
+    o->chunk_latency_p99_ms = percentile(s->lat_chunk.v, 99);
+    o->first_chunk_latency_p50_ms = percentile(s->lat_first.v, 50);
+    o->first_chunk_latency_p99_ms = percentile(s->lat_first.v, 99);
     o->deadline_misses = s->deadline_misses;
-    o->lateness_p50_ms = percentile(s->lateness, 50);
-    o->lateness_p99_ms = percentile(s->lateness, 99);
+    o->lateness_p50_ms = percentile(s->lateness.v, 50);
+    o->lateness_p99_ms = percentile(s->lateness.v, 99);
     o->pool_free_bytes = 0;
     for (auto &kv : s->free_blocks) o->pool_free_bytes += kv.second;
     return s->error;
