@@ -120,7 +120,11 @@ typedef struct {
 
 /* ---------------------------------------------------------------- context */
 
-/* Binds HIP device `device`. Fails with AWG_E_HIP when there is no such device. */
+/* Binds HIP device `device`. Fails with AWG_E_HIP when there is no such device.
+ * The context owns the smooth ramp tables H_N of its plans and server jobs: one
+ * device table per distinct (shape, N), (N + 1) x 8 bytes, shared by every plan
+ * that uses it and kept until awg_ctx_destroy (a long-lived context that sees
+ * many distinct smooth ramp lengths holds all of their tables). */
 awg_status awg_ctx_create(int device, awg_ctx **out);
 void awg_ctx_destroy(awg_ctx *ctx);
 
