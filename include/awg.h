@@ -242,6 +242,17 @@ awg_status awg_synth_static(awg_plan *plan, uint64_t n0, uint64_t count, int16_t
 awg_status awg_synth_chirp(awg_plan *plan, uint64_t n0, uint64_t count, int16_t *d_out,
                            void *hip_stream);
 
+/* Set-up ahead of a stream (for real-time callers): allocates now what the
+ * calls below would otherwise allocate on first use, so that the first chunk
+ * does not pay for it: the retune and amplitude staging slots (16 pinned
+ * buffers), and for an MFMA method and requests of up to max_count samples the
+ * plan's product workspace and, on a plan with ramps, the hybrid path's
+ * workspace and staging slots. Later calls reuse them (a plan retuned from
+ * static to ramped after this call sets up the hybrid path on its first call).
+ * AWG_E_INVALID for a host-only plan or an unknown method; AWG_E_NOMEM /
+ * AWG_E_HIP when an allocation fails. */
+awg_status awg_plan_reserve(awg_plan *plan, uint32_t method, uint64_t max_count);
+
 /* Streaming pathway: the next count samples after the plan's cursor into d_out,
  * then advance the cursor. *n0_out (nullable) receives the first sample index.
  * Results are bit-identical to awg_synth_chirp over the same range: the phase is

@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libawg.so")
 EXPORTED = [
     "awg_ctx_create", "awg_ctx_destroy", "awg_plan_tones", "awg_plan_destroy",
     "awg_plan_info_get", "awg_plan_words", "awg_ramp_table", "awg_plan_retune", "awg_plan_amplitude",
+    "awg_plan_reserve",
     "awg_synth_static", "awg_synth_chirp", "awg_stream_next", "awg_stream_seek",
     "awg_stream_tell", "awg_synth_f32", "awg_synth_multiplex", "awg_stream_next_multiplex",
     "awg_phase_dump", "awg_phase_plan", "awg_peak", "awg_strerror", "awg_version",
@@ -138,6 +139,7 @@ def lib():
         "awg_ramp_table": ([_I32, _U64, _VP], _I32),
         "awg_plan_retune": ([_VP, ctypes.POINTER(awg_retune), _I32, _VP], _I32),
         "awg_plan_amplitude": ([_VP, ctypes.POINTER(awg_amp_ramp), _I32, _VP], _I32),
+        "awg_plan_reserve": ([_VP, ctypes.c_uint32, _U64], _I32),
         "awg_synth_static": ([_VP, _U64, _U64, _VP, _VP], _I32),
         "awg_synth_chirp": ([_VP, _U64, _U64, _VP, _VP], _I32),
         "awg_stream_next": ([_VP, _U64, _VP, _VP, ctypes.POINTER(_U64)], _I32),
@@ -268,6 +270,10 @@ def awg_plan_amplitude(plan, events, stream=0):
 
 def awg_synth_static(plan, n0, count, d_out, stream=0):
     _check(lib().awg_synth_static(plan, int(n0), int(count), d_out, stream or None), "awg_synth_static")
+
+
+def awg_plan_reserve(plan, method, max_count):
+    _check(lib().awg_plan_reserve(plan, int(method), int(max_count)), "awg_plan_reserve")
 
 
 def awg_synth_chirp(plan, n0, count, d_out, stream=0):
@@ -467,6 +473,7 @@ class Plan:
         self.device = device
         ctx = None if host_only else context(device)
         self.tones = np.ascontiguousarray(tones, dtype=TONE_DTYPE)
+        self.method = method
         self.handle, self.f_quantised_hz = awg_plan_tones(ctx, fs_hz, gain_lsb, period_log2, method,
                                                           self.tones)
         self.n_tones = len(self.tones)
@@ -544,6 +551,12 @@ class Plan:
     def amplitude(self, events, stream=None):
         """Amplitude ramps: (tone, ramp, ramp_start, ramp_len, amplitude_end) each."""
         awg_plan_amplitude(self.handle, events, self._stream(stream))
+
+    def reserve(self, max_count, method=None):
+        """Set up workspaces and staging for calls of up to max_count samples
+        (method: the plan's own by default)."""
+        m = (self.method if method is None else method)
+        awg_plan_reserve(self.handle, m, max_count)
 
     def seek(self, n0):
         awg_stream_seek(self.handle, n0)

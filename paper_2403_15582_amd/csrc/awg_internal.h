@@ -251,6 +251,8 @@ awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count
 
 // Hybrid path (hybrid.cpp): a ramped plan's samples with the line tones on the
 // matrix cores and the ramping ones on the direct kernel.
+awg_status mfma_static_reserve(awg_plan *p, uint64_t max_count);
+awg_status hybrid_reserve(awg_plan *p, uint64_t max_count);
 awg_status hybrid_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,
                         float *out_f32, hipStream_t s);
 void hybrid_release(awg_plan *p);

@@ -565,6 +565,33 @@ awg_status awg_plan_amplitude(awg_plan *p, const awg_amp_ramp *ev, int32_t n_ev,
 // their records are written to a pinned slot that the scatter kernel reads in
 // place, and the rebuilt block table is uploaded from the same slot by a kernel
 // (no DMA engine in the chain).
+// The retune staging slots, all at once on first use (or awg_plan_reserve);
+// when an allocation fails none are kept, so a later call starts over.
+static awg_status ensure_retune_slots(awg_plan *p)
+{
+    if (!p->slots.empty()) return AWG_OK;
+    std::vector<awg_plan::Slot> v;
+    try { v.resize(kSlots); } catch (...) { return AWG_E_NOMEM; }
+    for (auto &sl : v) {
+        sl.host = nullptr; sl.mapped = nullptr; sl.done = nullptr; sl.used = false;
+    }
+    hipError_t e = hipSuccess;
+    for (auto &sl : v) {
+        e = alloc_upload_host(slot_block_offset(p) + sizeof(Block) * ((size_t)p->n_tones + 1), &sl.host, &sl.mapped);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e != hipSuccess) break;
+    }
+    if (e != hipSuccess) {
+        for (auto &sl : v) {
+            if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+        }
+        return hip_status(e);
+    }
+    p->slots.swap(v);
+    return AWG_OK;
+}
+
 static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, hipStream_t s)
 {
     build_blocks(p->dev_mirror, -1, &p->blocks);
@@ -572,17 +599,8 @@ static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, 
     // stage the new records and scatter them on the stream
     hipError_t e = hipSetDevice(p->ctx->device);
     if (e != hipSuccess) return hip_status(e);
-    if (p->slots.empty()) {
-        p->slots.resize(kSlots);
-        for (auto &s : p->slots) {
-            s.host = nullptr; s.mapped = nullptr; s.done = nullptr; s.used = false;
-        }
-        for (auto &s : p->slots) {
-            e = alloc_upload_host(slot_block_offset(p) + sizeof(Block) * ((size_t)p->n_tones + 1), &s.host, &s.mapped);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-            if (e != hipSuccess) return hip_status(e);
-        }
-    }
+    awg_status st = ensure_retune_slots(p);
+    if (st != AWG_OK) return st;
     const size_t si = p->next_slot;
     p->next_slot = (p->next_slot + 1) % kSlots;
     auto &slot = p->slots[si];
@@ -618,6 +636,19 @@ static awg_status synth_any(awg_plan *p, uint32_t method, uint64_t n0, uint64_t 
         if (count >= kHybridMin) return hybrid_synth(p, method, n0, count, out_i16, out_f32, s);
     }
     return hip_status(out_f32 ? launch_direct_f32(p, n0, count, out_f32, s) : launch_direct_i16(p, n0, count, out_i16, s));
+}
+
+awg_status awg_plan_reserve(awg_plan *p, uint32_t method, uint64_t max_count)
+{
+    awg_status st = device_ready(p);
+    if (st != AWG_OK) return st;
+    if (method > AWG_F_METHOD_MFMA_BF16X3) return AWG_E_INVALID;
+    if ((st = ensure_retune_slots(p)) != AWG_OK) return st;
+    if (method == AWG_F_METHOD_DIRECT || max_count < kHybridMin) return AWG_OK;
+    // a static plan's matrix-core calls use the product workspace; a ramped
+    // plan's take the hybrid path (and a plan retuned later may need both)
+    if ((st = mfma_static_reserve(p, max_count)) != AWG_OK) return st;
+    return p->n_ramped > 0 ? hybrid_reserve(p, max_count) : AWG_OK;
 }
 
 awg_status awg_synth_chirp(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d_out, void *hip_stream)

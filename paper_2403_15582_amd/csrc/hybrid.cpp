@@ -245,6 +245,58 @@ static bool dirty_blocks(const awg_plan *p, HybridState *h, uint32_t method, int
     return true;
 }
 
+// Staging blob capacity for the largest blob the plan can produce (every tone
+// with two lines, every tone direct, a full piece of rows, every k-block dirty).
+static size_t staging_cap(const awg_plan *p)
+{
+    const int32_t max_entries = (p->n_tones + 7) / 8 * 8 + p->n_tones;
+    const size_t kb_max = ((size_t)max_entries + 7) / 8;
+    return align_up(sizeof(uint32_t) * (size_t)max_entries, 256) + align_up(sizeof(ToneDev) * (size_t)p->n_tones, 256) +
+           align_up(sizeof(Block) * ((size_t)p->n_tones + 1), 256) + align_up(sizeof(uint32_t) * (kPiece / kRow), 256) +
+           sizeof(int32_t) * kb_max;
+}
+
+// Every staging slot with `bytes` of pinned host and device memory (slots that
+// already have them are left alone).
+static awg_status setup_slots(HybridState *h, size_t bytes)
+{
+    hipError_t e = hipSuccess;
+    for (auto &sl : h->slots) {
+        if (!sl.done) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess && !sl.host) {
+            e = alloc_upload_host(bytes, &sl.host, &sl.mapped);
+            if (e == hipSuccess) sl.host_cap = bytes;
+        }
+        if (e == hipSuccess && !sl.dev) {
+            e = hipMalloc(&sl.dev, bytes);
+            if (e == hipSuccess) sl.dev_cap = bytes;
+        }
+        if (e != hipSuccess) return hst(e);
+    }
+    return AWG_OK;
+}
+
+// The operand and plane workspace of at least `bytes` (a quarter more when it
+// grows, since the rows of a call vary); growing it waits for its last user
+// and drops the cached B operand.
+static awg_status ensure_work(HybridState *h, size_t bytes)
+{
+    if (h->work_cap >= bytes) return AWG_OK;
+    if (h->work_used) {
+        const hipError_t e = hipEventSynchronize(h->work_done);
+        if (e != hipSuccess) return hst(e);
+    }
+    if (h->d_work) (void)hipFree(h->d_work);
+    h->d_work = nullptr;
+    h->work_cap = 0;
+    const size_t want = bytes + bytes / 4;
+    const hipError_t e = hipMalloc(&h->d_work, want);
+    if (e != hipSuccess) return hst(e);
+    h->work_cap = want;
+    h->b_valid = false;
+    return AWG_OK;
+}
+
 static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n0, uint64_t count,
                         int16_t *out_i16, float *out_f32, hipStream_t s)
 {
@@ -266,26 +318,13 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
     const size_t kb_max = ((size_t)max_entries + 7) / 8;
     const size_t total = off_d + sizeof(int32_t) * kb_max;
     // slots are sized for the largest blob this plan can produce, so they are allocated once
-    const size_t cap = align_up(sizeof(uint32_t) * (size_t)max_entries, 256) +
-                       align_up(sizeof(ToneDev) * (size_t)p->n_tones, 256) +
-                       align_up(sizeof(Block) * ((size_t)p->n_tones + 1), 256) +
-                       align_up(sizeof(uint32_t) * (kPiece / kRow), 256) + sizeof(int32_t) * kb_max;
+    const size_t cap = staging_cap(p);
     hipError_t e = hipSuccess;
     // the first call sets up every slot, so that the calls after it (the next
     // chunks of a stream) do not each pay for a pinned allocation
     if (!h->slots[0].host) {
-        for (auto &sl : h->slots) {
-            if (!sl.done) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-            if (e == hipSuccess && !sl.host) {
-                e = alloc_upload_host(std::max(cap, total), &sl.host, &sl.mapped);
-                if (e == hipSuccess) sl.host_cap = std::max(cap, total);
-            }
-            if (e == hipSuccess && !sl.dev) {
-                e = hipMalloc(&sl.dev, std::max(cap, total));
-                if (e == hipSuccess) sl.dev_cap = std::max(cap, total);
-            }
-            if (e != hipSuccess) return hst(e);
-        }
+        const awg_status st = setup_slots(h, std::max(cap, total));
+        if (st != AWG_OK) return st;
     }
     HybridState::Slot &slot = h->slots[h->next];
     h->next = (h->next + 1) % kHybSlots;
@@ -321,19 +360,9 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
         e = hipEventCreateWithFlags(&h->work_done, hipEventDisableTiming);
         if (e != hipSuccess) return hst(e);
     }
-    if (gemm && h->work_cap < g.work_bytes()) {
-        if (h->work_used) {
-            e = hipEventSynchronize(h->work_done);
-            if (e != hipSuccess) return hst(e);
-        }
-        if (h->d_work) (void)hipFree(h->d_work);
-        h->d_work = nullptr;
-        h->work_cap = 0;
-        const size_t want = g.work_bytes() + g.work_bytes() / 4;      // headroom: rows vary by call
-        e = hipMalloc(&h->d_work, want);
-        if (e != hipSuccess) return hst(e);
-        h->work_cap = want;
-        h->b_valid = false;
+    if (gemm) {
+        const awg_status st = ensure_work(h, g.work_bytes());
+        if (st != AWG_OK) return st;
     }
     const bool partial = gemm && dirty_blocks(p, h, method, g.kb_n);
     if (partial && !h->dirty.empty())
@@ -355,6 +384,26 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     if (e == hipSuccess) slot.used = true;
     return hst(e);
+}
+
+awg_status hybrid_reserve(awg_plan *p, uint64_t max_count)
+{
+    if (p->n_tones >= (int32_t)(1u << kLineShift)) return AWG_E_UNSUPPORTED;
+    if (!p->hyb) {
+        try { p->hyb = new HybridState(); } catch (...) { return AWG_E_NOMEM; }
+    }
+    HybridState *h = p->hyb;
+    std::lock_guard<std::mutex> lock(h->mu);
+    if (!h->work_done) {
+        const hipError_t e = hipEventCreateWithFlags(&h->work_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hst(e);
+    }
+    awg_status st = setup_slots(h, staging_cap(p));
+    if (st != AWG_OK) return st;
+    // the workspace of a full piece with every tone on two lines
+    const int32_t max_entries = (p->n_tones + 7) / 8 * 8 + p->n_tones;
+    const LinesGeom g = lines_geometry(max_entries, max_entries, std::min<uint64_t>(max_count, kPiece));
+    return g.gz > 0 ? ensure_work(h, g.work_bytes()) : AWG_OK;
 }
 
 awg_status hybrid_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,

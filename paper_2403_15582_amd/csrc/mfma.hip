@@ -477,53 +477,80 @@ __global__ __launch_bounds__(256) void plane_sum_kernel(const float *__restrict_
     }
 }
 
-template <typename T>
-static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32, hipStream_t s)
+// Geometry of a static product over count samples: columns per row (long
+// requests take long rows, so that the per-call A operand (rows x 2K) stays
+// small while B (2K x columns, cached in the plan) grows; 2^24 samples make 1024
+// rows of 16384, 4 x 64 tiles of 256 x 256), operand sizes, split-K slices
+// (short requests have few output tiles: the inner dimension is split over up
+// to kTargetGroups workgroups, FP32 partial planes summed in slice order after)
+// and the workspace the product needs.
+struct StaticGeom {
+    uint64_t mcols, rows, plane;
+    int32_t rb_pad, cb_n, kb_n, gz, kb_split;
+    size_t a_bytes, b_bytes, need;
+};
+
+static StaticGeom static_geometry(const awg_plan *p, uint64_t count)
 {
-    // columns per row: long requests take long rows, so that the per-call A
-    // operand (rows x 2K) stays small while B (2K x columns, cached in the plan)
-    // grows; 2^24 samples make 1024 rows of 16384 (4 x 64 tiles of 256 x 256)
-    const uint64_t mcols = count >= (1ull << 24) ? 16384 : count >= (1ull << 20) ? 4096 : 1024;
-    const uint64_t rows = (count + mcols - 1) / mcols;
-    const int32_t rb_pad = (int32_t)(((rows + 31) / 32 + kTileRB - 1) / kTileRB * kTileRB);
-    const int32_t cb_n = (int32_t)(mcols / 32);
+    StaticGeom g;
+    g.mcols = count >= (1ull << 24) ? 16384 : count >= (1ull << 20) ? 4096 : 1024;
+    g.rows = (count + g.mcols - 1) / g.mcols;
+    g.rb_pad = (int32_t)(((g.rows + 31) / 32 + kTileRB - 1) / kTileRB * kTileRB);
+    g.cb_n = (int32_t)(g.mcols / 32);
     const int32_t n_groups = (p->n_tones + 3) / 4;
-    const int32_t kb_n = (n_groups + 1) / 2;          // k-blocks of 8 tones (zero-padded)
-    const size_t frag = kFragBytes;
-    const size_t a_bytes = (size_t)kb_n * rb_pad * frag, b_bytes = (size_t)kb_n * cb_n * frag;
-    // short requests have few output tiles: split the inner dimension over up to
-    // kTargetGroups workgroups (FP32 partial planes, summed in slice order after)
-    const int32_t tiles = (rb_pad / kTileRB) * (cb_n / kTileCB);
-    int32_t gz = 1, kb_split = kb_n;
-    if (tiles < kTargetGroups && kb_n > 1) {
-        gz = std::min(kb_n, (kTargetGroups + tiles - 1) / tiles);
-        kb_split = (kb_n + gz - 1) / gz;
-        gz = (kb_n + kb_split - 1) / kb_split;
+    g.kb_n = (n_groups + 1) / 2;                       // k-blocks of 8 tones (zero-padded)
+    g.a_bytes = (size_t)g.kb_n * g.rb_pad * kFragBytes;
+    g.b_bytes = (size_t)g.kb_n * g.cb_n * kFragBytes;
+    const int32_t tiles = (g.rb_pad / kTileRB) * (g.cb_n / kTileCB);
+    g.gz = 1;
+    g.kb_split = g.kb_n;
+    if (tiles < kTargetGroups && g.kb_n > 1) {
+        g.gz = std::min(g.kb_n, (kTargetGroups + tiles - 1) / tiles);
+        g.kb_split = (g.kb_n + g.gz - 1) / g.gz;
+        g.gz = (g.kb_n + g.kb_split - 1) / g.kb_split;
     }
-    const uint64_t plane = rows * mcols;
-    const size_t plane_bytes = gz > 1 ? (size_t)gz * plane * sizeof(float) : 0;
-    const size_t need = 2 * (a_bytes + b_bytes) + plane_bytes;
-    if (rows > (1ull << 26)) return AWG_E_UNSUPPORTED;
-    // calls on one plan may come from several host threads and streams: one at a
-    // time here, and each stream waits for the previous user of the workspace
-    std::lock_guard<std::mutex> lock(p->work_mu);
+    g.plane = g.rows * g.mcols;
+    const size_t plane_bytes = g.gz > 1 ? (size_t)g.gz * g.plane * sizeof(float) : 0;
+    g.need = 2 * (g.a_bytes + g.b_bytes) + plane_bytes;
+    return g;
+}
+
+// The plan's product workspace of at least `need` bytes (caller holds work_mu).
+// Growing it waits for the last user of the old one and drops the cached B.
+static awg_status ensure_static_work(awg_plan *p, size_t need)
+{
     if (!p->work_done) {
         hipError_t e = hipEventCreateWithFlags(&p->work_done, hipEventDisableTiming);
         if (e != hipSuccess) return hipst(e);
     }
-    if (p->d_work_bytes < need) {
-        if (p->work_used) {
-            hipError_t e = hipEventSynchronize(p->work_done);
-            if (e != hipSuccess) return hipst(e);
-        }
-        if (p->d_work) (void)hipFree(p->d_work);
-        p->d_work = nullptr;
-        p->d_work_bytes = 0;
-        p->mfma_b_key = 0;
-        hipError_t e = hipMalloc(&p->d_work, need);
+    if (p->d_work_bytes >= need) return AWG_OK;
+    if (p->work_used) {
+        hipError_t e = hipEventSynchronize(p->work_done);
         if (e != hipSuccess) return hipst(e);
-        p->d_work_bytes = need;
     }
+    if (p->d_work) (void)hipFree(p->d_work);
+    p->d_work = nullptr;
+    p->d_work_bytes = 0;
+    p->mfma_b_key = 0;
+    hipError_t e = hipMalloc(&p->d_work, need);
+    if (e != hipSuccess) return hipst(e);
+    p->d_work_bytes = need;
+    return AWG_OK;
+}
+
+template <typename T>
+static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32, hipStream_t s)
+{
+    const StaticGeom g = static_geometry(p, count);
+    const uint64_t mcols = g.mcols, rows = g.rows, plane = g.plane;
+    const int32_t rb_pad = g.rb_pad, cb_n = g.cb_n, kb_n = g.kb_n, gz = g.gz, kb_split = g.kb_split;
+    const size_t a_bytes = g.a_bytes, b_bytes = g.b_bytes;
+    if (rows > (1ull << 26)) return AWG_E_UNSUPPORTED;
+    // calls on one plan may come from several host threads and streams: one at a
+    // time here, and each stream waits for the previous user of the workspace
+    std::lock_guard<std::mutex> lock(p->work_mu);
+    const awg_status ws = ensure_static_work(p, g.need);
+    if (ws != AWG_OK) return ws;
     char *w = (char *)p->d_work;
     // B (depends on the tones and the column count only) is kept between calls
     T *b_hi = (T *)w, *b_lo = (T *)(w + b_bytes);
@@ -632,6 +659,20 @@ hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, 
     if (method == AWG_F_METHOD_MFMA_BF16X3)
         return lines_run<__bf16>(p, g, d_entries, n_entries, d_blocks, n_blocks, n0, count, (char *)d_work, s);
     return hipErrorInvalidValue;
+}
+
+awg_status mfma_static_reserve(awg_plan *p, uint64_t max_count)
+{
+    // the workspace of the largest product among requests of up to max_count
+    // samples (pieces of at most 2^28; short requests add split-K planes)
+    size_t need = 0;
+    const uint64_t top = std::min<uint64_t>(max_count, 1ull << 28);
+    const uint64_t counts[] = {top, (1ull << 24) - 1, 1ull << 22, (1ull << 20) - 1, 1ull << 18, 1ull << 16};
+    for (const uint64_t c : counts)
+        if (c >= (1ull << 16) && c <= top) need = std::max(need, static_geometry(p, c).need);
+    if (need == 0) return AWG_OK;
+    std::lock_guard<std::mutex> lock(p->work_mu);
+    return ensure_static_work(p, need);
 }
 
 awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,

@@ -278,3 +278,14 @@ def test_smooth_table_limit():
     with pytest.raises(awg.AwgError) as e:
         awg.awg_plan_tones(None, 280e6, 0.0, 0, 0, tones(1025))
     assert e.value.status == awg.AWG_E_UNSUPPORTED
+
+
+def test_reserve_on_host_only_plan_is_invalid():
+    w = W.static_100tone_chunk()
+    plan, _ = _host_plan(w)
+    try:
+        with pytest.raises(awg.AwgError) as e:
+            awg.awg_plan_reserve(plan, awg.AWG_F_METHOD_DIRECT, 1 << 20)
+        assert e.value.status == awg.AWG_E_INVALID
+    finally:
+        awg.awg_plan_destroy(plan)
