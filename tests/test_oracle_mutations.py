@@ -9,6 +9,7 @@ import math
 import subprocess
 from fractions import Fraction
 
+import numpy as np
 import pytest
 
 import test_oracle_pins as pins
@@ -27,6 +28,7 @@ SUM_PINS = [pins.test_quarter_rate_tone_is_exact, pins.test_eighth_rate_tone,
             pins.test_periodicity_with_bin_frequencies, pins.test_mean_power_and_default_gain,
             pins.test_held_tone_is_periodic_after_ramp, pins.test_brute_force_long_double,
             pins.test_c_sum_equals_python_bigint]
+QUANT_PINS = [pins.test_quantiser_ties_go_to_even, pins.test_quantiser_saturates_to_int16]
 
 
 AMP_CASES = [(words.RAMP_LINEAR, 1024, 512, Fraction(1, 2)), (words.RAMP_COSINE, 768, 256, Fraction(1, 4)),
@@ -64,6 +66,8 @@ def test_unmutated_oracle_passes_every_pin_used_here(oracle_built):
     assert not some_pin_fails(CHIRP_PINS)
     assert not some_pin_fails(SUM_PINS)
     assert not some_pin_fails(AMP_PINS)
+    assert not some_pin_fails(QUANT_PINS)
+    assert not some_pin_fails(PHASE_PINS)
 
 
 def _floor_round(x):
@@ -76,6 +80,28 @@ def _tuning_word_truncating(f_hz, fs_hz, period_log2=0):
     if period_log2 > 0:
         return _floor_round(f * (1 << period_log2) / fs) << (64 - period_log2)
     return _floor_round(f * words.TWO64 / fs)
+
+
+def _quantise_half_away(y):
+    y = np.asarray(y, dtype=np.float64)
+    r = np.sign(y) * np.floor(np.abs(y) + 0.5)                      # ties away from zero
+    return np.clip(r, words.INT16_MIN, words.INT16_MAX).astype(np.int16)
+
+
+def _quantise_no_clamp(y):
+    return np.rint(np.asarray(y, dtype=np.float64)).astype(np.int64).astype(np.int16)   # wraps
+
+
+QUANT_MUTANTS = {
+    "quantiser rounds ties away from zero": _quantise_half_away,
+    "quantiser does not saturate": _quantise_no_clamp,
+}
+
+
+@pytest.mark.parametrize("name", sorted(QUANT_MUTANTS))
+def test_python_quantiser_mutants_are_caught(monkeypatch, oracle_built, name):
+    monkeypatch.setattr(words, "quantise", QUANT_MUTANTS[name])
+    assert some_pin_fails(QUANT_PINS), name
 
 
 WORD_MUTANTS = {
@@ -199,11 +225,29 @@ def _newman_off_by_one(method, f_hz, amps):
 from oracle import phases as PH   # noqa: E402
 ORIG_PHASE_PLAN = PH.phase_plan
 PHASE_PINS = [pins.test_schroeder_equal_amplitudes_reduce_to_textbook_form, pins.test_newman_phases_by_hand,
-              pins.test_schroeder_phases_lower_the_crest_factor]
+              pins.test_schroeder_phases_lower_the_crest_factor, pins.test_schroeder_unequal_amplitudes_by_hand,
+              pins.test_schroeder_sweep_spends_time_by_power]
+
+
+def _schroeder_amplitude_weighted(method, f_hz, amps):
+    if method != PH.SCHROEDER:
+        return ORIG_PHASE_PLAN(method, f_hz, amps)
+    K = len(f_hz)
+    _, order = PH.rank_by_frequency(f_hz)
+    p = [Fraction(float(amps[i])) for i in order]                   # A_l instead of A_l^2
+    total = sum(p)
+    p = [x / total for x in p]
+    out = [0.0] * K
+    for k in range(1, K + 1):
+        t = -sum((k - l) * p[l - 1] for l in range(1, k))
+        out[order[k - 1]] = float(t - math.floor(t))
+    return out
 
 
 @pytest.mark.parametrize("name,fn", [("Schroeder phases with the wrong sign", _schroeder_sign_flipped),
-                                     ("Newman phases with k^2 for (k-1)^2", _newman_off_by_one)])
+                                     ("Newman phases with k^2 for (k-1)^2", _newman_off_by_one),
+                                     ("Schroeder weights amplitudes instead of powers",
+                                      _schroeder_amplitude_weighted)])
 def test_phase_plan_mutants_are_caught(monkeypatch, oracle_built, name, fn):
     monkeypatch.setattr(PH, "phase_plan", fn)
     assert some_pin_fails(PHASE_PINS), name
@@ -221,6 +265,8 @@ C_MUTANTS = {
     "linear term without 1/2": ("return (uint64_t)(prod >> 1);", "return (uint64_t)(prod);"),
     "post-window line uses the start frequency": ("return r->p_after + r->f_after * n;", "return r->p_after + r->f_line * n;"),
     "rounding truncates": ("double r = nearbyint(acc);", "double r = trunc(acc);"),
+    "rounding takes ties away from zero": ("double r = nearbyint(acc);", "double r = round(acc);"),
+    "no saturation": ("        if (r > 32767.0) r = 32767.0;\n        if (r < -32768.0) r = -32768.0;\n", ""),
     "amplitude held at its start after the ramp": ("if (d > r->m) return r->a_to;", "if (d > r->m) return r->a_from;"),
     "min-jerk amplitude profile coefficient": ("(10.0 - 15.0 * tau + 6.0 * tau * tau)", "(10.0 - 15.0 * tau + 5.0 * tau * tau)"),
 }
@@ -240,6 +286,6 @@ def test_c_oracle_mutants_are_caught(monkeypatch, tmp_path, oracle_built, name):
     monkeypatch.setattr(csynth, "_lib", None)
     monkeypatch.setattr(csynth, "build", lambda force=True: str(lib))
     try:
-        assert some_pin_fails(SUM_PINS + AMP_PINS), name
+        assert some_pin_fails(SUM_PINS + AMP_PINS + QUANT_PINS), name
     finally:
         csynth._lib = None

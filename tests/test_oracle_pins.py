@@ -103,6 +103,45 @@ def test_quarter_rate_tone_is_exact(oracle_built):
     assert list(q) == [1000, 0, -1000, 0]
 
 
+def _quarter_rate_codes(g, amp):
+    """Codes of a quarter-rate tone of amplitude*gain ``amp`` from the C sum and
+    from the Python evaluator (samples 0..7)."""
+    p = words.Plan(g["fs_hz"], float(amp), 0, one_tone(g["f_hz"]))
+    q, y = csynth.synth(p, 0, 8)
+    qp, yp = p.synth_points(range(8))
+    return q, y, qp, yp
+
+
+def test_quantiser_ties_go_to_even(oracle_built):
+    """Q of Eq. (2): samples exactly halfway between two codes go to the even code
+    (2.5 -> 2, -2.5 -> -2, 3.5 -> 4, -3.5 -> -4) in both the C sum and the Python
+    evaluator; rounding half away from zero would give 3 / -3."""
+    g = read_golden("quantiser_ties_and_saturation.txt")
+    for tag in ("tie_a", "tie_b"):
+        a = g[tag + "_amp"]
+        q, y, qp, yp = _quarter_rate_codes(g, a)
+        want = [0, g[tag + "_q1"], 0, g[tag + "_q3"]] * 2
+        assert [int(v) for v in q] == want, (tag, list(q))
+        assert [int(v) for v in qp] == want, (tag, list(qp))
+        assert y[1] == a and y[3] == -a and yp[1] == a and yp[3] == -a   # the ties are exact
+    assert [int(v) for v in words.quantise([0.5, 1.5, -0.5, -1.5, 2.5000001])] == [0, 2, 0, -2, 3]
+
+
+def test_quantiser_saturates_to_int16(oracle_built):
+    """Q of Eq. (2) for a 16-bit DAC: values beyond the code range take the end
+    codes 32767 and -32768 (no wrap-around); the tie at 32767.5 rounds to 32768
+    and saturates, the one at -32767.5 rounds to -32768, which is in range."""
+    g = read_golden("quantiser_ties_and_saturation.txt")
+    for tag in ("sat", "edge"):
+        a = g[tag + "_amp"]
+        q, y, qp, _ = _quarter_rate_codes(g, a)
+        want = [0, g[tag + "_q1"], 0, g[tag + "_q3"]] * 2
+        assert [int(v) for v in q] == want, (tag, list(q))
+        assert [int(v) for v in qp] == want, (tag, list(qp))
+        assert y[1] == a                                     # y itself is not clipped
+    assert [int(v) for v in words.quantise([1e9, -1e9, 32766.5, -32768.4])] == [32767, -32768, 32766, -32768]
+
+
 def test_eighth_rate_tone(oracle_built):
     p = words.Plan(FS, 20000.0, 0, one_tone(FS / 8))
     _, y = csynth.synth(p, 0, 16)
@@ -536,6 +575,40 @@ def test_schroeder_equal_amplitudes_reduce_to_textbook_form():
         k = K - i                                  # rank of input i (frequencies descend)
         t = Fraction(-k * (k - 1), 2 * K)
         assert abs(got[i] - float(t - math.floor(t))) < 1e-15
+
+
+def test_schroeder_unequal_amplitudes_by_hand():
+    """K = 3, A = 1, 2, 3: Schroeder's rule weights each tone by its power share
+    A^2 / sum A^2 (tests/golden/schroeder_unequal_k3.txt works it by hand);
+    frequencies are given out of order to check the ranking."""
+    g = read_golden("schroeder_unequal_k3.txt")
+    f = [3e6, 1e6, 2e6]
+    amps = [3.0, 1.0, 2.0]                          # rank 3, 1, 2
+    got = PH.phase_plan(PH.SCHROEDER, f, amps)
+    want = [Fraction(g["theta%d_num" % r], g["theta%d_den" % r]) for r in (3, 1, 2)]
+    for x, w in zip(got, want):
+        assert abs(x - float(w)) < 1e-15, (got, want)
+
+
+def test_schroeder_sweep_spends_time_by_power():
+    """Schroeder's construction: the phase slope between neighbouring tones is
+    minus the power fraction accumulated so far, so the waveform's frequency
+    sweep dwells on each tone for a share of the period equal to its power
+    share. With p_k = A_k^2 / sum A^2 and P_k = p_1 + ... + p_k (turns):
+    theta_{k+1} - theta_k = -P_k (mod 1). Two amplitude levels, 1 and 3, make the
+    weighting by power (not by amplitude) visible."""
+    rng = np.random.default_rng(11)
+    K = 40
+    amps = np.where(rng.random(K) < 0.5, 1.0, 3.0)
+    f = rng.permutation(np.arange(K) + 1.0) * 1e6
+    got = PH.phase_plan(PH.SCHROEDER, f, amps)
+    order = np.argsort(f, kind="stable")
+    power = amps[order] ** 2 / np.sum(amps ** 2)
+    P = np.cumsum(power)
+    th = np.array(got)[order]
+    for k in range(K - 1):
+        d = (th[k + 1] - th[k] + P[k]) % 1.0
+        assert min(d, 1.0 - d) < 1e-12, k
 
 
 def test_newman_phases_by_hand():
