@@ -410,6 +410,9 @@ typedef struct {
     uint64_t launches;
     double total_ms;
     double max_ms;
+    double work;             /* algorithmic tone-samples of the timed launches: tones x samples
+                                summed (direct kernels), line tones x the samples of the rows
+                                they cover (angle-addition products); 0 for helper kernels */
 } awg_kernel_stat;
 
 /* Event timing of the kernels of all calls on plans of ctx (off by default):

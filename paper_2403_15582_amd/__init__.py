@@ -15,6 +15,7 @@ fallback implementation.
 import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -58,7 +59,7 @@ class awg_plan_info(ctypes.Structure):
 
 class awg_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64),
-                ("total_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("work", ctypes.c_double)]
 
 
 class awg_server_params(ctypes.Structure):
@@ -108,14 +109,31 @@ class awg_amp_ramp(ctypes.Structure):
 _lib = None
 _exiting = False
 _VP = ctypes.c_void_p
+# objects that own library handles, closed in a fixed order at interpreter exit
+_live_servers = weakref.WeakSet()
+_live_plans = weakref.WeakSet()
 
 
 @atexit.register
-def _mark_exit():
-    # plans still alive at interpreter exit are left to the OS: the HIP runtime
-    # may already be tearing down when their finalizers would run
+def _teardown():
+    """Release every library object still alive at interpreter exit while the
+    HIP runtime is still fully up (Python's exit handlers all run before the
+    process's C-level exit, where the runtime tears down): servers first (their
+    scheduler threads launch work), then plans, then the cached contexts
+    (which synchronise their device before freeing). Finalizers that run
+    later see _exiting and do nothing."""
     global _exiting
-    _exiting = True
+    if _exiting:
+        return
+    try:
+        for s in list(_live_servers):
+            s.close()
+        for p in list(_live_plans):
+            p.close()
+        for dev in list(_ctx_cache):
+            awg_ctx_destroy(_ctx_cache.pop(dev))
+    finally:
+        _exiting = True
 
 _U64 = ctypes.c_uint64
 _I32 = ctypes.c_int32
@@ -395,11 +413,12 @@ def awg_profile_enable(ctx, enable=True):
 
 
 def awg_profile_read(ctx, reset=False):
-    """{kernel name: (launches, total_ms, max_ms)} since the last reset."""
+    """{kernel name: (launches, total_ms, max_ms, work)} since the last reset;
+    work = algorithmic tone-samples of the timed launches."""
     arr = (awg_kernel_stat * 64)()
     n = _I32()
     _check(lib().awg_profile_read(ctx, arr, 64, ctypes.byref(n), 1 if reset else 0), "awg_profile_read")
-    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms, arr[i].max_ms)
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms, arr[i].max_ms, arr[i].work)
             for i in range(min(n.value, 64))}
 
 
@@ -477,6 +496,7 @@ class Plan:
         self.handle, self.f_quantised_hz = awg_plan_tones(ctx, fs_hz, gain_lsb, period_log2, method,
                                                           self.tones)
         self.n_tones = len(self.tones)
+        _live_plans.add(self)
 
     def close(self):
         if self.handle:

@@ -123,8 +123,8 @@ struct Table {
 }  // namespace awg
 
 namespace awg {
-struct ProfRecord { const char *name; hipEvent_t start, stop; };
-struct ProfTotal { uint64_t launches; double total_ms, max_ms; };
+struct ProfRecord { const char *name; hipEvent_t start, stop; double work; };
+struct ProfTotal { uint64_t launches; double total_ms, max_ms, work; };
 }  // namespace awg
 
 struct awg_ctx {
@@ -139,7 +139,6 @@ struct awg_ctx {
     std::map<std::string, awg::ProfTotal> prof_totals;
     // smooth-ramp tables shared by all plans of the context, keyed by (shape, N)
     std::map<std::pair<int32_t, uint64_t>, awg::Table> tables;
-    hipStream_t upload_stream;
 };
 
 struct awg_plan {
@@ -211,12 +210,16 @@ public:
     ProfScope &operator=(const ProfScope &) = delete;
     template <typename F, typename... Args>
     void launch(F kernel, dim3 grid, dim3 block, uint32_t shmem, Args... args);
+    // algorithmic work of the scope's launches (tone-samples), added up by
+    // awg_profile_read for the launches that were timed
+    void add_work(double tone_samples) { work_ += tone_samples; }
 private:
     awg_ctx *ctx_;
     hipStream_t s_;
     const char *name_;
     hipEvent_t start_, stop_;
     bool launched_;
+    double work_ = 0.0;
 };
 
 // Kernel launchers (direct.hip, mfma.hip). Return a HIP error code.
@@ -263,12 +266,13 @@ constexpr uint32_t kLineShift = 29;
 enum : uint32_t { kLinePre = 0, kLinePost = 1, kLineSplitPre = 2, kLineSplitPost = 3, kLineNone = 4 };
 LinesGeom lines_geometry(int32_t n_entries, int32_t max_entries, uint64_t count);
 // d_blocks / n_blocks: the k-blocks whose B operand must be (re)built; all when d_blocks is null.
+// work: the algorithmic tone-samples of the launch, for the profiler.
 hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, const uint32_t *d_entries,
                         int32_t n_entries, const int32_t *d_blocks, int32_t n_blocks, uint64_t n0,
-                        uint64_t count, void *d_work, hipStream_t s);
+                        uint64_t count, void *d_work, hipStream_t s, double work);
 hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks,
                                 const uint32_t *d_order, uint64_t n0, uint64_t count, const float *planes,
                                 int32_t n_planes, uint64_t plane_stride, int16_t *out_i16, float *out_f32,
-                                hipStream_t s);
+                                hipStream_t s, double work);
 
 }  // namespace awg

@@ -269,7 +269,6 @@ awg_status awg_ctx_create(int device, awg_ctx **out)
     awg_ctx *c = new (std::nothrow) awg_ctx();
     if (!c) return AWG_E_NOMEM;
     c->device = device;
-    c->upload_stream = nullptr;
     *out = c;
     return AWG_OK;
 }
@@ -752,6 +751,7 @@ awg_status awg_synth_multiplex(awg_plan *const *plans, int32_t n_channels, uint6
     if (count > UINT64_MAX / (uint64_t)n_channels) return AWG_E_INVALID;
     if ((st = check_out(plans[0], d_out, count * (uint64_t)n_channels, sizeof(int16_t))) != AWG_OK) return st;
     ProfScope prof(plans[0]->ctx, (hipStream_t)hip_stream, "mux_kernel");
+    for (int32_t c = 0; c < n_channels; ++c) prof.add_work((double)plans[c]->n_tones * (double)count);
     return hip_status(launch_mux(items, n_channels, count, (hipStream_t)hip_stream, prof));
 }
 

@@ -634,6 +634,7 @@ static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, 
         hipError_t e;
         {
             ProfScope prof(p->ctx, s, F32OUT ? "direct_kernel_f32" : "direct_kernel");
+            prof.add_work((double)p->n_tones * (double)now);
             if (p->n_ramped == 0)
                 prof.launch(direct_kernel<kS, F32OUT, true>, dim3((uint32_t)now_tiles), dim3(256), 0, p->d_tones,
                             p->d_blocks, p->d_table_ptrs, n0, now, out);
@@ -686,13 +687,14 @@ hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint6
 hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks,
                                 const uint32_t *d_order, uint64_t n0, uint64_t count, const float *planes,
                                 int32_t n_planes, uint64_t plane_stride, int16_t *out_i16, float *out_f32,
-                                hipStream_t s)
+                                hipStream_t s, double work)
 {
     constexpr uint64_t T = kLanes * kS;
     const uint64_t tiles = (count + T - 1) / T;
     if (tiles == 0) return hipSuccess;
     if (tiles > kMaxTilesPerLaunch) return hipErrorInvalidValue;
     ProfScope prof(p->ctx, s, out_f32 ? "direct_hybrid_kernel_f32" : "direct_hybrid_kernel");
+    prof.add_work(work);
     if (out_f32)
         prof.launch(direct_hybrid_kernel<kS, true>, dim3((uint32_t)tiles), dim3(256), 0, d_tones, d_blocks, d_order,
                     p->d_table_ptrs, n0, count, (void *)out_f32, planes, n_planes, plane_stride);

@@ -75,6 +75,7 @@ struct HybridState {
     std::vector<uint32_t> entries, extras;
     std::vector<int32_t> split, only, dirty;
     int32_t n_line = 0;
+    double line_work = 0.0, direct_work = 0.0;   // tone-samples of the product / the direct kernel
     std::vector<ToneDev> direct;
     std::vector<Block> blocks;
     std::vector<float> cost;
@@ -129,7 +130,7 @@ static void sort_group(const std::vector<ToneDev> &tones, std::vector<int32_t> *
 // multiple of 8 are padding, and the second lines of tones split on both sides
 // follow. A tone's slot then keeps its frequency word, and with it its columns
 // of the B operand, until its line changes.
-static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t rows)
+static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t rows, uint64_t count)
 {
     const int32_t K = p->n_tones;
     h->entries.assign((size_t)(K + 7) / 8 * 8, kLineNone << kLineShift);
@@ -137,6 +138,11 @@ static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t ro
     h->split.clear();
     h->only.clear();
     h->n_line = 0;
+    // line rows are whole rows, except that the last row holds count - (rows - 1) * kRow samples
+    const double full = (double)count;
+    const double tail_short = (double)(rows * kRow - count);
+    h->line_work = 0.0;
+    h->direct_work = 0.0;
     const uint64_t last = n0 + rows * kRow - 1;
     for (int32_t k = 0; k < K; ++k) {
         const ToneDev &t = p->dev_mirror[k];
@@ -145,11 +151,13 @@ static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t ro
         if (t.lo > t.hi || last < t.lo) {
             h->entries[k] = kk | (kLinePre << kLineShift);
             h->n_line++;
+            h->line_work += full;
             continue;
         }
         if (n0 > t.hi) {
             h->entries[k] = kk | (kLinePost << kLineShift);
             h->n_line++;
+            h->line_work += full;
             continue;
         }
         // rows ending before lo (n0 + 1024c + 1023 < lo) and starting after hi
@@ -162,9 +170,13 @@ static void classify(const awg_plan *p, HybridState *h, uint64_t n0, uint64_t ro
             h->n_line++;
             if (pre_rows && post_rows) h->extras.push_back(kk | (kLineSplitPost << kLineShift));
             h->split.push_back(k);
+            const double line = (double)(line_rows * kRow) - (post_rows ? tail_short : 0.0);
+            h->line_work += line;
+            h->direct_work += full - line;
         } else {
             h->entries[k] = kk | (kLineNone << kLineShift);
             h->only.push_back(k);
+            h->direct_work += full;
         }
     }
     h->entries.insert(h->entries.end(), h->extras.begin(), h->extras.end());
@@ -301,7 +313,7 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
                         int16_t *out_i16, float *out_f32, hipStream_t s)
 {
     const uint64_t rows = (count + kRow - 1) / kRow;
-    classify(p, h, n0, rows);
+    classify(p, h, n0, rows, count);
     const int32_t n_entries = (int32_t)h->entries.size();
     const int32_t max_entries = (p->n_tones + 7) / 8 * 8 + p->n_tones;
     const int32_t n_direct = (int32_t)h->direct.size();
@@ -373,12 +385,12 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
     if (e == hipSuccess && h->work_used) e = hipStreamWaitEvent(s, h->work_done, 0);
     if (e == hipSuccess && gemm)
         e = launch_lines(p, method, g, (const uint32_t *)db, n_entries, partial ? (const int32_t *)(db + off_d) : nullptr,
-                         partial ? (int32_t)h->dirty.size() : 0, n0, count, h->d_work, s);
+                         partial ? (int32_t)h->dirty.size() : 0, n0, count, h->d_work, s, h->line_work);
     const float *planes = gemm ? (const float *)((char *)h->d_work + 2 * (g.a_bytes + g.b_bytes)) : nullptr;
     if (e == hipSuccess)
         e = launch_direct_hybrid(p, (const ToneDev *)(db + off_t), (const Block *)(db + off_b),
                                  (const uint32_t *)(db + off_o), n0, count, planes, gemm ? g.gz : 0, g.plane,
-                                 out_i16, out_f32, s);
+                                 out_i16, out_f32, s, h->direct_work);
     if (e == hipSuccess) e = hipEventRecord(h->work_done, s);
     if (e == hipSuccess) h->work_used = true;
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);

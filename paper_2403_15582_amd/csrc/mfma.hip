@@ -579,6 +579,7 @@ static awg_status run(awg_plan *p, uint64_t n0, uint64_t count, int16_t *out_i16
     float *planes = (float *)(w + 2 * (a_bytes + b_bytes));
     {
         ProfScope prof(p->ctx, s, f16 ? "angle_gemm_kernel_f16" : "angle_gemm_kernel_bf16");
+        prof.add_work((double)p->n_tones * (double)count);
         if (gz == 1)
             e = dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_n, 0, mcols, count,
                                  out_i16, out_f32);
@@ -621,7 +622,7 @@ LinesGeom lines_geometry(int32_t n_entries, int32_t max_entries, uint64_t count)
 template <typename T>
 static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_t *d_entries, int32_t n_entries,
                             const int32_t *d_blocks, int32_t n_blocks, uint64_t n0, uint64_t count, char *w,
-                            hipStream_t s)
+                            hipStream_t s, double work)
 {
     const bool f16 = std::is_same<T, _Float16>::value;
     T *b_hi = (T *)w, *b_lo = (T *)(w + g.b_bytes);
@@ -645,19 +646,22 @@ static hipError_t lines_run(const awg_plan *p, const LinesGeom &g, const uint32_
     if (e != hipSuccess) return e;
     dim3 grid((uint32_t)(g.cb_n / kTileCB), (uint32_t)(g.rb_pad / kTileRB), (uint32_t)g.gz);
     ProfScope prof(p->ctx, s, f16 ? "hyb_gemm_f16" : "hyb_gemm_bf16");
+    prof.add_work(work);
     return dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, g.kb_n, g.rb_pad, g.cb_n, g.kb_split, g.plane,
                             mcols, count, nullptr, planes);
 }
 
 hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, const uint32_t *d_entries,
                         int32_t n_entries, const int32_t *d_blocks, int32_t n_blocks, uint64_t n0,
-                        uint64_t count, void *d_work, hipStream_t s)
+                        uint64_t count, void *d_work, hipStream_t s, double work)
 {
     if (g.gz <= 0 || n_entries <= 0) return hipSuccess;
     if (method == AWG_F_METHOD_MFMA_F16X3)
-        return lines_run<_Float16>(p, g, d_entries, n_entries, d_blocks, n_blocks, n0, count, (char *)d_work, s);
+        return lines_run<_Float16>(p, g, d_entries, n_entries, d_blocks, n_blocks, n0, count, (char *)d_work, s,
+                                   work);
     if (method == AWG_F_METHOD_MFMA_BF16X3)
-        return lines_run<__bf16>(p, g, d_entries, n_entries, d_blocks, n_blocks, n0, count, (char *)d_work, s);
+        return lines_run<__bf16>(p, g, d_entries, n_entries, d_blocks, n_blocks, n0, count, (char *)d_work, s,
+                                 work);
     return hipErrorInvalidValue;
 }
 

@@ -52,7 +52,7 @@ ProfScope::~ProfScope()
         ctx_->prof_pool.push_back(stop_);
         return;
     }
-    ctx_->prof_pending.push_back(ProfRecord{name_, start_, stop_});
+    ctx_->prof_pending.push_back(ProfRecord{name_, start_, stop_, work_});
 }
 
 }  // namespace awg
@@ -85,6 +85,7 @@ awg_status awg_profile_read(awg_ctx *ctx, awg_kernel_stat *out, int32_t max_stat
         ProfTotal &t = ctx->prof_totals[r.name];
         t.launches += 1;
         t.total_ms += ms;
+        t.work += r.work;
         if (ms > t.max_ms) t.max_ms = ms;
         ctx->prof_pool.push_back(r.start);
         ctx->prof_pool.push_back(r.stop);
@@ -98,6 +99,7 @@ awg_status awg_profile_read(awg_ctx *ctx, awg_kernel_stat *out, int32_t max_stat
             out[i].launches = kv.second.launches;
             out[i].total_ms = kv.second.total_ms;
             out[i].max_ms = kv.second.max_ms;
+            out[i].work = kv.second.work;
         }
         ++i;
     }

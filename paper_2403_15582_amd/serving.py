@@ -11,7 +11,7 @@ import numpy as np
 
 from . import (awg_server_create, awg_server_destroy, awg_server_submit, awg_server_poll,
                awg_server_read, awg_server_release, awg_server_stats_get, AwgError, AWG_E_BUSY,
-               context)
+               context, _live_servers)
 
 
 class Server:
@@ -20,6 +20,13 @@ class Server:
         self.chunk_len = chunk_len
         self.handle = awg_server_create(context(device), mem_budget_bytes, max_jobs, ring_slots,
                                         chunk_len, max_pending, playout_delay_ms)
+        _live_servers.add(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def close(self):
         if self.handle:
@@ -36,9 +43,10 @@ class Server:
         return awg_server_stats_get(self.handle)
 
     def run_trace(self, jobs, collect=(), time_scale=1.0, timeout_s=120.0, poll_sleep_s=50e-6):
-        """Submit `jobs` (objects with arrival_s, fs_hz, tones, n_samples) at
-        arrival_s * time_scale after the start, drain every chunk, and return
-        {job index: int16 samples} for the indices in `collect`."""
+        """Submit `jobs` (objects with arrival_s, fs_hz, tones, n_samples and
+        optionally gain_lsb) at arrival_s * time_scale after the start, drain
+        every chunk, and return {job index: int16 samples} for the indices in
+        `collect`."""
         collect = set(collect)
         out = {k: np.zeros(jobs[k].n_samples, dtype=np.int16) for k in collect}
         start = time.perf_counter()
@@ -51,7 +59,8 @@ class Server:
             while nxt < len(jobs) and jobs[nxt].arrival_s * time_scale <= now:
                 j = jobs[nxt]
                 try:
-                    awg_server_submit(self.handle, j.fs_hz, j.tones, j.n_samples, user_tag=nxt)
+                    awg_server_submit(self.handle, j.fs_hz, j.tones, j.n_samples,
+                                      gain_lsb=getattr(j, "gain_lsb", 0.0), user_tag=nxt)
                 except AwgError as e:
                     if e.status == AWG_E_BUSY:
                         break                      # queue full: retry on the next pass

@@ -162,6 +162,7 @@ class Job:
     fs_hz: float
     n_samples: int
     tones: np.ndarray
+    gain_lsb: float = 0.0      # 0 = default (32767 / sum|A|)
 
 
 def poisson_jobs(seed=5, rate_hz=2000.0, seconds=2.0, kmin=50, kmax=2000,

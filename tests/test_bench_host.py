@@ -21,17 +21,26 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_roofline_direct_and_mfma():
+    """The dominant kernel (largest timed total) and its algorithmic rate from the
+    library's work count: 2 flop per tone-sample on the direct kernels over the
+    FP32 vector peak, 4 on the angle-addition products over the matrix peak."""
     K, L = 1000, 1 << 24
-    stats = {"direct_kernel": (5, 5 * 2.0, 2.1)}                      # 2 ms per launch
-    r = bench.roofline_for("direct", stats, K, L)
+    stats = {"direct_kernel": (5, 5 * 2.0, 2.1, 5.0 * K * L)}         # 2 ms per launch
+    r = bench.roofline_for(stats)
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == bench.PEAK_FP32_TFLOPS
     assert abs(r["achieved"] - 2.0 * K * L / 2e-3 / 1e12) < 1e-9
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
-    stats = {"angle_gemm_kernel_bf16": (5, 5 * 0.16, 0.17), "gen_a_kernel_bf16": (5, 5 * 0.013, 0.02)}
-    r = bench.roofline_for("mfma-bf16", stats, K, L)
+    assert r["work_per_launch"] == K * L
+    stats = {"angle_gemm_kernel_bf16": (5, 5 * 0.16, 0.17, 5.0 * K * L), "gen_a_kernel_bf16": (5, 5 * 0.013, 0.02, 0.0)}
+    r = bench.roofline_for(stats)
     assert r["bound"] == "mfma" and r["kernel"] == "angle_gemm_kernel_bf16"
     assert abs(r["achieved"] - 4.0 * K * L / 0.16e-3 / 1e12) < 1e-6
-    assert abs(r["issued_tflops"] - 3 * r["achieved"]) < 1e-6 and r["peak"] == bench.PEAK_MFMA16_TFLOPS
+    assert abs(r["issued_tflops_min"] - 3 * r["achieved"]) < 1e-6 and r["peak"] == bench.PEAK_MFMA16_TFLOPS
+    # the hybrid product counts only the tone-samples it covers
+    stats = {"hyb_gemm_bf16": (4, 4 * 0.1, 0.11, 4 * 9900.0 * (1 << 20)),
+             "direct_hybrid_kernel": (4, 4 * 0.05, 0.06, 4 * 100.0 * (1 << 20))}
+    r = bench.roofline_for(stats)
+    assert r["kernel"] == "hyb_gemm_bf16" and abs(r["achieved"] - 4.0 * 9900 * (1 << 20) / 0.1e-3 / 1e12) < 1e-6
 
 
 def test_traffic_lookup_follows_the_source_hash(tmp_path, monkeypatch):

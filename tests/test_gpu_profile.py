@@ -29,9 +29,12 @@ def test_sampled_kernel_timing(every, calls, timed):
     for o in outs:
         assert np.array_equal(to_np(o), ref)
     for name in ("gen_a_kernel_bf16", "angle_gemm_kernel_bf16"):
-        launches, total_ms, max_ms = st[name]
+        launches, total_ms, max_ms, work = st[name]
         assert launches == timed, (name, st)
         assert 0.0 < total_ms / launches <= max_ms < 100.0
+    # the product's algorithmic work: every tone at every sample of the timed calls
+    assert st["angle_gemm_kernel_bf16"][3] == timed * len(w.tones) * w.count
+    assert st["gen_a_kernel_bf16"][3] == 0.0
     assert awg.awg_profile_read(ctx) == {}
     p.close()
 

@@ -25,11 +25,23 @@ def _solo(torch, job):
     return q.cpu().numpy()
 
 
+def _big_job():
+    """A job at the top of the serving workload's ranges: 2000 tones chirped over
+    35 ms at 280 MS/s (9.8M samples, ten 2^20-sample chunks)."""
+    j = W.poisson_jobs(seed=71, max_jobs=1, kmin=2000, kmax=2000, dmin_ms=35.0, dmax_ms=35.0)[0]
+    assert j.fs_hz == 280e6 and j.n_samples == 9_800_000 and len(j.tones) == 2000
+    return j
+
+
 def test_mix_equals_alone_and_oracle():
     torch = need_gpu()
     jobs = _jobs(40)
-    say("serving mix of %d jobs, %d chunks" % (len(jobs), sum((j.n_samples + (1 << 20) - 1) >> 20 for j in jobs)))
-    keep = [0, 1, 7, 19, 39]
+    big = _big_job()
+    big.arrival_s = jobs[20].arrival_s + 1e-6        # lands in the middle of the mix
+    jobs.insert(21, big)
+    say("serving mix of %d jobs, %d chunks (job 21: K=2000, 35 ms)"
+        % (len(jobs), sum((j.n_samples + (1 << 20) - 1) >> 20 for j in jobs)))
+    keep = [0, 1, 7, 19, 21, 40]
     with Server(max_jobs=16, ring_slots=24) as srv:
         mixed = srv.run_trace(jobs, collect=keep, time_scale=0.05)
         st = srv.stats()
@@ -54,6 +66,16 @@ def test_mix_equals_alone_and_oracle():
                                        np.arange(max(0, j.n_samples - 300), j.n_samples)]))
         qo, yo = csynth.synth_at(op, ns)
         compare(mixed[k][ns], None, qo, yo, "served job %d (K=%d, %d samples)" % (k, len(j.tones), j.n_samples))
+    # the large job: its last (tenth, partial) chunk on every sample, and points of the others
+    j = jobs[21]
+    op = words.Plan(j.fs_hz, 0.0, 0, j.tones)
+    last0 = 9 << 20
+    qo, yo = csynth.synth(op, last0, j.n_samples - last0)
+    compare(mixed[21][last0:], None, qo, yo, "served job 21, last chunk (K=2000, samples %d..%d)"
+            % (last0, j.n_samples))
+    ns = np.unique(np.random.default_rng(21).integers(0, last0, 3000))
+    qo, yo = csynth.synth_at(op, ns)
+    compare(mixed[21][ns], None, qo, yo, "served job 21, chunks 0-8 (sampled %d)" % len(ns))
 
 
 def test_admission_by_memory_and_backpressure():
