@@ -118,7 +118,7 @@ def traffic_for(kernel):
 
 
 def is_matrix_kernel(name):
-    return name.startswith("angle_gemm") or name.startswith("hyb_gemm")
+    return name.startswith("angle_gemm") or name.startswith("hyb_gemm") or name.startswith("plb_gemm")
 
 
 def roofline_for(stats):

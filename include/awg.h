@@ -304,8 +304,32 @@ awg_status awg_stream_next_multiplex(awg_plan *const *plans, int32_t n_channels,
  * or all-zero amplitudes (Schroeder). */
 #define AWG_PHASES_SCHROEDER 1
 #define AWG_PHASES_NEWMAN    2
+#define AWG_PHASES_SEARCH    3   /* awg_phase_search only: phases found by the device search */
 awg_status awg_phase_plan(int32_t method, const double *f_hz, const double *amplitude, int32_t n_tones,
                           double *phase_turns_out);
+
+/* Crest-factor-aware phase planning on ctx's device, for tones on bins of the
+ * period L = 2^period_log2 (14 <= period_log2 <= 26; f as in awg_plan_tones
+ * with that period). Measures both closed forms above over one period, then
+ * (max_evals > 0) lowers the crest factor further by minimising the l_p norm
+ * of the period's samples, p = 8, 16, ..., 256, each stage by L-BFGS from the
+ * previous one (Guillaume et al. 1991, a Chebyshev approximation of the peak;
+ * max_evals bounds the evaluations, each one synthesis of the period plus one
+ * gradient correlation of every tone over it). Returns the phases (turns in
+ * [0, 1), input order) with the lowest crest factor found, which is
+ * max|y| / sqrt(sum A^2 / 2) over one period of y = sum A_k sin(2 pi b_k n / L
+ * + 2 pi phase_k) measured on the device for the phase words a plan makes of
+ * the returned turns (*crest_out, nullable), and which method gave them
+ * (*method_out, nullable: AWG_PHASES_*). Distinct bins are the caller's
+ * business (the crest factor assumes them). Allocates device memory for the
+ * period (4 L bytes) and partial sums (n_tones L / 4096 bytes), freed before
+ * returning. AWG_E_INVALID for null pointers, n_tones <= 0, max_evals < 0,
+ * bad fs, negative or all-zero amplitudes, f outside (0, fs/2);
+ * AWG_E_RANGE for a bin on 0 or L/2; AWG_E_UNSUPPORTED for a period outside
+ * [2^14, 2^26] or more than 2^20 tones (or partial sums above 1 GiB). */
+awg_status awg_phase_search(awg_ctx *ctx, double fs_hz, uint32_t period_log2, const double *f_hz,
+                            const double *amplitude, int32_t n_tones, int32_t max_evals, double *phase_turns_out,
+                            double *crest_out, int32_t *method_out);
 
 /* Peak |y| of a plan's unquantised sum over samples n0 .. n0+count-1, in LSB:
  * the direct kernel writes y (FP32) into d_scratch (device, count floats,
@@ -315,6 +339,7 @@ awg_status awg_phase_plan(int32_t method, const double *f_hz, const double *ampl
  * AWG_E_INVALID for NULL pointers or count = 0; AWG_E_RANGE as awg_synth_chirp. */
 awg_status awg_peak(awg_plan *plan, uint64_t n0, uint64_t count, float *d_scratch, float *d_peak,
                     void *hip_stream);
+
 
 /* Phase words of one tone as the direct kernel generates them (same code path,
  * same sample-to-lane mapping), for exact comparison: d_words[i] = phi(n0 + i). */

@@ -32,7 +32,8 @@ EXPORTED = [
     "awg_plan_reserve",
     "awg_synth_static", "awg_synth_chirp", "awg_stream_next", "awg_stream_seek",
     "awg_stream_tell", "awg_synth_f32", "awg_synth_multiplex", "awg_stream_next_multiplex",
-    "awg_phase_dump", "awg_phase_plan", "awg_peak", "awg_strerror", "awg_version",
+    "awg_phase_dump", "awg_phase_plan", "awg_phase_search", "awg_peak", "awg_strerror",
+    "awg_version",
     "awg_profile_enable", "awg_profile_read",
     "awg_server_create", "awg_server_destroy", "awg_server_submit", "awg_server_poll",
     "awg_server_slot", "awg_server_read", "awg_server_release", "awg_server_stats_get",
@@ -168,6 +169,8 @@ def lib():
         "awg_stream_next_multiplex": ([ctypes.POINTER(_VP), _I32, _U64, _VP, _VP, ctypes.POINTER(_U64)], _I32),
         "awg_phase_dump": ([_VP, _I32, _U64, _U64, _VP, _VP], _I32),
         "awg_phase_plan": ([_I32, _VP, _VP, _I32, _VP], _I32),
+        "awg_phase_search": ([_VP, ctypes.c_double, ctypes.c_uint32, _VP, _VP, _I32, _I32, _VP,
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)], _I32),
         "awg_peak": ([_VP, _U64, _U64, _VP, _VP, _VP], _I32),
         "awg_profile_enable": ([_VP, _I32], _I32),
         "awg_profile_read": ([_VP, ctypes.POINTER(awg_kernel_stat), _I32, ctypes.POINTER(_I32), _I32], _I32),
@@ -353,7 +356,7 @@ def multiplex(plans, n0, count, out=None, stream=None):
     return out
 
 
-AWG_PHASES_SCHROEDER, AWG_PHASES_NEWMAN = 1, 2
+AWG_PHASES_SCHROEDER, AWG_PHASES_NEWMAN, AWG_PHASES_SEARCH = 1, 2, 3
 
 
 def awg_phase_plan(method, f_hz, amplitude=None):
@@ -370,36 +373,25 @@ def awg_peak(plan, n0, count, d_scratch, d_peak, stream=0):
     _check(lib().awg_peak(plan, int(n0), int(count), d_scratch, d_peak, stream or None), "awg_peak")
 
 
-def crest_factor(tones, fs_hz, gain_lsb, period_log2, device=0):
-    """Crest factor (peak / rms) of the periodic waveform of static tones on
-    distinct bins of L = 2**period_log2, measured over one period on the device."""
-    import torch
-    p = Plan(tones, fs_hz, gain_lsb, period_log2, device=device)
-    L = 1 << int(period_log2)
-    scratch = torch.empty(L, dtype=torch.float32, device="cuda:%d" % device)
-    peak = torch.empty(1, dtype=torch.float32, device="cuda:%d" % device)
-    awg_peak(p.handle, 0, L, scratch.data_ptr(), peak.data_ptr(), torch.cuda.current_stream().cuda_stream)
-    gain = awg_plan_info_get(p.handle)["gain_lsb"]
-    rms = gain * float(np.sqrt(np.sum(np.asarray(tones["amplitude"], dtype=np.float64) ** 2) / 2.0))
-    value = float(peak.item()) / rms
-    p.close()
-    return value
+
+def awg_phase_search(ctx, fs_hz, period_log2, f_hz, amplitude, max_evals=300):
+    """Device crest-factor search: (phases in turns, crest factor, method)."""
+    f = np.ascontiguousarray(f_hz, dtype=np.float64)
+    a = np.ascontiguousarray(amplitude, dtype=np.float64)
+    out = np.empty(len(f), dtype=np.float64)
+    cf = ctypes.c_double()
+    m = _I32()
+    _check(lib().awg_phase_search(ctx, float(fs_hz), int(period_log2), f.ctypes.data, a.ctypes.data, len(f),
+                                  int(max_evals), out.ctypes.data, ctypes.byref(cf), ctypes.byref(m)),
+           "awg_phase_search")
+    return out, cf.value, m.value
 
 
-def plan_phases(tones, fs_hz, gain_lsb, period_log2, methods=(AWG_PHASES_SCHROEDER, AWG_PHASES_NEWMAN),
-                device=0):
-    """Crest-factor-aware phase planning: every closed form of ``methods`` is
-    synthesised over one period on the device and the phases with the lowest
-    measured crest factor are returned as (phases, {method: crest factor})."""
-    best, crest = None, {}
-    for m in methods:
-        ph = awg_phase_plan(m, tones["f_start_hz"], tones["amplitude"])
-        t = np.array(tones, copy=True)
-        t["phase_turns"] = ph
-        crest[m] = crest_factor(t, fs_hz, gain_lsb, period_log2, device)
-        if best is None or crest[m] < crest[best[0]]:
-            best = (m, ph)
-    return best[1], crest
+def plan_phases(tones, fs_hz, period_log2, max_evals=300, device=0):
+    """Crest-factor-aware phase planning (awg_phase_search): the closed forms and
+    the device search, the lowest measured crest factor wins. Returns
+    (phases in turns, crest factor, AWG_PHASES_* of the winner)."""
+    return awg_phase_search(context(device), fs_hz, period_log2, tones["f_start_hz"], tones["amplitude"], max_evals)
 
 
 def awg_phase_dump(plan, tone, n0, count, d_words, stream=0):

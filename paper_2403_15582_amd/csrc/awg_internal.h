@@ -112,6 +112,7 @@ struct LinesGeom {
 };
 
 struct HybridState;
+struct LineBuf;
 
 struct Table {
     int32_t shape;
@@ -178,12 +179,18 @@ struct awg_plan {
     bool work_used = false;
     // hybrid path (matrix cores + direct kernel for ramped plans), created on first use
     awg::HybridState *hyb;
+    // periodic line buffer (the hybrid path of plans on the bins of a period), created on first use
+    awg::LineBuf *plb = nullptr;
 };
 
 namespace awg {
 
 // Exact word arithmetic (plan.cpp)
 bool rne_ratio_shift(double num, double den, int shift, uint64_t *out);
+// Frequency word of f at fs: nint(f 2^64 / fs), or with p > 0 the bin
+// nint(f 2^p / fs) (Eq. (4)) times 2^(64-p). AWG_E_INVALID unless 0 < f < fs/2,
+// AWG_E_RANGE for the bins 0 and 2^(p-1).
+awg_status freq_word(double f, double fs, uint32_t p, uint64_t *out);
 uint64_t phase_word(double turns);
 int64_t rne_div(int64_t num, uint64_t den);
 int64_t minjerk_entry(uint64_t n, uint64_t d);
@@ -244,6 +251,35 @@ hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t s
 // address *mapped.
 hipError_t alloc_upload_host(size_t bytes, void **host, void **mapped);
 hipError_t launch_batch(const BatchItem *d_items, const uint32_t *d_header, uint32_t grid, hipStream_t s);
+
+// Periodic line-buffer path (linebuf.cpp): a segment of rows [row_begin,
+// row_end] of a call whose line tones of one group are q_row rather than the
+// q_next that S holds (both period sums of L floats), and a fold of one group's
+// sum into S (q_old: the sum S held for the group, or null).
+struct PlbSeg {
+    uint32_t row_begin, row_end;
+    const float *q_row;
+    const float *q_next;
+};
+static_assert(sizeof(PlbSeg) == 24, "PlbSeg must be 24 bytes");
+struct PlbFold {
+    const float *q_new;
+    const float *q_old;
+};
+hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const uint32_t *d_order,
+                      uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L, const PlbSeg *d_segs,
+                      int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s, double work);
+hipError_t launch_plb_fold(const awg_plan *p, int64_t *d_S, uint64_t L, const PlbFold *d_folds, int32_t n_fold,
+                           hipStream_t s);
+hipError_t launch_plb_zero(int64_t *d_S, uint64_t L, hipStream_t s);
+// Period sums of groups of tones (mfma.hip): d_list holds n_built groups of
+// group_tones static line records each (amplitude 0 for padding); the sum of
+// group z over samples [0, L) goes to q_base + plane_map[z] * L (d_plane_map:
+// device, n_built entries). d_work: at least group_work_bytes(...) bytes.
+size_t group_work_bytes(int32_t n_built, int32_t group_tones, uint64_t L);
+hipError_t launch_group_sums(const awg_plan *p, uint32_t method, const ToneDev *d_list, int32_t n_built,
+                             int32_t group_tones, uint64_t L, void *d_work, float *q_base,
+                             const int32_t *d_plane_map, hipStream_t s, double work);
 // Multiplexed channels: items[c] (c < n, n <= kMaxChannels) each cover the same
 // count samples; one launch, items passed by value.
 constexpr int kMaxChannels = 4;
@@ -255,11 +291,19 @@ awg_status mfma_static(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count
 // Hybrid path (hybrid.cpp): a ramped plan's samples with the line tones on the
 // matrix cores and the ramping ones on the direct kernel.
 awg_status mfma_static_reserve(awg_plan *p, uint64_t max_count);
-awg_status hybrid_reserve(awg_plan *p, uint64_t max_count);
+awg_status hybrid_reserve(awg_plan *p, uint32_t method, uint64_t max_count);
 awg_status hybrid_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,
                         float *out_f32, hipStream_t s);
 void hybrid_release(awg_plan *p);
 size_t hybrid_bytes(const awg_plan *p);       // device memory held by the hybrid path
+// Periodic line buffer (linebuf.cpp): the hybrid path of plans whose period
+// L = 2^p is between 2^10 and 2^24 and whose buffer fits its memory bound.
+bool plb_eligible(const awg_plan *p);
+awg_status plb_reserve(awg_plan *p, uint32_t method);
+awg_status plb_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32,
+                     hipStream_t s);
+void plb_release(awg_plan *p);
+size_t plb_bytes_of(const awg_plan *p);
 // Its two launches (mfma.hip, direct.hip). Line entries: bits 0..28 the tone's
 // device position, bits 29..31 the mode (kLine*; kLineNone: no rows, zero amplitude).
 constexpr uint32_t kLineShift = 29;

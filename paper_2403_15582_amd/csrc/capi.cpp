@@ -29,23 +29,6 @@ awg_status hip_status(hipError_t e)
     return AWG_E_HIP;
 }
 
-// Frequency word of f at fs (Eq. (4) when period_log2 > 0).
-awg_status freq_word(double f, double fs, uint32_t p, uint64_t *out)
-{
-    if (!std::isfinite(f) || !(f > 0.0) || !(f < fs * 0.5)) return AWG_E_INVALID;
-    uint64_t w;
-    if (p > 0) {
-        if (!rne_ratio_shift(f, fs, (int)p, &w)) return AWG_E_RANGE;
-        if (w < 1 || w >= (1ull << (p - 1))) return AWG_E_RANGE;
-        *out = w << (64 - p);
-        return AWG_OK;
-    }
-    if (!rne_ratio_shift(f, fs, 64, &w)) return AWG_E_RANGE;
-    if (w < 1 || w >= (1ull << 63)) return AWG_E_RANGE;
-    *out = w;
-    return AWG_OK;
-}
-
 bool smooth(int32_t shape) { return shape == AWG_RAMP_COSINE || shape == AWG_RAMP_MINJERK; }
 
 // Fill H_N[0..N] with up to 8 host threads.
@@ -647,7 +630,7 @@ awg_status awg_plan_reserve(awg_plan *p, uint32_t method, uint64_t max_count)
     // a static plan's matrix-core calls use the product workspace; a ramped
     // plan's take the hybrid path (and a plan retuned later may need both)
     if ((st = mfma_static_reserve(p, max_count)) != AWG_OK) return st;
-    return p->n_ramped > 0 ? hybrid_reserve(p, max_count) : AWG_OK;
+    return p->n_ramped > 0 ? hybrid_reserve(p, method, max_count) : AWG_OK;
 }
 
 awg_status awg_synth_chirp(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d_out, void *hip_stream)

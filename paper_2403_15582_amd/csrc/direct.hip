@@ -245,17 +245,32 @@ struct HybridIn {
     uint64_t add_stride;
 };
 
+// Extra input of the periodic line-buffer path (plans whose tones sit on bins of
+// a period L): the line tones come from S, an exact fixed-point period sum
+// (S[m] * 2^-32 at m = n mod L), plus for each segment whose rows hold this
+// tile the difference q_row[m] - q_next[m] of two cached group sums; every
+// tone of a split-flagged block is summed only on the tiles in [t.lo, t.hi]
+// (window tiles and lines alike). Segments are applied in list order.
+struct PlbIn {
+    const int64_t *S;            // nullptr: not the line-buffer path
+    uint64_t mask;               // L - 1
+    const PlbSeg *segs;
+    int32_t n_seg;
+    uint32_t row;                // this tile's row in the call
+};
+
 // One tile: the 64*S samples tile0 .. tile0 + 64*S - 1 of a tone list, summed
 // by the 4 waves of the workgroup and written to out[0 .. valid). STATIC: every
 // tone is a static line (no windows), so the regime logic is compiled out; the
 // arithmetic per sample is the same as the static regime of gen_phases, so both
 // instantiations give identical sums. HYB: see HybridIn. Ends with a barrier so
 // `part` can be reused by the next tile of the same workgroup.
-template <int S, bool F32OUT, bool STATIC, bool HYB = false>
+template <int S, bool F32OUT, bool STATIC, bool HYB = false, bool PLB = false>
 __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, const Block *__restrict__ blocks,
                                            const uint64_t *const *__restrict__ tables, uint64_t tile0,
                                            uint32_t valid, void *__restrict__ out, float (*part)[kLanes * S],
-                                           const HybridIn &hyb = HybridIn{0, nullptr, 0}, uint32_t ostride = 1)
+                                           const HybridIn &hyb = HybridIn{0, nullptr, 0}, uint32_t ostride = 1,
+                                           const PlbIn &plb = PlbIn{nullptr, 0, nullptr, 0, 0})
 {
     constexpr int T = kLanes * S;                 // samples per tile
     const uint32_t lane = threadIdx.x & 63u;
@@ -291,8 +306,10 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
             const ToneDev r = tones[k0];
             const bool pre = tile_last < r.a, post = tile0 > r.a + r.n;
             if (pre || post) {
-                // (a block of split tones on a line is summed elsewhere)
-                for (int k = k0; k < (split ? k0 : k1); ++k) {
+                // (a block of split tones on a line is summed elsewhere, except on
+                // the line-buffer path, where each tone is summed on its own tiles)
+                for (int k = k0; k < (split && !PLB ? k0 : k1); ++k) {
+                    if (PLB && split && (tile_last < tones[k].lo || tile0 > tones[k].hi)) continue;
                     const uint64_t P = pre ? tones[k].p0 : tones[k].p1, Fw = pre ? tones[k].f0 : tones[k].f1;
                     const float amp = tones[k].amp;
                     static_run<S>(P, Fw, tile0, j, [&](int s, uint64_t ph) {
@@ -314,11 +331,12 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                 } else {
                     // the table values of this lane's samples serve every tone of the block
                     const uint64_t *H = table_of(tables, r.table) + dt + j;
-                    // dF a multiple of 2^16 for every tone of the block (always for bin
-                    // frequencies) and a tagged table: the incremental step below; else
-                    // the full product per sample. One loop or the other per block, so
-                    // the two never hold registers at the same time.
-                    const bool step16 = (bk.flags & kBlockStep16) && table_monotone(tables, r.table);
+                    // A tagged table: incremental steps below (dF a multiple of 2^16 for
+                    // every tone of the block, always so for bin frequencies, or any dF);
+                    // else the full product per sample. One loop per block, so the loops
+                    // never hold registers at the same time.
+                    const bool tagged = table_monotone(tables, r.table);
+                    const bool step16 = (bk.flags & kBlockStep16) && tagged;
                     // the lane's first table value and the successive differences
                     // (non-negative, below 2^23 when tagged)
                     const uint64_t hv0 = H[0];
@@ -355,6 +373,44 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                                     const uint32_t hi = (uint32_t)(lo >> 32) + (uint32_t)__mul24(m_hi, (int32_t)dh[s]);
                                     ph += ((uint64_t)hi << 32) | (uint32_t)lo;
                                 }
+                            }
+                        }
+                    } else if (tagged) {
+                        // any dF = m 2^16 + r (m = floor(dF / 2^16), 0 <= r < 2^16): the chirp
+                        // term floor(dF H / 2^16) is m H + floor(r H / 2^16). The word steps
+                        // by f0 + m dh as in the loop above plus the carry out of the 16-bit
+                        // fraction q of r H / 2^16 (q + r dh < 2^40), all exact.
+                        uint64_t prev = hv0;
+#pragma unroll
+                        for (int s = 0; s + 1 < S; ++s) {
+                            const uint64_t cur = H[s + 1];
+                            dh[s] = (uint32_t)(cur - prev);
+                            prev = cur;
+                        }
+                        for (int k = k0; k < k1; ++k) {
+                            const uint64_t p0 = tones[k].p0, f0 = tones[k].f0;
+                            const int64_t dF = tones[k].coef;
+                            const float amp = tones[k].amp;
+                            const uint64_t m = (uint64_t)(dF >> 16);
+                            const uint32_t rr = (uint32_t)dF & 0xffffu;
+                            const uint32_t m_lo = (uint32_t)m;
+                            const int32_t m_hi = (int32_t)(m >> 32);            // |m_hi| <= 2^15
+                            const uint64_t u0 = (uint64_t)rr * hv0;             // < 2^62
+                            uint64_t ph = p0 + f0 * tile0 + f0 * (uint64_t)j + m * hv0 + (u0 >> 16);
+                            uint32_t q = (uint32_t)u0 & 0xffffu;
+#pragma unroll
+                            for (int s = 0; s < S; ++s) {
+                                blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
+                                if (s + 1 < S) {
+                                    const uint64_t t = (uint64_t)rr * dh[s] + q;
+                                    q = (uint32_t)t & 0xffffu;
+                                    const uint64_t lo = (uint64_t)m_lo * dh[s] + (f0 + (t >> 16));
+                                    const uint32_t hi = (uint32_t)(lo >> 32) + (uint32_t)__mul24(m_hi, (int32_t)dh[s]);
+                                    ph += ((uint64_t)hi << 32) | (uint32_t)lo;
+                                }
+                                // one sample at a time: hoisting the r dh products of later
+                                // samples ahead would cost registers (waves) for no gain
+                                __builtin_amdgcn_sched_barrier(0);
                             }
                         }
                     } else {
@@ -488,11 +544,44 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
             }
         }
     }
+    if (PLB) {
+        // the line tones: S and the segments' group differences at m = n mod L
+        const uint64_t m0 = (tile0 + i0) & plb.mask;
+        if (i0 + PER <= valid && (m0 & 3) == 0 && m0 + 3 <= plb.mask) {
+            const longlong2 sa = *(const longlong2 *)(plb.S + m0), sb = *(const longlong2 *)(plb.S + m0 + 2);
+            g[0] = (float)((double)sa.x * 0x1p-32);
+            g[1] = (float)((double)sa.y * 0x1p-32);
+            g[2] = (float)((double)sb.x * 0x1p-32);
+            g[3] = (float)((double)sb.y * 0x1p-32);
+            for (int32_t q = 0; q < plb.n_seg; ++q) {
+                const PlbSeg sg = plb.segs[q];
+                if (plb.row < sg.row_begin || plb.row > sg.row_end) continue;
+                const float4 u = *(const float4 *)(sg.q_row + m0), v = *(const float4 *)(sg.q_next + m0);
+                g[0] += u.x - v.x; g[1] += u.y - v.y; g[2] += u.z - v.z; g[3] += u.w - v.w;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const uint64_t m = (m0 + (uint64_t)e) & plb.mask;
+                g[e] = (float)((double)plb.S[m] * 0x1p-32);
+            }
+            for (int32_t q = 0; q < plb.n_seg; ++q) {
+                const PlbSeg sg = plb.segs[q];
+                if (plb.row < sg.row_begin || plb.row > sg.row_end) continue;
+#pragma unroll
+                for (int e = 0; e < PER; ++e) {
+                    const uint64_t m = (m0 + (uint64_t)e) & plb.mask;
+                    g[e] += sg.q_row[m] - sg.q_next[m];
+                }
+            }
+        }
+    }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = i0 + e;
         float y = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
         if (HYB && hyb.n_add > 0) y = g[e] + y;
+        if (PLB) y = g[e] + y;
         if (i < valid) {
             if (F32OUT) ((float *)out)[(size_t)i * ostride] = y;
             else ((int16_t *)out)[(size_t)i * ostride] = quantise(y);
@@ -537,6 +626,63 @@ __global__ __launch_bounds__(256) void direct_hybrid_kernel(const ToneDev *__res
     void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
     const HybridIn hyb{n_planes, planes + rel, plane_stride};
     synth_tile<S, F32OUT, false, true>(tones, blocks, tables, n0 + rel, valid, o, part, hyb);
+}
+
+// Periodic line-buffer path: tile order[b] of the range, the direct list's
+// tones on their own tiles, the line tones from S and the segments (PlbIn).
+template <int S, bool F32OUT>
+__global__ __launch_bounds__(256) void plb_kernel(const ToneDev *__restrict__ tones, const Block *__restrict__ blocks,
+                                                  const uint32_t *__restrict__ order,
+                                                  const uint64_t *const *__restrict__ tables, uint64_t n0,
+                                                  uint64_t count, void *__restrict__ out, const int64_t *__restrict__ S_sum,
+                                                  uint64_t mask, const PlbSeg *__restrict__ segs, int32_t n_seg)
+{
+    constexpr int T = kLanes * S;
+    __shared__ float part[kWaves][T];
+    const uint32_t row = order[blockIdx.x];
+    const uint64_t rel = (uint64_t)row * T;
+    const uint64_t left = count - rel;
+    const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
+    void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
+    const PlbIn plb{S_sum, mask, segs, n_seg, row};
+    synth_tile<S, F32OUT, false, true, true>(tones, blocks, tables, n0 + rel, valid, o, part,
+                                             HybridIn{0, nullptr, 0}, 1, plb);
+}
+
+// S[m] += sum over the folds f of fix(q_new_f[m]) - fix(q_old_f[m]) (q_old_f may
+// be null), fix(x) = x * 2^32 rounded to an integer: S stays the exact sum of
+// the fixed-point group sums it holds, whatever order groups come and go in.
+// Four samples per thread; L a multiple of 1024.
+__global__ __launch_bounds__(256) void plb_fold_kernel(int64_t *__restrict__ S_sum, uint64_t L,
+                                                       const PlbFold *__restrict__ folds, int32_t n_fold)
+{
+    const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= L) return;
+    int64_t acc[4] = {0, 0, 0, 0};
+    for (int32_t f = 0; f < n_fold; ++f) {
+        const PlbFold fd = folds[f];
+        const float4 a = *(const float4 *)(fd.q_new + i0);
+        acc[0] += (int64_t)__builtin_rint((double)a.x * 0x1p32);
+        acc[1] += (int64_t)__builtin_rint((double)a.y * 0x1p32);
+        acc[2] += (int64_t)__builtin_rint((double)a.z * 0x1p32);
+        acc[3] += (int64_t)__builtin_rint((double)a.w * 0x1p32);
+        if (fd.q_old) {
+            const float4 b = *(const float4 *)(fd.q_old + i0);
+            acc[0] -= (int64_t)__builtin_rint((double)b.x * 0x1p32);
+            acc[1] -= (int64_t)__builtin_rint((double)b.y * 0x1p32);
+            acc[2] -= (int64_t)__builtin_rint((double)b.z * 0x1p32);
+            acc[3] -= (int64_t)__builtin_rint((double)b.w * 0x1p32);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) S_sum[i0 + e] += acc[e];
+}
+
+// S[0 .. L) = 0 (a kernel, so the path records no memset).
+__global__ __launch_bounds__(256) void plb_zero_kernel(int64_t *__restrict__ S_sum, uint64_t L)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < L) S_sum[i] = 0;
 }
 
 // Batched synthesis of many plans' chunks in one launch (continuous batching).
@@ -701,6 +847,41 @@ hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const
     else
         prof.launch(direct_hybrid_kernel<kS, false>, dim3((uint32_t)tiles), dim3(256), 0, d_tones, d_blocks,
                     d_order, p->d_table_ptrs, n0, count, (void *)out_i16, planes, n_planes, plane_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const uint32_t *d_order,
+                      uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L, const PlbSeg *d_segs,
+                      int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s, double work)
+{
+    constexpr uint64_t T = kLanes * kS;
+    const uint64_t tiles = (count + T - 1) / T;
+    if (tiles == 0) return hipSuccess;
+    if (tiles > kMaxTilesPerLaunch || L < T || (L & (L - 1)) != 0) return hipErrorInvalidValue;
+    ProfScope prof(p->ctx, s, out_f32 ? "plb_kernel_f32" : "plb_kernel");
+    prof.add_work(work);
+    if (out_f32)
+        prof.launch(plb_kernel<kS, true>, dim3((uint32_t)tiles), dim3(256), 0, d_tones, d_blocks, d_order,
+                    p->d_table_ptrs, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg);
+    else
+        prof.launch(plb_kernel<kS, false>, dim3((uint32_t)tiles), dim3(256), 0, d_tones, d_blocks, d_order,
+                    p->d_table_ptrs, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_plb_fold(const awg_plan *p, int64_t *d_S, uint64_t L, const PlbFold *d_folds, int32_t n_fold,
+                           hipStream_t s)
+{
+    if (n_fold <= 0) return hipSuccess;
+    if (L < 1024 || (L & (L - 1)) != 0) return hipErrorInvalidValue;
+    ProfScope prof(p->ctx, s, "plb_fold_kernel");
+    prof.launch(plb_fold_kernel, dim3((uint32_t)(L / 1024)), dim3(256), 0, d_S, L, d_folds, n_fold);
+    return hipGetLastError();
+}
+
+hipError_t launch_plb_zero(int64_t *d_S, uint64_t L, hipStream_t s)
+{
+    hipLaunchKernelGGL(plb_zero_kernel, dim3((uint32_t)((L + 255) / 256)), dim3(256), 0, s, d_S, L);
     return hipGetLastError();
 }
 

@@ -84,6 +84,7 @@ struct HybridState {
 
 void hybrid_release(awg_plan *p)
 {
+    plb_release(p);
     HybridState *h = p->hyb;
     if (!h) return;
     for (auto &s : h->slots) {
@@ -102,8 +103,8 @@ void hybrid_release(awg_plan *p)
 size_t hybrid_bytes(const awg_plan *p)
 {
     const HybridState *h = p->hyb;
-    if (!h) return 0;
-    size_t b = h->work_cap;
+    if (!h) return plb_bytes_of(p);
+    size_t b = h->work_cap + plb_bytes_of(p);
     for (const auto &s : h->slots) b += s.dev_cap;
     return b;
 }
@@ -398,8 +399,9 @@ static awg_status piece(awg_plan *p, HybridState *h, uint32_t method, uint64_t n
     return hst(e);
 }
 
-awg_status hybrid_reserve(awg_plan *p, uint64_t max_count)
+awg_status hybrid_reserve(awg_plan *p, uint32_t method, uint64_t max_count)
 {
+    if (plb_eligible(p)) return plb_reserve(p, method);
     if (p->n_tones >= (int32_t)(1u << kLineShift)) return AWG_E_UNSUPPORTED;
     if (!p->hyb) {
         try { p->hyb = new HybridState(); } catch (...) { return AWG_E_NOMEM; }
@@ -421,6 +423,7 @@ awg_status hybrid_reserve(awg_plan *p, uint64_t max_count)
 awg_status hybrid_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,
                         float *out_f32, hipStream_t s)
 {
+    if (plb_eligible(p)) return plb_synth(p, method, n0, count, out_i16, out_f32, s);
     if (p->n_tones >= (int32_t)(1u << kLineShift)) return AWG_E_UNSUPPORTED;
     if (!p->hyb) {
         try { p->hyb = new HybridState(); } catch (...) { return AWG_E_NOMEM; }

@@ -225,12 +225,14 @@ constexpr int vmcnt_imm(int v) { return (v & 0xf) | ((v >> 4) << 14) | (0x7 << 4
 // flight while block kb is multiplied. vmcnt counts the copies in issue order.
 //
 // Split K: the grid's z index z sums k-blocks [z*kb_split, (z+1)*kb_split) and
-// writes its partial sums to plane z of the FP32 output (plane elements apart).
+// writes its partial sums to plane z of the FP32 output (plane elements apart),
+// or to plane plane_map[z] when a map is given (group products written straight
+// into their slots of a cache).
 template <typename T, bool F32OUT, int WR, int WC, int NST>
 __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
     const T *__restrict__ a_hi, const T *__restrict__ a_lo, const T *__restrict__ b_hi, const T *__restrict__ b_lo,
     int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split, uint64_t plane, uint64_t mcols, uint64_t count,
-    void *__restrict__ out)
+    void *__restrict__ out, const int32_t *__restrict__ plane_map)
 {
     typedef typename Split<T>::vec V;
     constexpr int W = WR * WC;
@@ -338,6 +340,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
     }
 
     // epilogue: reg v of lane l in tile (i, j) is row 8(v/4) + 4(l/32) + v%4, column l%32
+    const uint64_t pz = F32OUT && plane_map ? (uint64_t)plane_map[z] : (uint64_t)z;
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
 #pragma unroll
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
                 const uint64_t row = (uint64_t)(rb0 + TI * wr + i) * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const uint64_t rel = row * mcols + col;
                 if (rel < count) {
-                    if (F32OUT) ((float *)out)[z * plane + rel] = acc[i][j][v];
+                    if (F32OUT) ((float *)out)[pz * plane + rel] = acc[i][j][v];
                     else ((int16_t *)out)[rel] = to_i16(acc[i][j][v]);
                 }
             }
@@ -360,7 +363,8 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
 template <typename T, int WR, int WC, int NST>
 static hipError_t launch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T *a_lo, const T *b_hi,
                               const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
-                              uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32)
+                              uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32,
+                              const int32_t *plane_map)
 {
     constexpr int kLds = NST * 4 * kTileRB * kFragBytes;
     // the dynamic LDS limit is raised once per device (calls may come from
@@ -385,10 +389,11 @@ static hipError_t launch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T
     }
     if (out_f32)
         prof.launch(angle_gemm_kernel<T, true, WR, WC, NST>, grid, dim3(64 * WR * WC), (uint32_t)kLds, a_hi,
-                    a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_f32);
+                    a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_f32, plane_map);
     else
         prof.launch(angle_gemm_kernel<T, false, WR, WC, NST>, grid, dim3(64 * WR * WC), (uint32_t)kLds, a_hi,
-                    a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_i16);
+                    a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_i16,
+                    (const int32_t *)nullptr);
     return hipGetLastError();
 }
 
@@ -423,11 +428,12 @@ static void launch_gen_a(ProfScope &prof, const ToneDev *tones, const uint32_t *
 template <typename T>
 static hipError_t dispatch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T *a_lo, const T *b_hi,
                                 const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
-                                uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32)
+                                uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32,
+                                const int32_t *plane_map = nullptr)
 {
 #define AWG_GEMM(WR, WC, NST)                                                                                  \
     return launch_gemm<T, WR, WC, NST>(grid, prof, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, \
-                                       mcols, count, out_i16, out_f32)
+                                       mcols, count, out_i16, out_f32, plane_map)
     switch (gemm_variant()) {
     case 0: AWG_GEMM(2, 2, 2);
     case 1: AWG_GEMM(2, 2, 3);
@@ -662,6 +668,79 @@ hipError_t launch_lines(const awg_plan *p, uint32_t method, const LinesGeom &g, 
     if (method == AWG_F_METHOD_MFMA_BF16X3)
         return lines_run<__bf16>(p, g, d_entries, n_entries, d_blocks, n_blocks, n0, count, (char *)d_work, s,
                                  work);
+    return hipErrorInvalidValue;
+}
+
+// Period sums of tone groups (the periodic line-buffer path): rows of 1024
+// samples from 0 over one period L, k-blocks of 8 tones, group z = k-blocks
+// [z * kpg, (z + 1) * kpg) summed by split-K slice z into plane plane_map[z].
+struct GroupGeom {
+    int32_t rb_pad, cb_n, kb_n, kpg;
+    size_t a_bytes, b_bytes;
+};
+
+static GroupGeom group_geometry(int32_t n_built, int32_t group_tones, uint64_t L)
+{
+    GroupGeom g;
+    const uint64_t rows = L / kTileSamples;
+    g.rb_pad = (int32_t)(((rows + 31) / 32 + kTileRB - 1) / kTileRB * kTileRB);
+    g.cb_n = (int32_t)(kTileSamples / 32);
+    g.kpg = group_tones / 8;
+    g.kb_n = n_built * g.kpg;
+    g.a_bytes = (size_t)g.kb_n * g.rb_pad * kFragBytes;
+    g.b_bytes = (size_t)g.kb_n * g.cb_n * kFragBytes;
+    return g;
+}
+
+size_t group_work_bytes(int32_t n_built, int32_t group_tones, uint64_t L)
+{
+    const GroupGeom g = group_geometry(n_built, group_tones, L);
+    return 2 * (g.a_bytes + g.b_bytes);
+}
+
+template <typename T>
+static hipError_t group_run(const awg_plan *p, const ToneDev *d_list, int32_t n_built, int32_t group_tones,
+                            uint64_t L, char *w, float *q_base, const int32_t *d_plane_map, hipStream_t s,
+                            double work)
+{
+    const bool f16 = std::is_same<T, _Float16>::value;
+    const GroupGeom g = group_geometry(n_built, group_tones, L);
+    T *b_hi = (T *)w, *b_lo = (T *)(w + g.b_bytes);
+    T *a_hi = (T *)(w + 2 * g.b_bytes), *a_lo = (T *)(w + 2 * g.b_bytes + g.a_bytes);
+    const int32_t n_entries = n_built * group_tones;
+    hipError_t e;
+    {
+        ProfScope prof(p->ctx, s, f16 ? "plb_gen_a_f16" : "plb_gen_a_bf16");
+        launch_gen_a<T>(prof, d_list, nullptr, n_entries, 2 * g.kb_n, 0, kTileSamples, g.rb_pad, a_hi, a_lo);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    {
+        const int64_t b_threads = (int64_t)g.cb_n * 32 * (2 * g.kb_n);
+        ProfScope prof(p->ctx, s, f16 ? "plb_gen_b_f16" : "plb_gen_b_bf16");
+        prof.launch(gen_b_kernel<T>, dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, d_list,
+                    (const uint32_t *)nullptr, n_entries, 2 * g.kb_n, g.cb_n, b_hi, b_lo, (const int32_t *)nullptr);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    dim3 grid((uint32_t)(g.cb_n / kTileCB), (uint32_t)(g.rb_pad / kTileRB), (uint32_t)n_built);
+    ProfScope prof(p->ctx, s, f16 ? "plb_gemm_f16" : "plb_gemm_bf16");
+    prof.add_work(work);
+    return dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, g.kb_n, g.rb_pad, g.cb_n, g.kpg, L, kTileSamples, L,
+                            nullptr, q_base, d_plane_map);
+}
+
+hipError_t launch_group_sums(const awg_plan *p, uint32_t method, const ToneDev *d_list, int32_t n_built,
+                             int32_t group_tones, uint64_t L, void *d_work, float *q_base,
+                             const int32_t *d_plane_map, hipStream_t s, double work)
+{
+    if (n_built <= 0) return hipSuccess;
+    if (group_tones % 8 != 0 || L < kTileSamples || L % kTileSamples != 0 || n_built > 65535)
+        return hipErrorInvalidValue;
+    if (method == AWG_F_METHOD_MFMA_F16X3)
+        return group_run<_Float16>(p, d_list, n_built, group_tones, L, (char *)d_work, q_base, d_plane_map, s, work);
+    if (method == AWG_F_METHOD_MFMA_BF16X3)
+        return group_run<__bf16>(p, d_list, n_built, group_tones, L, (char *)d_work, q_base, d_plane_map, s, work);
     return hipErrorInvalidValue;
 }
 

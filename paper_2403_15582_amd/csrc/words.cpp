@@ -48,6 +48,23 @@ bool rne_ratio_shift(double num, double den, int shift, uint64_t *out)
     return true;
 }
 
+// Frequency word of f at fs (Eq. (4) when period_log2 > 0).
+awg_status freq_word(double f, double fs, uint32_t p, uint64_t *out)
+{
+    if (!std::isfinite(f) || !(f > 0.0) || !(f < fs * 0.5)) return AWG_E_INVALID;
+    uint64_t w;
+    if (p > 0) {
+        if (!rne_ratio_shift(f, fs, (int)p, &w)) return AWG_E_RANGE;
+        if (w < 1 || w >= (1ull << (p - 1))) return AWG_E_RANGE;
+        *out = w << (64 - p);
+        return AWG_OK;
+    }
+    if (!rne_ratio_shift(f, fs, 64, &w)) return AWG_E_RANGE;
+    if (w < 1 || w >= (1ull << 63)) return AWG_E_RANGE;
+    *out = w;
+    return AWG_OK;
+}
+
 // nint(turns * 2^64) mod 2^64 for any finite double.
 uint64_t phase_word(double turns)
 {

@@ -43,21 +43,50 @@ def test_peak_matches_oracle(n0, count):
     assert abs(got - float(np.max(np.abs(y)))) < 0.25, (got, np.max(np.abs(y)))
 
 
-def test_crest_factor_aware_phase_choice():
-    """200 tones: each closed form's crest factor measured on the GPU over one period
-    equals the oracle's; the planner returns the phases of the lowest one."""
+def _oracle_crest(t, turns, p2):
+    tt = t.copy()
+    tt["phase_turns"] = turns
+    op = words.Plan(FS, 0.0, p2, tt)
+    _, y = csynth.synth(op, 0, 1 << p2)
+    return PH.crest_factor(y, tt["amplitude"], op.gain)
+
+
+def test_closed_form_choice_on_the_device():
+    """max_evals = 0: the two closed forms are measured over one period on the
+    device and the better one is returned, with a crest factor equal to the
+    oracle's for those phases."""
     need_gpu()
+    ctx = awg.context(0)
     for equal in (True, False):
         t = _bin_tones(200, 16, 4, equal=equal)
-        ph, crest = awg.plan_phases(t, FS, 0.0, 16)
-        say("crest factors (equal=%s): %s" % (equal, {k: round(v, 4) for k, v in crest.items()}))
-        best = min(crest, key=crest.get)
-        assert np.array_equal(ph, awg.awg_phase_plan(best, t["f_start_hz"], t["amplitude"]))
-        for m, cf in crest.items():
-            tt = t.copy()
-            tt["phase_turns"] = PH.phase_plan(m, t["f_start_hz"], t["amplitude"])
-            op = words.Plan(FS, 0.0, 16, tt)
-            _, y = csynth.synth(op, 0, 1 << 16)
-            want = PH.crest_factor(y, tt["amplitude"], op.gain)
-            assert abs(cf - want) < 1e-4 * want, (m, cf, want)
-            assert cf < 0.25 * math.sqrt(2 * 200)          # far below aligned phases
+        ph, cf, m = awg.awg_phase_search(ctx, FS, 16, t["f_start_hz"], t["amplitude"], max_evals=0)
+        say("closed forms (equal=%s): method %d crest %.4f" % (equal, m, cf))
+        assert m in (awg.AWG_PHASES_SCHROEDER, awg.AWG_PHASES_NEWMAN)
+        assert np.array_equal(ph, awg.awg_phase_plan(m, t["f_start_hz"], t["amplitude"]))
+        want = {k: _oracle_crest(t, PH.phase_plan(k, t["f_start_hz"], t["amplitude"]), 16)
+                for k in (PH.SCHROEDER, PH.NEWMAN)}
+        assert abs(cf - want[m]) < 1e-4 * want[m], (cf, want)
+        assert want[m] <= min(want.values()) * (1 + 1e-4)
+        assert cf < 0.25 * math.sqrt(2 * 200)          # far below aligned phases
+
+
+def test_search_on_irregular_bins_of_the_static_buffer():
+    """The 1000 irregular bins of the 2^24-sample static buffer: the closed forms
+    stay near the random-phase level (about 4.35); the l_p search brings the
+    crest factor clearly below it, and the crest factor it reports equals the
+    oracle's over the whole period for the returned phases."""
+    from paper_2403_15582_amd import workloads as W
+    need_gpu()
+    w = W.static_period()
+    ctx = awg.context(0)
+    _, cf0, m0 = awg.awg_phase_search(ctx, w.fs_hz, w.period_log2, w.tones["f_start_hz"], w.tones["amplitude"],
+                                      max_evals=0)
+    say("static period closed forms: method %d crest %.4f" % (m0, cf0))
+    ph, cf, m = awg.awg_phase_search(ctx, w.fs_hz, w.period_log2, w.tones["f_start_hz"], w.tones["amplitude"],
+                                     max_evals=300)
+    say("static period l_p search: method %d crest %.4f" % (m, cf))
+    assert m == awg.AWG_PHASES_SEARCH and cf < 0.85 * cf0, (cf, cf0)
+    assert np.all((ph >= 0.0) & (ph < 1.0))
+    want = _oracle_crest(w.tones, ph, w.period_log2)
+    say("oracle crest factor of the returned phases over 2^24 samples: %.5f" % want)
+    assert abs(cf - want) < 1e-4 * want, (cf, want)
