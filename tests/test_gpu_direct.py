@@ -41,9 +41,14 @@ def test_phase_words_bit_exact_small_mixed():
 
 
 def test_phase_words_bit_exact_long_ramps():
+    """35 ms ramps of every shape, with bin frequencies (dF a multiple of 2^16)
+    and with free ones (any dF: the smooth loops carry the fraction of r H)."""
     torch = need_gpu()
-    for shape in ("linear", "cosine", "minjerk"):
+    for shape, free in [(s, f) for s in ("linear", "cosine", "minjerk") for f in (False, True)]:
         w = W.chirp_35ms(shape=shape, K=8)
+        if free:
+            w.period_log2 = 0
+            shape += "-free"
         op = oracle_plan(w, tables=False)
         lp = lib_plan(w)
         N = W.RAMP_35MS
@@ -180,10 +185,14 @@ def test_static_period_full_direct_sampled_and_periodic():
     compare(q[ns], y[ns], qo, yo, "static-period direct (sampled %d)" % len(ns))
 
 
-@pytest.mark.parametrize("shape", ["linear", "cosine", "minjerk", "mixed"])
+@pytest.mark.parametrize("shape", ["linear", "cosine", "minjerk", "mixed", "cosine-free", "mixed-free"])
 def test_chirp_35ms_streamed_equals_oneshot_and_oracle(shape):
+    """Config 3: 1000 tones chirped over 35 ms, streamed in 10 chunks of 2^20;
+    "-free": frequencies not snapped to bins (any dF), as the config states them."""
     torch = need_gpu()
-    w = W.chirp_35ms(shape=shape)
+    w = W.chirp_35ms(shape=shape.split("-")[0])
+    if shape.endswith("-free"):
+        w.period_log2 = 0
     lp = lib_plan(w)
     say("chirp-35ms/%s streamed 10 x 2^20 x 1000" % shape)
     chunks = []
