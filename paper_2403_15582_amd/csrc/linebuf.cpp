@@ -20,16 +20,16 @@
 // Each call over [n0, n0 + count) in rows of 1024 samples is evaluated from
 // the call alone (the plan's state and the range), so equal calls give equal
 // samples whatever the plan computed before:
-//  * a tone's "next" line is the one it is on at the call's last sample (the
-//    line before its windows if that sample is still inside them); each group's
-//    version of next lines is folded into S before the call is summed;
+//  * a tone's "next" line is the one it is on at the call's last sample (none,
+//    i.e. zero amplitude, if that sample is still inside its windows); each
+//    group's version of next lines is folded into S before the call is summed;
 //  * rows before a tone's windows, where it is still on its line before them
 //    while its next line is the one after, hold a different version of the
 //    group: for those rows the call adds Q(row version) - Q(next version)
 //    ("segments");
 //  * on the rows its windows meet, a tone runs on the direct kernel with its
-//    exact chirp phase, together with a copy of its next line at minus its
-//    amplitude (the line S and the segments count for it there).
+//    exact chirp phase, together with a copy of its next line, if it has one,
+//    at minus its amplitude (the line S and the segments count for it there).
 // The direct kernel adds, per tile, S, the segments and its own sum, and rounds.
 #include <algorithm>
 #include <cstring>
@@ -73,6 +73,12 @@ struct Line {
     bool operator==(const Line &o) const { return p == o.p && f == o.f && fbits(a) == fbits(o.a); }
     bool operator!=(const Line &o) const { return !(*this == o); }
 };
+
+// A line with zero amplitude contributes nothing, whatever its words: all such
+// lines are one line, kNoLine, so that versions differing only there are equal.
+constexpr Line kNoLine{0, 0, 0.0f};
+
+Line line_of(uint64_t p, uint64_t f, float a) { return a == 0.0f ? kNoLine : Line{p, f, a}; }
 
 uint64_t mix(uint64_t h, uint64_t v)
 {
@@ -266,15 +272,16 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
     return AWG_OK;
 }
 
-// Launch order of the tiles, costliest first: a window tile costs 2 (the tone
-// and its negative line), a tile where a window opens or closes 3.5 more.
+// Launch order of the tiles, costliest first: a window tile costs 1 per tone
+// (2 with its negative line), a tile where a window opens or closes 3.5 more.
 void tile_order(LineBuf &b, uint64_t n0, uint64_t rows)
 {
     b.cost.assign(rows + 1, 0.0f);
     for (int32_t k = 0; k < b.K; ++k) {
         if (b.wr_lo[k] > b.wr_hi[k]) continue;
-        b.cost[b.wr_lo[k]] += 2.0f;
-        b.cost[b.wr_hi[k] + 1] -= 2.0f;
+        const float c = b.next[k] != kNoLine ? 2.0f : 1.0f;
+        b.cost[b.wr_lo[k]] += c;
+        b.cost[b.wr_hi[k] + 1] -= c;
     }
     float run = 0.0f;
     for (uint64_t r = 0; r < rows; ++r) {
@@ -295,7 +302,12 @@ void tile_order(LineBuf &b, uint64_t n0, uint64_t rows)
 void sort_direct(std::vector<ToneDev> *v)
 {
     std::stable_sort(v->begin(), v->end(), [](const ToneDev &a, const ToneDev &b) {
-        if (a.shape != b.shape) return a.shape > b.shape;            // ramped tones first, lines last
+        // ramped tones first, in the plan's device order (shape, window, table),
+        // so that a call whose tones all ramp sums them as the direct kernel
+        // does; lines last
+        const bool la = a.shape == AWG_RAMP_NONE, lb = b.shape == AWG_RAMP_NONE;
+        if (la != lb) return lb;
+        if (a.shape != b.shape) return a.shape < b.shape;
         if (a.a != b.a) return a.a < b.a;
         if (a.n != b.n) return a.n < b.n;
         if (a.table != b.table) return a.table < b.table;
@@ -333,27 +345,33 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     double direct_work = 0.0;
     for (int32_t k = 0; k < K; ++k) {
         const ToneDev &t = p->dev_mirror[p->inv[k]];
-        b.l1[k] = Line{t.p0 - kPhaseBias, t.f0, t.amp};
-        b.l2[k] = Line{t.p1 - kPhaseBias, t.f1, t.amp1};
+        b.l1[k] = line_of(t.p0 - kPhaseBias, t.f0, t.amp);
+        b.l2[k] = line_of(t.p1 - kPhaseBias, t.f1, t.amp1);
         const bool windowed = t.lo <= t.hi;
-        b.next[k] = windowed && last > t.hi ? b.l2[k] : b.l1[k];
+        // still inside its windows at the call's last sample: on no line (the
+        // direct kernel takes it on every row its windows meet)
+        b.next[k] = !windowed || last < t.lo ? b.l1[k] : (last > t.hi ? b.l2[k] : kNoLine);
         if (windowed && t.hi >= n0 && t.lo <= last) {
             const uint64_t lo = t.lo <= n0 ? 0 : (t.lo - n0) / kRow;
             const uint64_t hi = std::min<uint64_t>(rows - 1, (t.hi - n0) / kRow);
             b.wr_lo[k] = (int32_t)lo;
             b.wr_hi[k] = (int32_t)hi;
-            if (last > t.hi && lo > 0 && b.l1[k] != b.l2[k]) b.sw[k] = (uint32_t)lo;
-            // the tone on its window rows, and its next line with the opposite sign
+            if (lo > 0 && b.l1[k] != b.next[k]) b.sw[k] = (uint32_t)lo;
+            // the tone on its window rows, and its next line (if any) with the
+            // opposite sign
             ToneDev d = t;
             d.lo = n0 + lo * kRow;
             d.hi = n0 + hi * kRow + (kRow - 1);
             b.direct.push_back(d);
-            ToneDev neg = line_record(b.next[k], -1.0f);
-            neg.lo = d.lo;
-            neg.hi = d.hi;
-            b.direct.push_back(neg);
             const double n_samp = (double)(std::min(d.hi, last) - d.lo + 1);
-            direct_work += 2.0 * n_samp;
+            direct_work += n_samp;
+            if (b.next[k] != kNoLine) {
+                ToneDev neg = line_record(b.next[k], -1.0f);
+                neg.lo = d.lo;
+                neg.hi = d.hi;
+                b.direct.push_back(neg);
+                direct_work += n_samp;
+            }
         }
     }
     // segments of the pass: one per distinct switch row of each group (counted

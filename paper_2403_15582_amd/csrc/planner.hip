@@ -411,7 +411,7 @@ extern "C" awg_status awg_phase_search(awg_ctx *ctx, double fs_hz, uint32_t peri
         std::vector<double> turns(n_tones), theta(n_tones);
         int32_t best_method = 0;
         double best_cf = INFINITY;
-        std::vector<double> best_theta;
+        std::vector<double> best_theta, best_turns;
         for (int32_t m : {AWG_PHASES_SCHROEDER, AWG_PHASES_NEWMAN}) {
             st = awg_phase_plan(m, f_hz, amplitude, n_tones, turns.data());
             if (st != AWG_OK) return st;
@@ -424,6 +424,7 @@ extern "C" awg_status awg_phase_search(awg_ctx *ctx, double fs_hz, uint32_t peri
                 best_cf = cf;
                 best_method = m;
                 best_theta = theta;
+                best_turns = turns;            // returned as the closed form gives them
             }
         }
         if (max_evals > 0) {
@@ -448,6 +449,10 @@ extern "C" awg_status awg_phase_search(awg_ctx *ctx, double fs_hz, uint32_t peri
             }
         }
         for (int32_t k = 0; k < n_tones; ++k) {
+            if (best_method != AWG_PHASES_SEARCH) {
+                phase_turns_out[k] = best_turns[k];
+                continue;
+            }
             double t = best_theta[k] / kTwoPi;
             t -= std::floor(t);
             if (t >= 1.0) t -= 1.0;
