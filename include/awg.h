@@ -340,6 +340,20 @@ awg_status awg_phase_search(awg_ctx *ctx, double fs_hz, uint32_t period_log2, co
 awg_status awg_peak(awg_plan *plan, uint64_t n0, uint64_t count, float *d_scratch, float *d_peak,
                     void *hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): awg_peak without the caller's
+ * scratch. The FP32 samples go to a scratch array the library keeps in device
+ * memory, one per device (AWG_PEAK_NOALLOC_MAX floats = 16 MiB, held until the
+ * process ends; its address is looked up when a context is created). The call
+ * enqueues the same kernels as awg_peak, so *d_peak is bit-identical to it, and
+ * it calls no allocating routine: no hipMalloc/hipFree, no profiler events
+ * (its launches are never timed by awg_profile_*). Calls on one device share
+ * that array and each overwrites it, so calls that may overlap on one device
+ * (two streams, two threads) race: serialise them. AWG_E_UNSUPPORTED for
+ * count > AWG_PEAK_NOALLOC_MAX; otherwise errors as awg_peak. */
+#define AWG_PEAK_NOALLOC_MAX (1u << 22)
+awg_status awg_peak_noalloc(awg_plan *plan, uint64_t n0, uint64_t count, float *d_peak, void *hip_stream);
+
 
 /* Phase words of one tone as the direct kernel generates them (same code path,
  * same sample-to-lane mapping), for exact comparison: d_words[i] = phi(n0 + i). */

@@ -32,7 +32,7 @@ EXPORTED = [
     "awg_plan_reserve",
     "awg_synth_static", "awg_synth_chirp", "awg_stream_next", "awg_stream_seek",
     "awg_stream_tell", "awg_synth_f32", "awg_synth_multiplex", "awg_stream_next_multiplex",
-    "awg_phase_dump", "awg_phase_plan", "awg_phase_search", "awg_peak", "awg_strerror",
+    "awg_phase_dump", "awg_phase_plan", "awg_phase_search", "awg_peak", "awg_peak_noalloc", "awg_strerror",
     "awg_version",
     "awg_profile_enable", "awg_profile_read",
     "awg_server_create", "awg_server_destroy", "awg_server_submit", "awg_server_poll",
@@ -172,6 +172,7 @@ def lib():
         "awg_phase_search": ([_VP, ctypes.c_double, ctypes.c_uint32, _VP, _VP, _I32, _I32, _VP,
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)], _I32),
         "awg_peak": ([_VP, _U64, _U64, _VP, _VP, _VP], _I32),
+        "awg_peak_noalloc": ([_VP, _U64, _U64, _VP, _VP], _I32),
         "awg_profile_enable": ([_VP, _I32], _I32),
         "awg_profile_read": ([_VP, ctypes.POINTER(awg_kernel_stat), _I32, ctypes.POINTER(_I32), _I32], _I32),
         "awg_server_create": ([_VP, ctypes.POINTER(awg_server_params), ctypes.POINTER(_VP)], _I32),
@@ -371,6 +372,13 @@ def awg_phase_plan(method, f_hz, amplitude=None):
 
 def awg_peak(plan, n0, count, d_scratch, d_peak, stream=0):
     _check(lib().awg_peak(plan, int(n0), int(count), d_scratch, d_peak, stream or None), "awg_peak")
+
+
+AWG_PEAK_NOALLOC_MAX = 1 << 22
+
+
+def awg_peak_noalloc(plan, n0, count, d_peak, stream=0):
+    _check(lib().awg_peak_noalloc(plan, int(n0), int(count), d_peak, stream or None), "awg_peak_noalloc")
 
 
 

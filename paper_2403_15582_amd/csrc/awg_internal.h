@@ -140,6 +140,9 @@ struct awg_ctx {
     std::map<std::string, awg::ProfTotal> prof_totals;
     // smooth-ramp tables shared by all plans of the context, keyed by (shape, N)
     std::map<std::pair<int32_t, uint64_t>, awg::Table> tables;
+    // device address of this device's copy of the allocation-free peak call's
+    // scratch array (looked up once per device when a context is created)
+    float *noalloc_scratch = nullptr;
 };
 
 struct awg_plan {
@@ -233,7 +236,7 @@ private:
 hipError_t launch_direct_i16(const awg_plan *p, uint64_t n0, uint64_t count, int16_t *out,
                              hipStream_t s);
 hipError_t launch_direct_f32(const awg_plan *p, uint64_t n0, uint64_t count, float *out,
-                             hipStream_t s);
+                             hipStream_t s, bool timed = true);
 hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint64_t count,
                              uint64_t *out, hipStream_t s);
 // One changed tone for the scatter kernel: its device position and record.
@@ -241,6 +244,10 @@ struct ScatterRecord { uint32_t index; uint32_t pad; ToneDev tone; };
 hipError_t launch_scatter_tones(ToneDev *d_tones, const void *d_records, int32_t n,
                                 hipStream_t s);
 hipError_t launch_peak(const float *d_y, uint64_t count, float *d_peak, hipStream_t s);
+// Device address of the current device's copy of the allocation-free peak
+// call's scratch array (AWG_PEAK_NOALLOC_MAX floats), looked up on the first
+// call for a device (which must be current) and remembered per device.
+hipError_t noalloc_scratch(int device, float **ptr);
 // Copy `bytes` from pinned host memory (src: its device-mapped address, from a
 // coherent hipHostMalloc allocation) to device memory dst, by a kernel on s: the
 // copy stays on the compute queue in stream order, with no hand-off to a DMA

@@ -252,6 +252,13 @@ awg_status awg_ctx_create(int device, awg_ctx **out)
     awg_ctx *c = new (std::nothrow) awg_ctx();
     if (!c) return AWG_E_NOMEM;
     c->device = device;
+    // once per device, with the device current: the address of its copy of the
+    // allocation-free peak call's scratch array
+    if (noalloc_scratch(device, &c->noalloc_scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return AWG_E_HIP;
+    }
     *out = c;
     return AWG_OK;
 }
@@ -763,6 +770,22 @@ awg_status awg_peak(awg_plan *p, uint64_t n0, uint64_t count, float *d_scratch, 
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = launch_direct_f32(p, n0, count, d_scratch, s);
     if (e == hipSuccess) e = launch_peak(d_scratch, count, d_peak, s);
+    return hip_status(e);
+}
+
+awg_status awg_peak_noalloc(awg_plan *p, uint64_t n0, uint64_t count, float *d_peak, void *hip_stream)
+{
+    awg_status st = device_ready(p);
+    if (st != AWG_OK) return st;
+    if (!d_peak || count == 0) return AWG_E_INVALID;
+    if (count > AWG_PEAK_NOALLOC_MAX) return AWG_E_UNSUPPORTED;
+    if ((st = check_range(n0, count)) != AWG_OK) return st;
+    if ((st = check_out(p, d_peak, 1, sizeof(float))) != AWG_OK) return st;
+    float *scr = p->ctx->noalloc_scratch;      // this device's copy, never the symbol itself
+    if (!scr) return AWG_E_HIP;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = launch_direct_f32(p, n0, count, scr, s, false);
+    if (e == hipSuccess) e = launch_peak(scr, count, d_peak, s);
     return hip_status(e);
 }
 

@@ -19,6 +19,8 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "awg_internal.h"
 #include "prof_launch.h"
@@ -769,7 +771,8 @@ constexpr uint64_t kMaxTilesPerLaunch = 1u << 30;
 static_assert(kLanes * kS == kTileSamples, "tile size");
 
 template <bool F32OUT>
-static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, void *out, hipStream_t s)
+static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, void *out, hipStream_t s,
+                                bool timed = true)
 {
     constexpr uint64_t T = kLanes * kS;
     const uint64_t esz = F32OUT ? 4 : 2;
@@ -779,7 +782,8 @@ static hipError_t launch_direct(const awg_plan *p, uint64_t n0, uint64_t count, 
         const uint64_t now = now_tiles * T < count ? now_tiles * T : count;
         hipError_t e;
         {
-            ProfScope prof(p->ctx, s, F32OUT ? "direct_kernel_f32" : "direct_kernel");
+            // untimed launches take no profiler events (the allocation-free call)
+            ProfScope prof(timed ? p->ctx : nullptr, s, F32OUT ? "direct_kernel_f32" : "direct_kernel");
             prof.add_work((double)p->n_tones * (double)now);
             if (p->n_ramped == 0)
                 prof.launch(direct_kernel<kS, F32OUT, true>, dim3((uint32_t)now_tiles), dim3(256), 0, p->d_tones,
@@ -802,9 +806,9 @@ hipError_t launch_direct_i16(const awg_plan *p, uint64_t n0, uint64_t count, int
     return launch_direct<false>(p, n0, count, out, s);
 }
 
-hipError_t launch_direct_f32(const awg_plan *p, uint64_t n0, uint64_t count, float *out, hipStream_t s)
+hipError_t launch_direct_f32(const awg_plan *p, uint64_t n0, uint64_t count, float *out, hipStream_t s, bool timed)
 {
-    return launch_direct<true>(p, n0, count, out, s);
+    return launch_direct<true>(p, n0, count, out, s, timed);
 }
 
 hipError_t launch_phase_dump(const awg_plan *p, int32_t tone, uint64_t n0, uint64_t count,
@@ -906,6 +910,32 @@ __global__ __launch_bounds__(256) void peak_kernel(const float *__restrict__ y, 
 }
 
 __global__ void zero_word_kernel(unsigned int *w) { *w = 0u; }
+
+// Scratch of awg_peak_noalloc: the FP32 samples of one request. A file-scope
+// device array, so that the call allocates nothing; every device the library
+// runs on holds its own copy until the process ends. Host code never passes
+// the array's name to a kernel (on the host it only stands for the symbol):
+// it uses the device address noalloc_scratch looked up for the device.
+static __device__ __align__(256) float scratch[AWG_PEAK_NOALLOC_MAX];
+
+hipError_t noalloc_scratch(int device, float **ptr)
+{
+    static std::mutex mu;
+    static std::map<int, float *> addr;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    void *a = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!a) return hipErrorInvalidSymbol;
+    addr[device] = (float *)a;
+    *ptr = (float *)a;
+    return hipSuccess;
+}
 
 hipError_t launch_peak(const float *d_y, uint64_t count, float *d_peak, hipStream_t s)
 {
