@@ -158,6 +158,8 @@ struct awg_plan {
     std::vector<const uint64_t *> table_ptrs;   // device pointers, indexed by ToneDev::table
     std::map<std::pair<int32_t, uint64_t>, uint16_t> table_index;
     std::vector<awg::Block> blocks;    // block table of dev_mirror (header first)
+    bool blocks_stale = false;         // a retune changed dev_mirror: blocks and d_blocks are rebuilt
+                                       // by the next call that reads them (sync_blocks)
     awg::Block *d_blocks;              // device copy, room for n_tones + 1 entries
     awg::ToneDev *d_tones;             // device copy of dev_mirror
     const uint64_t **d_table_ptrs;     // device copy of table_ptrs
@@ -202,6 +204,57 @@ uint64_t chirp_end_term(int32_t shape, int64_t coef, int64_t dF, uint64_t n);
 ToneDev to_device(const ToneHost &t, uint16_t table);
 // Block table of a tone list (see Block). Tones [0, n_split) are marked split
 // (hybrid path) and no block spans position n_split. At most n + 1 entries.
+// build_blocks_by reads tone i of an n-tone list through tone(i).
+template <class Get>
+void build_blocks_by(int32_t n, int32_t n_split, Get &&tone, std::vector<Block> *out)
+{
+    constexpr int32_t kMinRun = 8;
+    out->clear();
+    out->push_back(Block{0, 0, 0});
+    auto same = [&](int32_t x, int32_t y) {
+        const ToneDev &a = tone(x), &b = tone(y);
+        return a.shape == b.shape && a.a == b.a && a.n == b.n && a.table == b.table && a.ashape == b.ashape &&
+               a.b == b.b && a.m == b.m && ((x < n_split) == (y < n_split));
+    };
+    int32_t mixed_begin = -1, mixed_count = 0;
+    uint16_t mixed_flags = 0;
+    auto flush = [&]() {
+        if (mixed_count > 0) out->push_back(Block{(uint32_t)mixed_begin, (uint16_t)mixed_count, mixed_flags});
+        mixed_begin = -1;
+        mixed_count = 0;
+    };
+    for (int32_t i = 0; i < n;) {
+        int32_t j = i + 1;
+        while (j < n && same(i, j)) ++j;
+        const int32_t L = j - i;
+        const uint16_t flags = (i < n_split ? kBlockSplit : 0) | (tone(i).ashape != AWG_RAMP_NONE ? kBlockAmp : 0);
+        if (L >= kMinRun) {
+            flush();
+            int32_t nb = (L + kBlock - 1) / kBlock;
+            nb = (nb + kWaves - 1) / kWaves * kWaves;
+            const int32_t base = L / nb, extra = L % nb;
+            int32_t b = i;
+            const bool smooth = tone(i).shape == AWG_RAMP_COSINE || tone(i).shape == AWG_RAMP_MINJERK;
+            for (int32_t q = 0; q < nb; ++q) {
+                const int32_t c = base + (q < extra ? 1 : 0);
+                bool step16 = smooth;
+                for (int32_t k = b; step16 && k < b + c; ++k) step16 = (tone(k).coef & 0xffff) == 0;
+                out->push_back(Block{(uint32_t)b, (uint16_t)c,
+                                     (uint16_t)(kBlockUniform | flags | (step16 ? kBlockStep16 : 0))});
+                b += c;
+            }
+        } else {
+            for (int32_t k = i; k < j; ++k) {
+                if (mixed_count > 0 && (mixed_count == kBlock || mixed_flags != flags)) flush();
+                if (mixed_count == 0) { mixed_begin = k; mixed_flags = flags; }
+                ++mixed_count;
+            }
+        }
+        i = j;
+    }
+    flush();
+    (*out)[0].begin = (uint32_t)(out->size() - 1);
+}
 void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vector<Block> *out);
 
 // Device table H_N of a smooth shape, created once per context (capi.cpp).
@@ -273,6 +326,25 @@ struct PlbFold {
     const float *q_new;
     const float *q_old;
 };
+// An entry of the line-buffer path's staged tone lists, made into a ToneDev
+// record on the device by launch_plb_stage: a plan tone's record (src >= 0:
+// its device position) or a line (src < 0: words p, f without the device bias,
+// signed amplitude a), summed on the rows [lo_row, hi_row] of the pass
+// (lo_row < 0: no window, lo = 1 > hi = 0).
+struct PlbDesc {
+    uint64_t p, f;
+    float a;
+    int32_t src;
+    int32_t lo_row, hi_row;
+};
+static_assert(sizeof(PlbDesc) == 32, "PlbDesc must be 32 bytes");
+// One launch: the records of desc[0 .. n_first) to dst_first and of
+// desc[n_first .. n_desc) to dst_rest (window rows start at n0), and a plain
+// copy of raw_bytes (a multiple of 16) from raw_src (pinned, mapped) to raw_dst,
+// both 16-byte aligned.
+hipError_t launch_plb_stage(const PlbDesc *desc, int32_t n_first, int32_t n_desc, const ToneDev *plan_tones,
+                            uint64_t n0, ToneDev *dst_first, ToneDev *dst_rest, const void *raw_src, void *raw_dst,
+                            size_t raw_bytes, hipStream_t s);
 hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const uint32_t *d_order,
                       uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L, const PlbSeg *d_segs,
                       int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s, double work);

@@ -583,8 +583,13 @@ static awg_status ensure_retune_slots(awg_plan *p)
 
 static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, hipStream_t s)
 {
-    build_blocks(p->dev_mirror, -1, &p->blocks);
-    if (!p->ctx) return AWG_OK;
+    if (!p->ctx) {
+        build_blocks(p->dev_mirror, -1, &p->blocks);
+        return AWG_OK;
+    }
+    // the block table is rebuilt by the next call that reads it: the line-buffer
+    // path (a stream of retunes and chunks) never does
+    p->blocks_stale = true;
     // stage the new records and scatter them on the stream
     hipError_t e = hipSetDevice(p->ctx->device);
     if (e != hipSuccess) return hip_status(e);
@@ -604,13 +609,32 @@ static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, 
         rec[i].tone = p->dev_mirror[p->inv[changed[i]]];
     }
     e = launch_scatter_tones(p->d_tones, slot.mapped, n_ev, s);
-    // the block table follows the records in the same pinned slot
+    if (e == hipSuccess) e = hipEventRecord(slot.done, s);
+    slot.used = true;
+    return hip_status(e);
+}
+
+// The plan's block table for its current tones, on the device in stream order
+// before the caller's kernels (after retunes it is rebuilt here, staged in a
+// retune slot and moved by the copy kernel).
+static awg_status sync_blocks(awg_plan *p, hipStream_t s)
+{
+    if (!p->blocks_stale) return AWG_OK;
+    build_blocks(p->dev_mirror, -1, &p->blocks);
+    awg_status st = ensure_retune_slots(p);
+    if (st != AWG_OK) return st;
+    const size_t si = p->next_slot;
+    p->next_slot = (p->next_slot + 1) % kSlots;
+    auto &slot = p->slots[si];
+    hipError_t e = slot.used ? hipEventSynchronize(slot.done) : hipSuccess;
+    if (e != hipSuccess) return hip_status(e);
     Block *blk = (Block *)((char *)slot.host + slot_block_offset(p));
     const size_t blk_bytes = sizeof(Block) * p->blocks.size();
     std::memcpy(blk, p->blocks.data(), blk_bytes);
-    if (e == hipSuccess) e = launch_upload((const char *)slot.mapped + slot_block_offset(p), p->d_blocks, blk_bytes, s);
+    e = launch_upload((const char *)slot.mapped + slot_block_offset(p), p->d_blocks, blk_bytes, s);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     slot.used = true;
+    if (e == hipSuccess) p->blocks_stale = false;
     return hip_status(e);
 }
 
@@ -624,6 +648,8 @@ static awg_status synth_any(awg_plan *p, uint32_t method, uint64_t n0, uint64_t 
         if (p->n_ramped == 0) return mfma_static(p, method, n0, count, out_i16, out_f32, s);
         if (count >= kHybridMin) return hybrid_synth(p, method, n0, count, out_i16, out_f32, s);
     }
+    const awg_status st = sync_blocks(p, s);
+    if (st != AWG_OK) return st;
     return hip_status(out_f32 ? launch_direct_f32(p, n0, count, out_f32, s) : launch_direct_i16(p, n0, count, out_i16, s));
 }
 
@@ -740,6 +766,8 @@ awg_status awg_synth_multiplex(awg_plan *const *plans, int32_t n_channels, uint6
     if (count == 0) return AWG_OK;
     if (count > UINT64_MAX / (uint64_t)n_channels) return AWG_E_INVALID;
     if ((st = check_out(plans[0], d_out, count * (uint64_t)n_channels, sizeof(int16_t))) != AWG_OK) return st;
+    for (int32_t c = 0; c < n_channels; ++c)
+        if ((st = sync_blocks(plans[c], (hipStream_t)hip_stream)) != AWG_OK) return st;
     ProfScope prof(plans[0]->ctx, (hipStream_t)hip_stream, "mux_kernel");
     for (int32_t c = 0; c < n_channels; ++c) prof.add_work((double)plans[c]->n_tones * (double)count);
     return hip_status(launch_mux(items, n_channels, count, (hipStream_t)hip_stream, prof));
@@ -768,6 +796,7 @@ awg_status awg_peak(awg_plan *p, uint64_t n0, uint64_t count, float *d_scratch, 
     if ((st = check_out(p, d_scratch, count, sizeof(float))) != AWG_OK) return st;
     if ((st = check_out(p, d_peak, 1, sizeof(float))) != AWG_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
+    if ((st = sync_blocks(p, s)) != AWG_OK) return st;
     hipError_t e = launch_direct_f32(p, n0, count, d_scratch, s);
     if (e == hipSuccess) e = launch_peak(d_scratch, count, d_peak, s);
     return hip_status(e);
@@ -784,6 +813,9 @@ awg_status awg_peak_noalloc(awg_plan *p, uint64_t n0, uint64_t count, float *d_p
     float *scr = p->ctx->noalloc_scratch;      // this device's copy, never the symbol itself
     if (!scr) return AWG_E_HIP;
     hipStream_t s = (hipStream_t)hip_stream;
+    // after a retune (whose call set up the staging slots) the block table is
+    // staged in one of them: no allocation here either
+    if ((st = sync_blocks(p, s)) != AWG_OK) return st;
     hipError_t e = launch_direct_f32(p, n0, count, scr, s, false);
     if (e == hipSuccess) e = launch_peak(scr, count, d_peak, s);
     return hip_status(e);

@@ -994,6 +994,64 @@ hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t s
     return hipGetLastError();
 }
 
+// The line-buffer path's staged lists: compact descriptors from pinned memory
+// become ToneDev records in device memory (plan tones gathered from the plan's
+// device table), and the rest of the staging blob is copied as it is.
+__global__ __launch_bounds__(256) void plb_stage_kernel(const PlbDesc *__restrict__ desc, int32_t n_first,
+                                                        int32_t n_desc, const ToneDev *__restrict__ plan_tones,
+                                                        uint64_t n0, ToneDev *__restrict__ dst_first,
+                                                        ToneDev *__restrict__ dst_rest,
+                                                        const uint4 *__restrict__ raw_src, uint4 *__restrict__ raw_dst,
+                                                        uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = tid; i < (uint64_t)n_desc; i += stride) {
+        const PlbDesc d = desc[i];
+        ToneDev t;
+        if (d.src >= 0) {
+            t = plan_tones[d.src];
+        } else {
+            t.p0 = t.p1 = d.p + kPhaseBias;
+            t.f0 = t.f1 = d.f;
+            t.a = UINT64_MAX;
+            t.coef = 0;
+            t.n = 0;
+            t.amp = t.amp1 = d.a;
+            t.shape = AWG_RAMP_NONE;
+            t.table = 0;
+            t.ashape = AWG_RAMP_NONE;
+            t.pad = 0;
+            t.b = 0;
+            t.m = 0;
+        }
+        if (d.lo_row >= 0) {
+            t.lo = n0 + (uint64_t)d.lo_row * kTileSamples;
+            t.hi = n0 + (uint64_t)d.hi_row * kTileSamples + (kTileSamples - 1);
+        } else {
+            t.lo = 1;
+            t.hi = 0;
+        }
+        if (i < (uint64_t)n_first) dst_first[i] = t;
+        else dst_rest[i - (uint64_t)n_first] = t;
+    }
+    for (uint64_t i = tid; i < n16; i += stride) raw_dst[i] = raw_src[i];
+}
+
+hipError_t launch_plb_stage(const PlbDesc *desc, int32_t n_first, int32_t n_desc, const ToneDev *plan_tones,
+                            uint64_t n0, ToneDev *dst_first, ToneDev *dst_rest, const void *raw_src, void *raw_dst,
+                            size_t raw_bytes, hipStream_t s)
+{
+    if (n_first < 0 || n_first > n_desc) return hipErrorInvalidValue;
+    if (((uintptr_t)raw_src | (uintptr_t)raw_dst | raw_bytes) & 15) return hipErrorInvalidValue;
+    const uint64_t n16 = raw_bytes / 16;
+    const uint64_t work = std::max<uint64_t>((uint64_t)n_desc, n16);
+    const uint64_t blocks = std::min<uint64_t>(std::max<uint64_t>((work + 255) / 256, 1), 1024);
+    hipLaunchKernelGGL(plb_stage_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, desc, n_first, n_desc, plan_tones,
+                       n0, dst_first, dst_rest, (const uint4 *)raw_src, (uint4 *)raw_dst, n16);
+    return hipGetLastError();
+}
+
 hipError_t alloc_upload_host(size_t bytes, void **host, void **mapped)
 {
     *host = nullptr;

@@ -98,8 +98,8 @@ struct LineBuf {
     void *d_bwork = nullptr;              // product operands of one batch of groups
     size_t bwork_bytes = 0;
     bool s_zeroed = false;
-    hipEvent_t work_done = nullptr;
-    bool work_used = false;
+    int last_slot = -1;                   // staging slot of the latest pass (its event ends that pass)
+    hipStream_t last_stream = nullptr;
     // cache of group sums: per group, version hash -> slot; the slot's words
     struct Entry { int32_t group; uint64_t hash; uint64_t last_use; bool live; std::vector<Line> words; };
     std::vector<Entry> slot_entry;        // per slot
@@ -108,14 +108,28 @@ struct LineBuf {
     std::vector<int32_t> s_slot;          // per group: the slot S holds (-1: none)
     uint64_t tick = 0;
     // staging
-    struct Slot { void *host = nullptr, *mapped = nullptr, *dev = nullptr; size_t cap = 0; hipEvent_t done = nullptr; bool used = false; };
+    struct Slot {
+        void *host = nullptr, *mapped = nullptr, *dev = nullptr;
+        size_t cap_h = 0, cap_d = 0;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    };
     Slot slots[kSlots];
     int next_slot = 0;
     // host scratch of one pass
-    std::vector<Line> next, l1, l2;
+    std::vector<Line> next;               // per tone: the line at the last sample of the latest pass
+    bool next_held = false;               // S holds exactly the versions of `next` (the latest pass completed)
+    std::vector<uint8_t> dirty;           // per group: a tone's next line changed in this pass
+    std::vector<Line> l1;                 // per tone: its line before its windows (set where sw != 0)
     std::vector<uint32_t> sw;             // per tone: first window row when it switches lines there, else 0
-    std::vector<int32_t> wr_lo, wr_hi;    // per tone: window rows of the pass (wr_lo > wr_hi: none)
-    std::vector<ToneDev> build_list, direct;
+    struct Win { int32_t k; int32_t lo, hi; };
+    std::vector<Win> win;                 // tones whose windows meet the pass: their window rows
+    std::vector<std::pair<int32_t, uint32_t>> gsw;   // distinct (group, switch row) pairs, sorted
+    std::vector<uint32_t> didx;           // sort order of a part of the direct list
+    std::vector<PlbDesc> dsorted;
+    std::vector<PlbDesc> build_list;      // kGroupTones lines per version to build
+    std::vector<PlbDesc> direct, dneg;    // window tones, and the negative lines
+    std::vector<int32_t> key, cnt;        // tile order
     std::vector<int32_t> build_map;
     std::vector<PlbSeg> segs;
     std::vector<PlbFold> folds;
@@ -126,7 +140,6 @@ struct LineBuf {
     std::vector<uint32_t> order;
     std::vector<float> cost;
     std::vector<int32_t> pinned;          // per slot: pass stamp
-    std::vector<uint32_t> bps;
     std::vector<Line> ver;
 };
 
@@ -139,43 +152,52 @@ size_t plb_bytes(uint64_t L, int32_t n_groups, int32_t n_slots)
 
 int32_t groups_of(int32_t K) { return (K + kGroupTones - 1) / kGroupTones; }
 
-// The largest staging blob of a pass: the build list (a next version of every
-// group and a version per segment), its map, the direct list (every tone and
-// its negative line), blocks, tile order, segments, folds.
-size_t blob_cap(const LineBuf &b)
+// Entries of the largest pass: a version of every group and one per segment
+// (build list), every tone and its negative line (direct list).
+size_t max_entries(const LineBuf &b) { return (size_t)(b.n_groups + kMaxSegs) * kGroupTones + 2 * (size_t)b.K; }
+
+// The part of a staging blob copied as it is: build map, blocks, tile order,
+// segments, folds (at their largest).
+size_t raw_cap(const LineBuf &b)
 {
     const size_t ng = (size_t)b.n_groups, K = (size_t)b.K, nb = ng + kMaxSegs;
-    return align_up(sizeof(ToneDev) * nb * kGroupTones, 256) + align_up(sizeof(int32_t) * nb, 256) +
-           align_up(sizeof(ToneDev) * 2 * K, 256) + align_up(sizeof(Block) * (2 * K + 1), 256) +
+    return align_up(sizeof(int32_t) * nb, 256) + align_up(sizeof(Block) * (2 * K + 1), 256) +
            align_up(sizeof(uint32_t) * (kPiece / kRow), 256) + align_up(sizeof(PlbSeg) * kMaxSegs, 256) +
            align_up(sizeof(PlbFold) * ng, 256);
 }
 
-ToneDev line_record(const Line &l, float sign)
+// Host blob: descriptors, then the raw part. Device blob: the build list's and
+// the direct list's records, then the raw part.
+size_t host_cap(const LineBuf &b) { return align_up(sizeof(PlbDesc) * max_entries(b), 256) + raw_cap(b); }
+size_t dev_cap(const LineBuf &b) { return align_up(sizeof(ToneDev) * max_entries(b), 256) + 256 + raw_cap(b); }
+
+// A line as a staged entry (no window), amplitude times sign.
+PlbDesc line_desc(const Line &l, float sign, int32_t lo_row = -1, int32_t hi_row = -1)
+{
+    return PlbDesc{l.p, l.f, sign * l.a, -1, lo_row, hi_row};
+}
+
+// The fields that cut blocks, shared by every line record
+ToneDev line_key()
 {
     ToneDev t;
     std::memset(&t, 0, sizeof(t));
-    t.p0 = t.p1 = l.p + kPhaseBias;
-    t.f0 = t.f1 = l.f;
     t.a = UINT64_MAX;
-    t.n = 0;
-    t.amp = t.amp1 = sign * l.a;
     t.shape = AWG_RAMP_NONE;
     t.ashape = AWG_RAMP_NONE;
-    t.lo = 1;
-    t.hi = 0;
     return t;
 }
 
+// Three independent hash chains (words, frequencies, amplitudes) joined at the end.
 uint64_t version_hash(const Line *w, int32_t n)
 {
-    uint64_t h = 0x243f6a8885a308d3ull;
+    uint64_t h0 = 0x243f6a8885a308d3ull, h1 = 0x13198a2e03707344ull, h2 = 0xa4093822299f31d0ull;
     for (int32_t i = 0; i < n; ++i) {
-        h = mix(h, w[i].p);
-        h = mix(h, w[i].f);
-        h = mix(h, fbits(w[i].a));
+        h0 = mix(h0, w[i].p);
+        h1 = mix(h1, w[i].f);
+        h2 = mix(h2, fbits(w[i].a));
     }
-    return h;
+    return mix(mix(h0, h1), h2);
 }
 
 // The slot holding group g's version w (nullptr-free), or -1.
@@ -232,10 +254,8 @@ int32_t need(LineBuf &b, int32_t g, const Line *w, int32_t n, int32_t stamp)
         e.live = true;
         e.words.assign(w, w + n);
         b.index[g].emplace(h, s);
-        for (int32_t i = 0; i < kGroupTones; ++i) {
-            const int32_t k = g * kGroupTones + i;
-            b.build_list.push_back(k < b.K && i < n ? line_record(w[i], 1.0f) : line_record(Line{0, 0, 0.0f}, 0.0f));
-        }
+        for (int32_t i = 0; i < kGroupTones; ++i)
+            b.build_list.push_back(i < n ? line_desc(w[i], 1.0f) : line_desc(kNoLine, 0.0f));
         b.build_map.push_back(s);
     }
     b.slot_entry[s].last_use = b.tick;
@@ -254,13 +274,15 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
     hipError_t e = hipMalloc(&b.d_S, sizeof(int64_t) * b.L);
     if (e == hipSuccess) e = hipMalloc(&b.d_Q, sizeof(float) * b.L * (size_t)b.n_slots);
     if (e == hipSuccess) e = hipMalloc(&b.d_bwork, b.bwork_bytes);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b.work_done, hipEventDisableTiming);
-    const size_t cap = blob_cap(b);
+    const size_t ch = host_cap(b), cd = dev_cap(b);
     for (auto &sl : b.slots) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = alloc_upload_host(cap, &sl.host, &sl.mapped);
-        if (e == hipSuccess) e = hipMalloc(&sl.dev, cap);
-        if (e == hipSuccess) sl.cap = cap;
+        if (e == hipSuccess) e = alloc_upload_host(ch, &sl.host, &sl.mapped);
+        if (e == hipSuccess) e = hipMalloc(&sl.dev, cd);
+        if (e == hipSuccess) {
+            sl.cap_h = ch;
+            sl.cap_d = cd;
+        }
     }
     if (e != hipSuccess) return hst(e);
     b.slot_entry.assign(b.n_slots, LineBuf::Entry{0, 0, 0, false, {}});
@@ -274,37 +296,54 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
 
 // Launch order of the tiles, costliest first: a window tile costs 1 per tone
 // (2 with its negative line), a tile where a window opens or closes 3.5 more.
-void tile_order(LineBuf &b, uint64_t n0, uint64_t rows)
+// Costs are multiples of 1/2, so the order is a counting sort on twice the
+// cost, rows of equal cost in row order.
+void tile_order(LineBuf &b, const awg_plan *p, uint64_t n0, uint64_t rows)
 {
     b.cost.assign(rows + 1, 0.0f);
-    for (int32_t k = 0; k < b.K; ++k) {
-        if (b.wr_lo[k] > b.wr_hi[k]) continue;
-        const float c = b.next[k] != kNoLine ? 2.0f : 1.0f;
-        b.cost[b.wr_lo[k]] += c;
-        b.cost[b.wr_hi[k] + 1] -= c;
+    for (const LineBuf::Win &w : b.win) {
+        const float c = b.next[w.k] != kNoLine ? 2.0f : 1.0f;
+        b.cost[w.lo] += c;
+        b.cost[w.hi + 1] -= c;
     }
     float run = 0.0f;
     for (uint64_t r = 0; r < rows; ++r) {
         run += b.cost[r];
         b.cost[r] = run;
     }
-    for (const ToneDev &t : b.direct) {
+    for (const PlbDesc &d : b.direct) {
+        if (d.src < 0) continue;
+        const ToneDev &t = p->dev_mirror[d.src];
         if (t.shape == AWG_RAMP_NONE && t.ashape == AWG_RAMP_NONE) continue;
         const uint64_t ends[2] = {t.a, t.a + t.n};
         for (uint64_t x : ends)
             if (x >= n0 && (x - n0) / kRow < rows && (x - n0) % kRow != 0) b.cost[(x - n0) / kRow] += 3.5f;
     }
+    b.key.resize(rows);
+    int32_t top = 0;
+    for (uint64_t r = 0; r < rows; ++r) {
+        b.key[r] = (int32_t)(2.0f * b.cost[r] + 0.5f);
+        top = std::max(top, b.key[r]);
+    }
+    b.cnt.assign((size_t)top + 2, 0);
+    for (uint64_t r = 0; r < rows; ++r) b.cnt[top - b.key[r] + 1]++;
+    for (int32_t c = 1; c <= top + 1; ++c) b.cnt[c] += b.cnt[c - 1];
     b.order.resize(rows);
-    for (uint64_t r = 0; r < rows; ++r) b.order[r] = (uint32_t)r;
-    std::stable_sort(b.order.begin(), b.order.end(), [&](uint32_t x, uint32_t y) { return b.cost[x] > b.cost[y]; });
+    for (uint64_t r = 0; r < rows; ++r) b.order[b.cnt[top - b.key[r]]++] = (uint32_t)r;
 }
 
-void sort_direct(std::vector<ToneDev> *v)
+// Order of the direct list: plan tones (ramped ones first, then by window,
+// table and amplitude window, then window rows) and after them the negative
+// lines by window rows, ties in list order. The tones arrive in the plan's
+// device order, which is the same for the first keys (so that a call whose
+// tones all ramp sums them as the direct kernel does), and the lines in their
+// tones' order; each part is sorted only if it is not in order already.
+void sort_part(LineBuf &lb, const awg_plan *p, std::vector<PlbDesc> *v)
 {
-    std::stable_sort(v->begin(), v->end(), [](const ToneDev &a, const ToneDev &b) {
-        // ramped tones first, in the plan's device order (shape, window, table),
-        // so that a call whose tones all ramp sums them as the direct kernel
-        // does; lines last
+    const ToneDev lk = line_key();
+    auto rec = [&](const PlbDesc &d) -> const ToneDev & { return d.src >= 0 ? p->dev_mirror[d.src] : lk; };
+    auto less = [&](const PlbDesc &x, const PlbDesc &y) {
+        const ToneDev &a = rec(x), &b = rec(y);
         const bool la = a.shape == AWG_RAMP_NONE, lb = b.shape == AWG_RAMP_NONE;
         if (la != lb) return lb;
         if (a.shape != b.shape) return a.shape < b.shape;
@@ -314,8 +353,21 @@ void sort_direct(std::vector<ToneDev> *v)
         if (a.ashape != b.ashape) return a.ashape < b.ashape;
         if (a.b != b.b) return a.b < b.b;
         if (a.m != b.m) return a.m < b.m;
-        return a.lo < b.lo;
+        return x.lo_row < y.lo_row;
+    };
+    bool sorted = true;
+    for (size_t i = 1; sorted && i < v->size(); ++i) sorted = !less((*v)[i], (*v)[i - 1]);
+    if (sorted) return;
+    lb.didx.resize(v->size());
+    for (size_t i = 0; i < v->size(); ++i) lb.didx[i] = (uint32_t)i;
+    std::sort(lb.didx.begin(), lb.didx.end(), [&](uint32_t x, uint32_t y) {
+        if (less((*v)[x], (*v)[y])) return true;
+        if (less((*v)[y], (*v)[x])) return false;
+        return x < y;
     });
+    lb.dsorted.resize(v->size());
+    for (size_t i = 0; i < v->size(); ++i) lb.dsorted[i] = (*v)[lb.didx[i]];
+    v->swap(lb.dsorted);
 }
 
 // One pass of at most kPiece samples. *split: the pass needs more than kMaxSegs
@@ -329,81 +381,87 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     const int32_t K = b.K;
     b.tick++;
     const int32_t stamp = (int32_t)(b.tick & 0x7fffffff);
+    // the previous pass's next lines are what S holds only if it completed
+    const bool held = b.next_held && (int32_t)b.next.size() == K;
+    b.next_held = false;
     b.next.resize(K);
+    b.dirty.assign(b.n_groups, held ? 0 : 1);
     b.l1.resize(K);
-    b.l2.resize(K);
     b.sw.assign(K, 0);
-    b.wr_lo.assign(K, 1);
-    b.wr_hi.assign(K, 0);
+    b.win.clear();
+    b.gsw.clear();
     b.build_list.clear();
     b.build_map.clear();
     b.direct.clear();
+    b.dneg.clear();
     b.segs.clear();
     b.seg_slot.clear();
     b.seg_next.clear();
     b.fold_slots.clear();
     double direct_work = 0.0;
-    for (int32_t k = 0; k < K; ++k) {
-        const ToneDev &t = p->dev_mirror[p->inv[k]];
-        b.l1[k] = line_of(t.p0 - kPhaseBias, t.f0, t.amp);
-        b.l2[k] = line_of(t.p1 - kPhaseBias, t.f1, t.amp1);
+    for (int32_t i = 0; i < K; ++i) {              // device order
+        const ToneDev &t = p->dev_mirror[i];
+        const int32_t k = p->perm[i];
         const bool windowed = t.lo <= t.hi;
         // still inside its windows at the call's last sample: on no line (the
         // direct kernel takes it on every row its windows meet)
-        b.next[k] = !windowed || last < t.lo ? b.l1[k] : (last > t.hi ? b.l2[k] : kNoLine);
+        const Line nx = !windowed || last < t.lo ? line_of(t.p0 - kPhaseBias, t.f0, t.amp)
+                        : last > t.hi             ? line_of(t.p1 - kPhaseBias, t.f1, t.amp1)
+                                                  : kNoLine;
+        if (nx != b.next[k]) {
+            b.next[k] = nx;
+            b.dirty[k / kGroupTones] = 1;
+        }
         if (windowed && t.hi >= n0 && t.lo <= last) {
             const uint64_t lo = t.lo <= n0 ? 0 : (t.lo - n0) / kRow;
             const uint64_t hi = std::min<uint64_t>(rows - 1, (t.hi - n0) / kRow);
-            b.wr_lo[k] = (int32_t)lo;
-            b.wr_hi[k] = (int32_t)hi;
-            if (lo > 0 && b.l1[k] != b.next[k]) b.sw[k] = (uint32_t)lo;
+            b.win.push_back(LineBuf::Win{k, (int32_t)lo, (int32_t)hi});
+            const Line l1 = line_of(t.p0 - kPhaseBias, t.f0, t.amp);
+            if (lo > 0 && l1 != nx) {
+                b.sw[k] = (uint32_t)lo;
+                b.l1[k] = l1;
+                b.gsw.emplace_back(k / kGroupTones, (uint32_t)lo);
+            }
             // the tone on its window rows, and its next line (if any) with the
             // opposite sign
-            ToneDev d = t;
-            d.lo = n0 + lo * kRow;
-            d.hi = n0 + hi * kRow + (kRow - 1);
-            b.direct.push_back(d);
-            const double n_samp = (double)(std::min(d.hi, last) - d.lo + 1);
+            b.direct.push_back(PlbDesc{0, 0, 0.0f, i, (int32_t)lo, (int32_t)hi});
+            const double n_samp = (double)(std::min(n0 + hi * kRow + (kRow - 1), last) - (n0 + lo * kRow) + 1);
             direct_work += n_samp;
-            if (b.next[k] != kNoLine) {
-                ToneDev neg = line_record(b.next[k], -1.0f);
-                neg.lo = d.lo;
-                neg.hi = d.hi;
-                b.direct.push_back(neg);
+            if (nx != kNoLine) {
+                b.dneg.push_back(line_desc(nx, -1.0f, (int32_t)lo, (int32_t)hi));
                 direct_work += n_samp;
             }
         }
     }
     // segments of the pass: one per distinct switch row of each group (counted
     // before the cache is touched)
-    int64_t n_segs = 0;
-    for (int32_t g = 0; g < b.n_groups; ++g) {
-        const int32_t k0 = g * kGroupTones, n = std::min(kGroupTones, K - k0);
-        b.bps.clear();
-        for (int32_t i = 0; i < n; ++i)
-            if (b.sw[k0 + i]) b.bps.push_back(b.sw[k0 + i]);
-        std::sort(b.bps.begin(), b.bps.end());
-        n_segs += std::unique(b.bps.begin(), b.bps.end()) - b.bps.begin();
-    }
-    if (n_segs > kMaxSegs) {
-        *split = true;
+    std::sort(b.gsw.begin(), b.gsw.end());
+    b.gsw.erase(std::unique(b.gsw.begin(), b.gsw.end()), b.gsw.end());
+    if ((int64_t)b.gsw.size() > kMaxSegs) {
+        *split = true;            // next[] is this range's, not what S holds
         return AWG_OK;
     }
     // versions: each group's next version (held by S), and the versions of its
     // rows before the switch rows of its tones
+    size_t gi = 0;
     for (int32_t g = 0; g < b.n_groups; ++g) {
         const int32_t k0 = g * kGroupTones, n = std::min(kGroupTones, K - k0);
-        const int32_t snext = need(b, g, &b.next[k0], n, stamp);
+        // most groups keep the version S already holds: no line of theirs
+        // changed since a completed pass (or their words equal it), so no hash
+        int32_t snext = b.s_slot[g];
+        if (snext >= 0 && b.slot_entry[snext].live &&
+            (!b.dirty[g] || std::equal(b.slot_entry[snext].words.begin(), b.slot_entry[snext].words.end(),
+                                       &b.next[k0], &b.next[k0] + n))) {
+            b.slot_entry[snext].last_use = b.tick;
+            b.pinned[snext] = stamp;
+        } else {
+            snext = need(b, g, &b.next[k0], n, stamp);
+        }
         if (snext < 0) return AWG_E_NOMEM;
         if (b.s_slot[g] != snext) b.fold_slots.emplace_back(snext, b.s_slot[g]);
-        b.bps.clear();
-        for (int32_t i = 0; i < n; ++i)
-            if (b.sw[k0 + i]) b.bps.push_back(b.sw[k0 + i]);
-        if (b.bps.empty()) continue;
-        std::sort(b.bps.begin(), b.bps.end());
-        b.bps.erase(std::unique(b.bps.begin(), b.bps.end()), b.bps.end());
         uint32_t begin = 0;
-        for (uint32_t bp : b.bps) {
+        for (; gi < b.gsw.size() && b.gsw[gi].first == g; ++gi) {
+            const uint32_t bp = b.gsw[gi].second;
             // rows [begin, bp): tones that switch at bp or later are still on their first line
             b.ver.assign(&b.next[k0], &b.next[k0] + n);
             for (int32_t i = 0; i < n; ++i)
@@ -416,52 +474,72 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
             begin = bp;
         }
     }
-    sort_direct(&b.direct);
-    build_blocks(b.direct, (int32_t)b.direct.size(), &b.blocks);
-    tile_order(b, n0, rows);
+    sort_part(b, p, &b.direct);
+    sort_part(b, p, &b.dneg);
+    b.direct.insert(b.direct.end(), b.dneg.begin(), b.dneg.end());
+    {
+        const ToneDev lk = line_key();
+        build_blocks_by((int32_t)b.direct.size(), (int32_t)b.direct.size(),
+                        [&](int32_t i) -> const ToneDev & {
+                            return b.direct[i].src >= 0 ? p->dev_mirror[b.direct[i].src] : lk;
+                        },
+                        &b.blocks);
+    }
+    tile_order(b, p, n0, rows);
 
-    // staging blob: build list | build map | direct list | blocks | tile order | segments | folds
+    // host blob: descriptors (build list, then direct list) | raw part
+    // device blob: build records | direct records | raw part
+    // raw part: build map | blocks | tile order | segments | folds
     const int32_t n_built = (int32_t)b.build_map.size();
+    const int32_t n_be = (int32_t)b.build_list.size();
     const int32_t n_direct = (int32_t)b.direct.size();
     const int32_t n_seg = (int32_t)b.segs.size();
     const int32_t n_fold = (int32_t)b.fold_slots.size();
-    const size_t off_m = align_up(sizeof(ToneDev) * b.build_list.size(), 256);
-    const size_t off_d = off_m + align_up(sizeof(int32_t) * (size_t)n_built, 256);
-    const size_t off_b = off_d + align_up(sizeof(ToneDev) * (size_t)n_direct, 256);
-    const size_t off_o = off_b + align_up(sizeof(Block) * b.blocks.size(), 256);
-    const size_t off_s = off_o + align_up(sizeof(uint32_t) * rows, 256);
-    const size_t off_f = off_s + align_up(sizeof(PlbSeg) * (size_t)n_seg, 256);
-    const size_t total = off_f + sizeof(PlbFold) * (size_t)n_fold;
+    const size_t r_b = align_up(sizeof(int32_t) * (size_t)n_built, 256);
+    const size_t r_o = r_b + align_up(sizeof(Block) * b.blocks.size(), 256);
+    const size_t r_s = r_o + align_up(sizeof(uint32_t) * rows, 256);
+    const size_t r_f = r_s + align_up(sizeof(PlbSeg) * (size_t)n_seg, 256);
+    const size_t raw = align_up(r_f + sizeof(PlbFold) * (size_t)n_fold, 16);
+    const size_t h_raw = align_up(sizeof(PlbDesc) * (size_t)(n_be + n_direct), 256);
+    const size_t d_dir = align_up(sizeof(ToneDev) * (size_t)n_be, 256);
+    const size_t d_raw = align_up(d_dir + sizeof(ToneDev) * (size_t)n_direct, 256);
     LineBuf::Slot &slot = b.slots[b.next_slot];
+    const int this_slot = b.next_slot;
     b.next_slot = (b.next_slot + 1) % kSlots;
-    if (total > slot.cap) return AWG_E_UNSUPPORTED;
+    if (h_raw + raw > slot.cap_h || d_raw + raw > slot.cap_d) return AWG_E_UNSUPPORTED;
     hipError_t e = slot.used ? hipEventSynchronize(slot.done) : hipSuccess;
     if (e != hipSuccess) return hst(e);
     slot.used = false;
     char *hb = (char *)slot.host;
     char *db = (char *)slot.dev;
-    if (!b.build_list.empty()) std::memcpy(hb, b.build_list.data(), sizeof(ToneDev) * b.build_list.size());
-    if (n_built) std::memcpy(hb + off_m, b.build_map.data(), sizeof(int32_t) * (size_t)n_built);
-    if (n_direct) std::memcpy(hb + off_d, b.direct.data(), sizeof(ToneDev) * (size_t)n_direct);
-    std::memcpy(hb + off_b, b.blocks.data(), sizeof(Block) * b.blocks.size());
-    std::memcpy(hb + off_o, b.order.data(), sizeof(uint32_t) * rows);
-    PlbSeg *sg = (PlbSeg *)(hb + off_s);
+    PlbDesc *hd = (PlbDesc *)hb;
+    if (n_be) std::memcpy(hd, b.build_list.data(), sizeof(PlbDesc) * (size_t)n_be);
+    if (n_direct) std::memcpy(hd + n_be, b.direct.data(), sizeof(PlbDesc) * (size_t)n_direct);
+    char *hr = hb + h_raw;
+    if (n_built) std::memcpy(hr, b.build_map.data(), sizeof(int32_t) * (size_t)n_built);
+    std::memcpy(hr + r_b, b.blocks.data(), sizeof(Block) * b.blocks.size());
+    std::memcpy(hr + r_o, b.order.data(), sizeof(uint32_t) * rows);
+    PlbSeg *sg = (PlbSeg *)(hr + r_s);
     for (int32_t i = 0; i < n_seg; ++i) {
         sg[i] = b.segs[i];
         sg[i].q_row = b.d_Q + (size_t)b.seg_slot[i] * b.L;
         sg[i].q_next = b.d_Q + (size_t)b.seg_next[i] * b.L;
     }
-    PlbFold *fd = (PlbFold *)(hb + off_f);
+    PlbFold *fd = (PlbFold *)(hr + r_f);
     for (int32_t i = 0; i < n_fold; ++i) {
         fd[i].q_new = b.d_Q + (size_t)b.fold_slots[i].first * b.L;
         fd[i].q_old = b.fold_slots[i].second >= 0 ? b.d_Q + (size_t)b.fold_slots[i].second * b.L : nullptr;
     }
-    e = launch_upload(slot.mapped, db, total, s);
-    if (e == hipSuccess && b.work_used) e = hipStreamWaitEvent(s, b.work_done, 0);
+    // the previous pass's work (S, the cache) precedes this one on s
+    if (b.last_slot >= 0 && b.last_stream != s) e = hipStreamWaitEvent(s, b.slots[b.last_slot].done, 0);
+    if (e == hipSuccess)
+        e = launch_plb_stage((const PlbDesc *)slot.mapped, n_be, n_be + n_direct, p->d_tones, n0, (ToneDev *)db,
+                             (ToneDev *)(db + d_dir), (const char *)slot.mapped + h_raw, db + d_raw, raw, s);
     if (e == hipSuccess && !b.s_zeroed) {
         e = launch_plb_zero(b.d_S, b.L, s);
         if (e == hipSuccess) b.s_zeroed = true;
     }
+    char *dr = db + d_raw;
     // the new versions' period sums, in batches
     for (int32_t i = 0; e == hipSuccess && i < n_built; i += kBuildBatch) {
         const int32_t nb = std::min(kBuildBatch, n_built - i);
@@ -469,17 +547,19 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
         for (int32_t z = i; z < i + nb; ++z)
             work += (double)std::min(kGroupTones, K - b.slot_entry[b.build_map[z]].group * kGroupTones) * (double)b.L;
         e = launch_group_sums(p, b.method, (const ToneDev *)db + (size_t)i * kGroupTones, nb, kGroupTones, b.L,
-                              b.d_bwork, b.d_Q, (const int32_t *)(db + off_m) + i, s, work);
+                              b.d_bwork, b.d_Q, (const int32_t *)dr + i, s, work);
     }
     // S to the call's next versions, then the call
-    if (e == hipSuccess) e = launch_plb_fold(p, b.d_S, b.L, (const PlbFold *)(db + off_f), n_fold, s);
+    if (e == hipSuccess) e = launch_plb_fold(p, b.d_S, b.L, (const PlbFold *)(dr + r_f), n_fold, s);
     if (e == hipSuccess)
-        e = launch_plb(p, (const ToneDev *)(db + off_d), (const Block *)(db + off_b), (const uint32_t *)(db + off_o),
-                       n0, count, b.d_S, b.L, (const PlbSeg *)(db + off_s), n_seg, out_i16, out_f32, s, direct_work);
-    if (e == hipSuccess) e = hipEventRecord(b.work_done, s);
-    if (e == hipSuccess) b.work_used = true;
+        e = launch_plb(p, (const ToneDev *)(db + d_dir), (const Block *)(dr + r_b), (const uint32_t *)(dr + r_o),
+                       n0, count, b.d_S, b.L, (const PlbSeg *)(dr + r_s), n_seg, out_i16, out_f32, s, direct_work);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
-    if (e == hipSuccess) slot.used = true;
+    if (e == hipSuccess) {
+        slot.used = true;
+        b.last_slot = this_slot;
+        b.last_stream = s;
+    }
     if (e != hipSuccess) {
         // the device state is unknown: start over on the next call
         for (int32_t sl = 0; sl < b.n_slots; ++sl) {
@@ -493,6 +573,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
         return hst(e);
     }
     for (const auto &f : b.fold_slots) b.s_slot[b.slot_entry[f.first].group] = f.first;
+    b.next_held = true;
     return AWG_OK;
 }
 
@@ -510,7 +591,6 @@ void plb_release(awg_plan *p)
 {
     LineBuf *b = p->plb;
     if (!b) return;
-    if (b->work_done) (void)hipEventSynchronize(b->work_done);
     for (auto &sl : b->slots) {
         if (sl.done) (void)hipEventSynchronize(sl.done);
         if (sl.host) (void)hipHostFree(sl.host);
@@ -520,7 +600,6 @@ void plb_release(awg_plan *p)
     if (b->d_S) (void)hipFree(b->d_S);
     if (b->d_Q) (void)hipFree(b->d_Q);
     if (b->d_bwork) (void)hipFree(b->d_bwork);
-    if (b->work_done) (void)hipEventDestroy(b->work_done);
     delete b;
     p->plb = nullptr;
 }
@@ -530,7 +609,7 @@ size_t plb_bytes_of(const awg_plan *p)
     const LineBuf *b = p->plb;
     if (!b) return 0;
     size_t n = plb_bytes(b->L, b->n_groups, b->n_slots);
-    for (const auto &sl : b->slots) n += sl.cap;
+    for (const auto &sl : b->slots) n += sl.cap_d;
     return n;
 }
 

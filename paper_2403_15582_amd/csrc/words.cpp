@@ -237,53 +237,7 @@ ToneDev to_device(const ToneHost &t, uint16_t table)
 // mixed blocks of up to kBlock tones that share their flags (split, amplitude).
 void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vector<Block> *out)
 {
-    constexpr int32_t kMinRun = 8;
-    const int32_t n = (int32_t)tones.size();
-    out->clear();
-    out->push_back(Block{0, 0, 0});
-    auto same = [&](int32_t x, int32_t y) {
-        const ToneDev &a = tones[x], &b = tones[y];
-        return a.shape == b.shape && a.a == b.a && a.n == b.n && a.table == b.table && a.ashape == b.ashape &&
-               a.b == b.b && a.m == b.m && ((x < n_split) == (y < n_split));
-    };
-    int32_t mixed_begin = -1, mixed_count = 0;
-    uint16_t mixed_flags = 0;
-    auto flush = [&]() {
-        if (mixed_count > 0) out->push_back(Block{(uint32_t)mixed_begin, (uint16_t)mixed_count, mixed_flags});
-        mixed_begin = -1;
-        mixed_count = 0;
-    };
-    for (int32_t i = 0; i < n;) {
-        int32_t j = i + 1;
-        while (j < n && same(i, j)) ++j;
-        const int32_t L = j - i;
-        const uint16_t flags = (i < n_split ? kBlockSplit : 0) | (tones[i].ashape != AWG_RAMP_NONE ? kBlockAmp : 0);
-        if (L >= kMinRun) {
-            flush();
-            int32_t nb = (L + kBlock - 1) / kBlock;
-            nb = (nb + kWaves - 1) / kWaves * kWaves;
-            const int32_t base = L / nb, extra = L % nb;
-            int32_t b = i;
-            const bool smooth = tones[i].shape == AWG_RAMP_COSINE || tones[i].shape == AWG_RAMP_MINJERK;
-            for (int32_t q = 0; q < nb; ++q) {
-                const int32_t c = base + (q < extra ? 1 : 0);
-                bool step16 = smooth;
-                for (int32_t k = b; step16 && k < b + c; ++k) step16 = (tones[k].coef & 0xffff) == 0;
-                out->push_back(Block{(uint32_t)b, (uint16_t)c,
-                                     (uint16_t)(kBlockUniform | flags | (step16 ? kBlockStep16 : 0))});
-                b += c;
-            }
-        } else {
-            for (int32_t k = i; k < j; ++k) {
-                if (mixed_count > 0 && (mixed_count == kBlock || mixed_flags != flags)) flush();
-                if (mixed_count == 0) { mixed_begin = k; mixed_flags = flags; }
-                ++mixed_count;
-            }
-        }
-        i = j;
-    }
-    flush();
-    (*out)[0].begin = (uint32_t)(out->size() - 1);
+    build_blocks_by((int32_t)tones.size(), n_split, [&](int32_t i) -> const ToneDev & { return tones[i]; }, out);
 }
 
 }  // namespace awg
