@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <atomic>
 #include <map>
 #include <mutex>
@@ -204,9 +205,11 @@ uint64_t chirp_end_term(int32_t shape, int64_t coef, int64_t dF, uint64_t n);
 ToneDev to_device(const ToneHost &t, uint16_t table);
 // Block table of a tone list (see Block). Tones [0, n_split) are marked split
 // (hybrid path) and no block spans position n_split. At most n + 1 entries.
-// build_blocks_by reads tone i of an n-tone list through tone(i).
-template <class Get>
-void build_blocks_by(int32_t n, int32_t n_split, Get &&tone, std::vector<Block> *out)
+// build_blocks_by reads tone i of an n-tone list through tone(i), and cuts the
+// run of like tones that starts at i into blocks of at most max_block(i) tones
+// (at most kBlock).
+template <class Get, class MaxBlock>
+void build_blocks_by(int32_t n, int32_t n_split, Get &&tone, MaxBlock &&max_block, std::vector<Block> *out)
 {
     constexpr int32_t kMinRun = 8;
     out->clear();
@@ -230,7 +233,9 @@ void build_blocks_by(int32_t n, int32_t n_split, Get &&tone, std::vector<Block> 
         const uint16_t flags = (i < n_split ? kBlockSplit : 0) | (tone(i).ashape != AWG_RAMP_NONE ? kBlockAmp : 0);
         if (L >= kMinRun) {
             flush();
-            int32_t nb = (L + kBlock - 1) / kBlock;
+            // at least kWaves tones per block: with runs of kMinRun or more, no block is empty
+            const int32_t mb = std::max<int32_t>(kWaves, std::min<int32_t>(kBlock, max_block(i)));
+            int32_t nb = (L + mb - 1) / mb;
             nb = (nb + kWaves - 1) / kWaves * kWaves;
             const int32_t base = L / nb, extra = L % nb;
             int32_t b = i;
@@ -254,6 +259,11 @@ void build_blocks_by(int32_t n, int32_t n_split, Get &&tone, std::vector<Block> 
     }
     flush();
     (*out)[0].begin = (uint32_t)(out->size() - 1);
+}
+template <class Get>
+void build_blocks_by(int32_t n, int32_t n_split, Get &&tone, std::vector<Block> *out)
+{
+    build_blocks_by(n, n_split, tone, [](int32_t) { return kBlock; }, out);
 }
 void build_blocks(const std::vector<ToneDev> &tones, int32_t n_split, std::vector<Block> *out);
 
@@ -345,9 +355,35 @@ static_assert(sizeof(PlbDesc) == 32, "PlbDesc must be 32 bytes");
 hipError_t launch_plb_stage(const PlbDesc *desc, int32_t n_first, int32_t n_desc, const ToneDev *plan_tones,
                             uint64_t n0, ToneDev *dst_first, ToneDev *dst_rest, const void *raw_src, void *raw_dst,
                             size_t raw_bytes, hipStream_t s);
-hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const uint32_t *d_order,
-                      uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L, const PlbSeg *d_segs,
-                      int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s, double work);
+// A piece of a split tile's work: tones off .. off + cnt - 1 of block `block`
+// (cnt = 0: the whole block).
+struct PlbPiece {
+    uint32_t block;
+    uint16_t off, cnt;
+};
+// A work item of the line-buffer kernel: a whole tile (part < 0: every block,
+// then the line tones and the rounding) or one part of a split tile (the
+// pieces [first, first + count), its sum into partial slot `part`).
+struct PlbItem {
+    uint32_t row;
+    int32_t part;
+    uint32_t first, count;
+};
+// A split tile: its parts' sums sit in partial slots first .. first + n - 1.
+struct PlbSplit {
+    uint32_t row;
+    uint32_t first, n;
+    uint32_t pad;
+};
+// The line-buffer launch: n_items work items, then (n_split > 0) one combine
+// workgroup per split tile. d_partials holds 1024 floats per partial slot;
+// d_span[i] = (first row, last row) the tones of block i are summed on.
+hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const PlbItem *d_items,
+                      int32_t n_items, const PlbPiece *d_pieces, const int2 *d_span, float *d_partials,
+                      const PlbSplit *d_splits,
+                      int32_t n_split, uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L,
+                      const PlbSeg *d_segs, int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s,
+                      double work);
 hipError_t launch_plb_fold(const awg_plan *p, int64_t *d_S, uint64_t L, const PlbFold *d_folds, int32_t n_fold,
                            hipStream_t s);
 hipError_t launch_plb_zero(int64_t *d_S, uint64_t L, hipStream_t s);

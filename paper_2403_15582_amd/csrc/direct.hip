@@ -259,7 +259,53 @@ struct PlbIn {
     const PlbSeg *segs;
     int32_t n_seg;
     uint32_t row;                // this tile's row in the call
+    // one part of a split tile: only the pieces pieces[0 .. n_pieces) (piece j
+    // on wave j mod 4), and the tile's sum goes to partial[0 .. 64 S) without
+    // the line tones and the rounding (the combine kernel adds them)
+    const PlbPiece *pieces;      // nullptr: every block, then the full epilogue
+    uint32_t n_pieces;
+    float *partial;
+    // per block: the first and last row its tones are summed on (blocks whose
+    // span misses this row are skipped whole)
+    const int2 *span;
 };
+
+// The line tones of samples tile0 + i0 .. i0 + PER - 1: S and the segments'
+// group differences at m = n mod L, in list order.
+template <int PER>
+__device__ __forceinline__ void plb_lines(const PlbIn &plb, uint64_t tile0, uint32_t i0, uint32_t valid,
+                                          float (&g)[PER])
+{
+    const uint64_t m0 = (tile0 + i0) & plb.mask;
+    if (PER == 4 && i0 + PER <= valid && (m0 & 3) == 0 && m0 + 3 <= plb.mask) {
+        const longlong2 sa = *(const longlong2 *)(plb.S + m0), sb = *(const longlong2 *)(plb.S + m0 + 2);
+        g[0] = (float)((double)sa.x * 0x1p-32);
+        g[1] = (float)((double)sa.y * 0x1p-32);
+        g[2] = (float)((double)sb.x * 0x1p-32);
+        g[3] = (float)((double)sb.y * 0x1p-32);
+        for (int32_t q = 0; q < plb.n_seg; ++q) {
+            const PlbSeg sg = plb.segs[q];
+            if (plb.row < sg.row_begin || plb.row > sg.row_end) continue;
+            const float4 u = *(const float4 *)(sg.q_row + m0), v = *(const float4 *)(sg.q_next + m0);
+            g[0] += u.x - v.x; g[1] += u.y - v.y; g[2] += u.z - v.z; g[3] += u.w - v.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const uint64_t m = (m0 + (uint64_t)e) & plb.mask;
+            g[e] = (float)((double)plb.S[m] * 0x1p-32);
+        }
+        for (int32_t q = 0; q < plb.n_seg; ++q) {
+            const PlbSeg sg = plb.segs[q];
+            if (plb.row < sg.row_begin || plb.row > sg.row_end) continue;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const uint64_t m = (m0 + (uint64_t)e) & plb.mask;
+                g[e] += sg.q_row[m] - sg.q_next[m];
+            }
+        }
+    }
+}
 
 // One tile: the 64*S samples tile0 .. tile0 + 64*S - 1 of a tone list, summed
 // by the 4 waves of the workgroup and written to out[0 .. valid). STATIC: every
@@ -272,7 +318,7 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                                            const uint64_t *const *__restrict__ tables, uint64_t tile0,
                                            uint32_t valid, void *__restrict__ out, float (*part)[kLanes * S],
                                            const HybridIn &hyb = HybridIn{0, nullptr, 0}, uint32_t ostride = 1,
-                                           const PlbIn &plb = PlbIn{nullptr, 0, nullptr, 0, 0})
+                                           const PlbIn &plb = PlbIn{nullptr, 0, nullptr, 0, 0, nullptr, 0, nullptr, nullptr})
 {
     constexpr int T = kLanes * S;                 // samples per tile
     const uint32_t lane = threadIdx.x & 63u;
@@ -285,9 +331,20 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
     const int n_blocks = (int)blocks[0].begin;
     const uint64_t tile_last = tile0 + (uint64_t)(T - 1);
     const uint32_t j = lane * S;
-    for (int bi = wave; bi < n_blocks; bi += kWaves) {
-        const Block bk = blocks[1 + bi];
-        const int k0 = (int)bk.begin, k1 = k0 + (int)bk.count;
+    const bool listed = PLB && plb.pieces != nullptr;
+    const int n_iter = listed ? (int)plb.n_pieces : n_blocks;
+    for (int it = wave; it < n_iter; it += kWaves) {
+        PlbPiece pc{(uint32_t)it, 0, 0};
+        if (listed) pc = plb.pieces[it];
+        if (PLB && !listed) {
+            const int2 sp = plb.span[pc.block];
+            if ((int)plb.row < sp.x || (int)plb.row > sp.y) continue;
+        }
+        const Block bk = blocks[1 + pc.block];
+        // a piece may take a sub-range of a block's tones (a uniform block's
+        // tones share its regime, so any of them stands for the block)
+        const int k0 = (int)bk.begin + (int)pc.off;
+        const int k1 = pc.cnt ? k0 + (int)pc.cnt : (int)bk.begin + (int)bk.count;
         const bool split = HYB && (bk.flags & kBlockSplit);
         float blk[S];
 #pragma unroll
@@ -546,38 +603,19 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
             }
         }
     }
-    if (PLB) {
-        // the line tones: S and the segments' group differences at m = n mod L
-        const uint64_t m0 = (tile0 + i0) & plb.mask;
-        if (i0 + PER <= valid && (m0 & 3) == 0 && m0 + 3 <= plb.mask) {
-            const longlong2 sa = *(const longlong2 *)(plb.S + m0), sb = *(const longlong2 *)(plb.S + m0 + 2);
-            g[0] = (float)((double)sa.x * 0x1p-32);
-            g[1] = (float)((double)sa.y * 0x1p-32);
-            g[2] = (float)((double)sb.x * 0x1p-32);
-            g[3] = (float)((double)sb.y * 0x1p-32);
-            for (int32_t q = 0; q < plb.n_seg; ++q) {
-                const PlbSeg sg = plb.segs[q];
-                if (plb.row < sg.row_begin || plb.row > sg.row_end) continue;
-                const float4 u = *(const float4 *)(sg.q_row + m0), v = *(const float4 *)(sg.q_next + m0);
-                g[0] += u.x - v.x; g[1] += u.y - v.y; g[2] += u.z - v.z; g[3] += u.w - v.w;
-            }
-        } else {
+    if (PLB && plb.partial) {
+        // one part of a split tile: its four wave sums, every sample of the tile
+        float y[PER];
 #pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                const uint64_t m = (m0 + (uint64_t)e) & plb.mask;
-                g[e] = (float)((double)plb.S[m] * 0x1p-32);
-            }
-            for (int32_t q = 0; q < plb.n_seg; ++q) {
-                const PlbSeg sg = plb.segs[q];
-                if (plb.row < sg.row_begin || plb.row > sg.row_end) continue;
-#pragma unroll
-                for (int e = 0; e < PER; ++e) {
-                    const uint64_t m = (m0 + (uint64_t)e) & plb.mask;
-                    g[e] += sg.q_row[m] - sg.q_next[m];
-                }
-            }
+        for (int e = 0; e < PER; ++e) {
+            const uint32_t i = i0 + e;
+            y[e] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
         }
+        *(float4 *)(plb.partial + i0) = make_float4(y[0], y[1], y[2], y[3]);
+        __syncthreads();
+        return;
     }
+    if (PLB) plb_lines<PER>(plb, tile0, i0, valid, g);
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = i0 + e;
@@ -634,21 +672,64 @@ __global__ __launch_bounds__(256) void direct_hybrid_kernel(const ToneDev *__res
 // tones on their own tiles, the line tones from S and the segments (PlbIn).
 template <int S, bool F32OUT>
 __global__ __launch_bounds__(256) void plb_kernel(const ToneDev *__restrict__ tones, const Block *__restrict__ blocks,
-                                                  const uint32_t *__restrict__ order,
+                                                  const PlbItem *__restrict__ items,
                                                   const uint64_t *const *__restrict__ tables, uint64_t n0,
                                                   uint64_t count, void *__restrict__ out, const int64_t *__restrict__ S_sum,
-                                                  uint64_t mask, const PlbSeg *__restrict__ segs, int32_t n_seg)
+                                                  uint64_t mask, const PlbSeg *__restrict__ segs, int32_t n_seg,
+                                                  const PlbPiece *__restrict__ pieces, float *__restrict__ partials,
+                                                  const int2 *__restrict__ span)
 {
     constexpr int T = kLanes * S;
     __shared__ float part[kWaves][T];
-    const uint32_t row = order[blockIdx.x];
+    const PlbItem item = items[blockIdx.x];
+    const uint32_t row = item.row;
     const uint64_t rel = (uint64_t)row * T;
     const uint64_t left = count - rel;
     const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
     void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
-    const PlbIn plb{S_sum, mask, segs, n_seg, row};
+    const bool is_part = item.part >= 0;
+    const PlbIn plb{S_sum, mask, segs, n_seg, row, is_part ? pieces + item.first : nullptr, item.count,
+                    is_part ? partials + (size_t)item.part * T : nullptr, span};
     synth_tile<S, F32OUT, false, true, true>(tones, blocks, tables, n0 + rel, valid, o, part,
                                              HybridIn{0, nullptr, 0}, 1, plb);
+}
+
+// The split tiles of a line-buffer launch: the parts' sums added in part order,
+// then the line tones and the rounding, as the tile epilogue does for a whole
+// tile (y = lines + sum).
+template <bool F32OUT>
+__global__ __launch_bounds__(256) void plb_combine_kernel(const PlbSplit *__restrict__ splits,
+                                                          const float *__restrict__ partials, uint64_t n0,
+                                                          uint64_t count, void *__restrict__ out,
+                                                          const int64_t *__restrict__ S_sum, uint64_t mask,
+                                                          const PlbSeg *__restrict__ segs, int32_t n_seg)
+{
+    constexpr int T = kTileSamples;
+    constexpr int PER = T / 256;
+    const PlbSplit sp = splits[blockIdx.x];
+    const uint64_t rel = (uint64_t)sp.row * T;
+    const uint64_t left = count - rel;
+    const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
+    const uint32_t i0 = threadIdx.x * PER;
+    const float *pp = partials + (size_t)sp.first * T + i0;
+    float4 v = *(const float4 *)pp;
+    float y[PER] = {v.x, v.y, v.z, v.w};
+    for (uint32_t q = 1; q < sp.n; ++q) {
+        v = *(const float4 *)(pp + (size_t)q * T);
+        y[0] += v.x; y[1] += v.y; y[2] += v.z; y[3] += v.w;
+    }
+    const PlbIn plb{S_sum, mask, segs, n_seg, sp.row, nullptr, 0, nullptr, nullptr};
+    float g[PER];
+    plb_lines<PER>(plb, n0 + rel, i0, valid, g);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const uint32_t i = i0 + e;
+        const float z = g[e] + y[e];
+        if (i < valid) {
+            if (F32OUT) ((float *)out)[rel + i] = z;
+            else ((int16_t *)out)[rel + i] = quantise(z);
+        }
+    }
 }
 
 // S[m] += sum over the folds f of fix(q_new_f[m]) - fix(q_old_f[m]) (q_old_f may
@@ -854,22 +935,40 @@ hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const
     return hipGetLastError();
 }
 
-hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const uint32_t *d_order,
-                      uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L, const PlbSeg *d_segs,
-                      int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s, double work)
+hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const PlbItem *d_items,
+                      int32_t n_items, const PlbPiece *d_pieces, const int2 *d_span, float *d_partials,
+                      const PlbSplit *d_splits,
+                      int32_t n_split, uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L,
+                      const PlbSeg *d_segs, int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s,
+                      double work)
 {
     constexpr uint64_t T = kLanes * kS;
+    static_assert(T == kTileSamples, "line-buffer rows are direct-kernel tiles");
     const uint64_t tiles = (count + T - 1) / T;
     if (tiles == 0) return hipSuccess;
-    if (tiles > kMaxTilesPerLaunch || L < T || (L & (L - 1)) != 0) return hipErrorInvalidValue;
-    ProfScope prof(p->ctx, s, out_f32 ? "plb_kernel_f32" : "plb_kernel");
-    prof.add_work(work);
+    if (tiles > kMaxTilesPerLaunch || L < T || (L & (L - 1)) != 0 || n_items <= 0 || n_split < 0)
+        return hipErrorInvalidValue;
+    {
+        ProfScope prof(p->ctx, s, out_f32 ? "plb_kernel_f32" : "plb_kernel");
+        prof.add_work(work);
+        if (out_f32)
+            prof.launch(plb_kernel<kS, true>, dim3((uint32_t)n_items), dim3(256), 0, d_tones, d_blocks, d_items,
+                        p->d_table_ptrs, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg, d_pieces, d_partials,
+                        d_span);
+        else
+            prof.launch(plb_kernel<kS, false>, dim3((uint32_t)n_items), dim3(256), 0, d_tones, d_blocks, d_items,
+                        p->d_table_ptrs, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg, d_pieces, d_partials,
+                        d_span);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess || n_split == 0) return e;
+    }
+    ProfScope prof(p->ctx, s, "plb_combine_kernel");
     if (out_f32)
-        prof.launch(plb_kernel<kS, true>, dim3((uint32_t)tiles), dim3(256), 0, d_tones, d_blocks, d_order,
-                    p->d_table_ptrs, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg);
+        prof.launch(plb_combine_kernel<true>, dim3((uint32_t)n_split), dim3(256), 0, d_splits,
+                    (const float *)d_partials, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg);
     else
-        prof.launch(plb_kernel<kS, false>, dim3((uint32_t)tiles), dim3(256), 0, d_tones, d_blocks, d_order,
-                    p->d_table_ptrs, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg);
+        prof.launch(plb_combine_kernel<false>, dim3((uint32_t)n_split), dim3(256), 0, d_splits,
+                    (const float *)d_partials, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg);
     return hipGetLastError();
 }
 

@@ -20,16 +20,15 @@
 // Each call over [n0, n0 + count) in rows of 1024 samples is evaluated from
 // the call alone (the plan's state and the range), so equal calls give equal
 // samples whatever the plan computed before:
-//  * a tone's "next" line is the one it is on at the call's last sample (none,
-//    i.e. zero amplitude, if that sample is still inside its windows); each
-//    group's version of next lines is folded into S before the call is summed;
-//  * rows before a tone's windows, where it is still on its line before them
-//    while its next line is the one after, hold a different version of the
-//    group: for those rows the call adds Q(row version) - Q(next version)
-//    ("segments");
+//  * a tone's "next" line is none (zero amplitude) if its windows meet the
+//    call, else the one it is on over the whole call; each group's version of
+//    next lines is folded into S before the call is summed;
 //  * on the rows its windows meet, a tone runs on the direct kernel with its
-//    exact chirp phase, together with a copy of its next line, if it has one,
-//    at minus its amplitude (the line S and the segments count for it there).
+//    exact phase (S and the segments hold nothing for it there);
+//  * on the call's rows before and after those, where it is on its line before
+//    or after its windows, the group holds a different version: for each run
+//    of rows with one version the call adds Q(row version) - Q(next version)
+//    ("segments").
 // The direct kernel adds, per tile, S, the segments and its own sum, and rounds.
 #include <algorithm>
 #include <cstring>
@@ -50,6 +49,10 @@ constexpr int32_t kMaxSegs = 64;                      // segments of one pass (m
 constexpr int32_t kBuildBatch = 32;                   // groups per product launch
 constexpr int kSlots = 4;                             // pinned staging slots in flight
 constexpr size_t kMaxBytes = 16ull << 30;             // device memory of the buffer and its cache
+constexpr int32_t kMaxParts = 1024;                   // partial sums of split tiles per pass (4 MiB)
+constexpr int32_t kPartPieces = 4;                    // pieces per part: one per wave
+constexpr int32_t kPieceTones = 8;                    // tones per piece of a block with a window edge in the row
+constexpr int32_t kMaxPieces = kMaxParts * kPartPieces;
 
 awg_status hst(hipError_t e)
 {
@@ -95,6 +98,7 @@ struct LineBuf {
     int32_t K = 0, n_groups = 0, n_slots = 0;
     int64_t *d_S = nullptr;
     float *d_Q = nullptr;                 // n_slots period sums
+    float *d_part = nullptr;              // kMaxParts partial tile sums
     void *d_bwork = nullptr;              // product operands of one batch of groups
     size_t bwork_bytes = 0;
     bool s_zeroed = false;
@@ -120,16 +124,24 @@ struct LineBuf {
     std::vector<Line> next;               // per tone: the line at the last sample of the latest pass
     bool next_held = false;               // S holds exactly the versions of `next` (the latest pass completed)
     std::vector<uint8_t> dirty;           // per group: a tone's next line changed in this pass
-    std::vector<Line> l1;                 // per tone: its line before its windows (set where sw != 0)
-    std::vector<uint32_t> sw;             // per tone: first window row when it switches lines there, else 0
+    // per tone whose windows meet the pass (wlo >= 0): its window rows and its
+    // lines before (l1) and after (l2) them
+    std::vector<int32_t> wlo, whi;
+    std::vector<Line> l1, l2;
     struct Win { int32_t k; int32_t lo, hi; };
     std::vector<Win> win;                 // tones whose windows meet the pass: their window rows
-    std::vector<std::pair<int32_t, uint32_t>> gsw;   // distinct (group, switch row) pairs, sorted
+    std::vector<std::pair<int32_t, uint32_t>> gsw;   // distinct (group, row where a line starts or ends), sorted
     std::vector<uint32_t> didx;           // sort order of a part of the direct list
     std::vector<PlbDesc> dsorted;
     std::vector<PlbDesc> build_list;      // kGroupTones lines per version to build
-    std::vector<PlbDesc> direct, dneg;    // window tones, and the negative lines
+    std::vector<PlbDesc> direct;          // the tones whose windows meet the pass
     std::vector<int32_t> key, cnt;        // tile order
+    std::vector<int32_t> blo, bhi;        // per block: the rows its tones are summed on
+    std::vector<int32_t> span;            // the same, interleaved (staged)
+    std::vector<PlbItem> items;           // work items: parts of split tiles, then whole tiles
+    std::vector<PlbPiece> pieces;
+    std::vector<PlbSplit> splits;
+    std::vector<uint8_t> is_split;        // per row
     std::vector<int32_t> build_map;
     std::vector<PlbSeg> segs;
     std::vector<PlbFold> folds;
@@ -147,22 +159,25 @@ namespace {
 
 size_t plb_bytes(uint64_t L, int32_t n_groups, int32_t n_slots)
 {
-    return sizeof(int64_t) * L + sizeof(float) * L * (size_t)n_slots + group_work_bytes(kBuildBatch, kGroupTones, L);
+    return sizeof(int64_t) * L + sizeof(float) * L * (size_t)n_slots + group_work_bytes(kBuildBatch, kGroupTones, L) +
+           sizeof(float) * kRow * kMaxParts;
 }
 
 int32_t groups_of(int32_t K) { return (K + kGroupTones - 1) / kGroupTones; }
 
 // Entries of the largest pass: a version of every group and one per segment
-// (build list), every tone and its negative line (direct list).
-size_t max_entries(const LineBuf &b) { return (size_t)(b.n_groups + kMaxSegs) * kGroupTones + 2 * (size_t)b.K; }
+// (build list), every tone (direct list).
+size_t max_entries(const LineBuf &b) { return (size_t)(b.n_groups + kMaxSegs) * kGroupTones + (size_t)b.K; }
 
-// The part of a staging blob copied as it is: build map, blocks, tile order,
-// segments, folds (at their largest).
+// The part of a staging blob copied as it is: build map, blocks, work items,
+// pieces, split tiles, segments, folds (at their largest).
 size_t raw_cap(const LineBuf &b)
 {
-    const size_t ng = (size_t)b.n_groups, K = (size_t)b.K, nb = ng + kMaxSegs;
+    const size_t ng = (size_t)b.n_groups, K = (size_t)b.K, nb = ng + kMaxSegs, rows = kPiece / kRow;
     return align_up(sizeof(int32_t) * nb, 256) + align_up(sizeof(Block) * (2 * K + 1), 256) +
-           align_up(sizeof(uint32_t) * (kPiece / kRow), 256) + align_up(sizeof(PlbSeg) * kMaxSegs, 256) +
+           align_up(sizeof(PlbItem) * (rows + kMaxParts), 256) + align_up(sizeof(PlbPiece) * kMaxPieces, 256) +
+           align_up(sizeof(int32_t) * 2 * (2 * K + 1), 256) +
+           align_up(sizeof(PlbSplit) * rows, 256) + align_up(sizeof(PlbSeg) * kMaxSegs, 256) +
            align_up(sizeof(PlbFold) * ng, 256);
 }
 
@@ -274,6 +289,7 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
     hipError_t e = hipMalloc(&b.d_S, sizeof(int64_t) * b.L);
     if (e == hipSuccess) e = hipMalloc(&b.d_Q, sizeof(float) * b.L * (size_t)b.n_slots);
     if (e == hipSuccess) e = hipMalloc(&b.d_bwork, b.bwork_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b.d_part, sizeof(float) * kRow * kMaxParts);
     const size_t ch = host_cap(b), cd = dev_cap(b);
     for (auto &sl : b.slots) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
@@ -294,17 +310,24 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
     return AWG_OK;
 }
 
-// Launch order of the tiles, costliest first: a window tile costs 1 per tone
-// (2 with its negative line), a tile where a window opens or closes 3.5 more.
-// Costs are multiples of 1/2, so the order is a counting sort on twice the
-// cost, rows of equal cost in row order.
-void tile_order(LineBuf &b, const awg_plan *p, uint64_t n0, uint64_t rows)
+// Work items of a pass. A row's cost: 1 per window tone summed on it, 3.5 more
+// per window that opens or closes inside it. All
+// rows of a 2^20-sample call run at once (four workgroups per compute unit),
+// so the costliest rows would set the launch time: rows above 1.5 times the
+// mean are split into parts of kPartPieces pieces (one per wave), a piece
+// being a block or, for a block with a window edge in the row, kPieceTones of
+// its tones; the parts run first and write partial sums that the combine
+// kernel adds in part order. Whole rows follow, costliest first. Costs are
+// multiples of 1/2, so the order is a counting sort on twice the cost, rows of
+// equal cost in row order.
+void plan_items(LineBuf &b, const awg_plan *p, uint64_t n0, uint64_t rows)
 {
+    const uint64_t last = n0 + rows * kRow - 1;
+    auto edge_in = [&](uint64_t x) { return x >= n0 && x <= last && (x - n0) % kRow != 0; };
     b.cost.assign(rows + 1, 0.0f);
     for (const LineBuf::Win &w : b.win) {
-        const float c = b.next[w.k] != kNoLine ? 2.0f : 1.0f;
-        b.cost[w.lo] += c;
-        b.cost[w.hi + 1] -= c;
+        b.cost[w.lo] += 1.0f;
+        b.cost[w.hi + 1] -= 1.0f;
     }
     float run = 0.0f;
     for (uint64_t r = 0; r < rows; ++r) {
@@ -317,19 +340,85 @@ void tile_order(LineBuf &b, const awg_plan *p, uint64_t n0, uint64_t rows)
         if (t.shape == AWG_RAMP_NONE && t.ashape == AWG_RAMP_NONE) continue;
         const uint64_t ends[2] = {t.a, t.a + t.n};
         for (uint64_t x : ends)
-            if (x >= n0 && (x - n0) / kRow < rows && (x - n0) % kRow != 0) b.cost[(x - n0) / kRow] += 3.5f;
+            if (edge_in(x)) b.cost[(x - n0) / kRow] += 3.5f;
     }
     b.key.resize(rows);
     int32_t top = 0;
+    double total = 0.0;
     for (uint64_t r = 0; r < rows; ++r) {
         b.key[r] = (int32_t)(2.0f * b.cost[r] + 0.5f);
         top = std::max(top, b.key[r]);
+        total += b.cost[r];
     }
     b.cnt.assign((size_t)top + 2, 0);
     for (uint64_t r = 0; r < rows; ++r) b.cnt[top - b.key[r] + 1]++;
     for (int32_t c = 1; c <= top + 1; ++c) b.cnt[c] += b.cnt[c - 1];
     b.order.resize(rows);
     for (uint64_t r = 0; r < rows; ++r) b.order[b.cnt[top - b.key[r]]++] = (uint32_t)r;
+
+    // the rows each block's tones are summed on, and whether a window of its
+    // (uniform) tones opens or closes inside a row of the pass
+    const int32_t nbk = (int32_t)b.blocks.size() - 1;
+    b.blo.assign(nbk, INT32_MAX);
+    b.bhi.assign(nbk, -1);
+    for (int32_t bi = 0; bi < nbk; ++bi) {
+        const Block &bk = b.blocks[1 + bi];
+        for (uint32_t k = bk.begin; k < bk.begin + bk.count; ++k) {
+            b.blo[bi] = std::min(b.blo[bi], b.direct[k].lo_row);
+            b.bhi[bi] = std::max(b.bhi[bi], b.direct[k].hi_row);
+        }
+    }
+    b.span.resize(2 * (size_t)nbk);
+    for (int32_t bi = 0; bi < nbk; ++bi) {
+        b.span[2 * bi] = b.blo[bi];
+        b.span[2 * bi + 1] = b.bhi[bi];
+    }
+    b.items.clear();
+    b.pieces.clear();
+    b.splits.clear();
+    b.is_split.assign(rows, 0);
+    const float thr = std::max(1.5f * (float)(total / (double)rows), 16.0f);
+    int32_t slots = 0;
+    for (uint64_t oi = 0; oi < rows; ++oi) {
+        const uint32_t r = b.order[oi];
+        if (b.cost[r] <= thr) break;
+        const size_t first = b.pieces.size();
+        for (int32_t bi = 0; bi < nbk; ++bi) {
+            if (b.blo[bi] > (int32_t)r || b.bhi[bi] < (int32_t)r) continue;
+            const Block &bk = b.blocks[1 + bi];
+            bool cut = false;
+            if (bk.flags & kBlockUniform) {
+                const PlbDesc &d = b.direct[bk.begin];
+                if (d.src >= 0) {
+                    const ToneDev &t = p->dev_mirror[d.src];
+                    const uint64_t x0 = t.a, x1 = t.a + t.n;
+                    cut = t.shape != AWG_RAMP_NONE && ((edge_in(x0) && (x0 - n0) / kRow == r) ||
+                                                       (edge_in(x1) && (x1 - n0) / kRow == r));
+                }
+            }
+            if (!cut) {
+                b.pieces.push_back(PlbPiece{(uint32_t)bi, 0, 0});
+                continue;
+            }
+            for (uint32_t o = 0; o < bk.count; o += kPieceTones)
+                b.pieces.push_back(PlbPiece{(uint32_t)bi, (uint16_t)o,
+                                            (uint16_t)std::min<uint32_t>(kPieceTones, bk.count - o)});
+        }
+        const int32_t n_pc = (int32_t)(b.pieces.size() - first);
+        const int32_t P = (n_pc + kPartPieces - 1) / kPartPieces;
+        if (P < 2 || slots + P > kMaxParts) {
+            b.pieces.resize(first);
+            continue;
+        }
+        b.splits.push_back(PlbSplit{r, (uint32_t)slots, (uint32_t)P, 0});
+        for (int32_t q = 0; q < P; ++q)
+            b.items.push_back(PlbItem{r, slots + q, (uint32_t)(first + (size_t)q * kPartPieces),
+                                      (uint32_t)std::min<int32_t>(kPartPieces, n_pc - q * kPartPieces)});
+        slots += P;
+        b.is_split[r] = 1;
+    }
+    for (uint64_t oi = 0; oi < rows; ++oi)
+        if (!b.is_split[b.order[oi]]) b.items.push_back(PlbItem{b.order[oi], -1, 0, 0});
 }
 
 // Order of the direct list: plan tones (ramped ones first, then by window,
@@ -386,14 +475,15 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     b.next_held = false;
     b.next.resize(K);
     b.dirty.assign(b.n_groups, held ? 0 : 1);
+    b.wlo.assign(K, -1);
+    b.whi.resize(K);
     b.l1.resize(K);
-    b.sw.assign(K, 0);
+    b.l2.resize(K);
     b.win.clear();
     b.gsw.clear();
     b.build_list.clear();
     b.build_map.clear();
     b.direct.clear();
-    b.dneg.clear();
     b.segs.clear();
     b.seg_slot.clear();
     b.seg_next.clear();
@@ -403,43 +493,43 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
         const ToneDev &t = p->dev_mirror[i];
         const int32_t k = p->perm[i];
         const bool windowed = t.lo <= t.hi;
-        // still inside its windows at the call's last sample: on no line (the
-        // direct kernel takes it on every row its windows meet)
-        const Line nx = !windowed || last < t.lo ? line_of(t.p0 - kPhaseBias, t.f0, t.amp)
-                        : last > t.hi             ? line_of(t.p1 - kPhaseBias, t.f1, t.amp1)
-                                                  : kNoLine;
+        const bool meets = windowed && t.hi >= n0 && t.lo <= last;
+        const Line nx = meets                        ? kNoLine
+                        : !windowed || last < t.lo ? line_of(t.p0 - kPhaseBias, t.f0, t.amp)
+                                                   : line_of(t.p1 - kPhaseBias, t.f1, t.amp1);
         if (nx != b.next[k]) {
             b.next[k] = nx;
             b.dirty[k / kGroupTones] = 1;
         }
-        if (windowed && t.hi >= n0 && t.lo <= last) {
+        if (meets) {
             const uint64_t lo = t.lo <= n0 ? 0 : (t.lo - n0) / kRow;
             const uint64_t hi = std::min<uint64_t>(rows - 1, (t.hi - n0) / kRow);
             b.win.push_back(LineBuf::Win{k, (int32_t)lo, (int32_t)hi});
-            const Line l1 = line_of(t.p0 - kPhaseBias, t.f0, t.amp);
-            if (lo > 0 && l1 != nx) {
-                b.sw[k] = (uint32_t)lo;
-                b.l1[k] = l1;
-                b.gsw.emplace_back(k / kGroupTones, (uint32_t)lo);
-            }
-            // the tone on its window rows, and its next line (if any) with the
-            // opposite sign
+            b.wlo[k] = (int32_t)lo;
+            b.whi[k] = (int32_t)hi;
+            b.l1[k] = line_of(t.p0 - kPhaseBias, t.f0, t.amp);
+            b.l2[k] = line_of(t.p1 - kPhaseBias, t.f1, t.amp1);
+            // rows before and after the window rows that the call covers
+            if (lo > 0 && b.l1[k] != kNoLine) b.gsw.emplace_back(k / kGroupTones, (uint32_t)lo);
+            if (hi + 1 < rows && b.l2[k] != kNoLine) b.gsw.emplace_back(k / kGroupTones, (uint32_t)(hi + 1));
+            // the tone on its window rows
             b.direct.push_back(PlbDesc{0, 0, 0.0f, i, (int32_t)lo, (int32_t)hi});
-            const double n_samp = (double)(std::min(n0 + hi * kRow + (kRow - 1), last) - (n0 + lo * kRow) + 1);
-            direct_work += n_samp;
-            if (nx != kNoLine) {
-                b.dneg.push_back(line_desc(nx, -1.0f, (int32_t)lo, (int32_t)hi));
-                direct_work += n_samp;
-            }
+            direct_work += (double)(std::min(n0 + hi * kRow + (kRow - 1), last) - (n0 + lo * kRow) + 1);
         }
     }
-    // segments of the pass: one per distinct switch row of each group (counted
-    // before the cache is touched)
+    // segments of the pass: per group, the runs of rows between the rows where
+    // a line starts or ends (at most one more than those rows; counted before
+    // the cache is touched)
     std::sort(b.gsw.begin(), b.gsw.end());
     b.gsw.erase(std::unique(b.gsw.begin(), b.gsw.end()), b.gsw.end());
-    if ((int64_t)b.gsw.size() > kMaxSegs) {
-        *split = true;            // next[] is this range's, not what S holds
-        return AWG_OK;
+    {
+        int64_t n_runs = 0;
+        for (size_t x = 0; x < b.gsw.size(); ++x)
+            n_runs += (x == 0 || b.gsw[x].first != b.gsw[x - 1].first) ? 2 : 1;
+        if (n_runs > kMaxSegs) {
+            *split = true;        // next[] is this range's, not what S holds
+            return AWG_OK;
+        }
     }
     // versions: each group's next version (held by S), and the versions of its
     // rows before the switch rows of its tones
@@ -459,24 +549,40 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
         }
         if (snext < 0) return AWG_E_NOMEM;
         if (b.s_slot[g] != snext) b.fold_slots.emplace_back(snext, b.s_slot[g]);
+        // runs [begin, end) between this group's line rows: each tone whose
+        // windows meet the call is on l1 before its window rows, on l2 after
+        // them, and on none (the direct kernel) on them
+        const size_t g_end = [&] {
+            size_t x = gi;
+            while (x < b.gsw.size() && b.gsw[x].first == g) ++x;
+            return x;
+        }();
+        if (gi == g_end) continue;
         uint32_t begin = 0;
-        for (; gi < b.gsw.size() && b.gsw[gi].first == g; ++gi) {
-            const uint32_t bp = b.gsw[gi].second;
-            // rows [begin, bp): tones that switch at bp or later are still on their first line
+        for (size_t x = gi; x <= g_end; ++x) {
+            const uint32_t end = x < g_end ? b.gsw[x].second : (uint32_t)rows;
+            if (end <= begin) continue;
             b.ver.assign(&b.next[k0], &b.next[k0] + n);
-            for (int32_t i = 0; i < n; ++i)
-                if (b.sw[k0 + i] >= bp) b.ver[i] = b.l1[k0 + i];
-            const int32_t sv = need(b, g, b.ver.data(), n, stamp);
-            if (sv < 0) return AWG_E_NOMEM;
-            b.segs.push_back(PlbSeg{begin, bp - 1, nullptr, nullptr});
-            b.seg_slot.push_back(sv);
-            b.seg_next.push_back(snext);
-            begin = bp;
+            bool differs = false;
+            for (int32_t i = 0; i < n; ++i) {
+                const int32_t k = k0 + i;
+                if (b.wlo[k] < 0) continue;
+                const Line l = (int32_t)begin < b.wlo[k] ? b.l1[k] : ((int32_t)begin > b.whi[k] ? b.l2[k] : kNoLine);
+                b.ver[i] = l;
+                differs = differs || l != kNoLine;
+            }
+            if (differs) {
+                const int32_t sv = need(b, g, b.ver.data(), n, stamp);
+                if (sv < 0) return AWG_E_NOMEM;
+                b.segs.push_back(PlbSeg{begin, end - 1, nullptr, nullptr});
+                b.seg_slot.push_back(sv);
+                b.seg_next.push_back(snext);
+            }
+            begin = end;
         }
+        gi = g_end;
     }
     sort_part(b, p, &b.direct);
-    sort_part(b, p, &b.dneg);
-    b.direct.insert(b.direct.end(), b.dneg.begin(), b.dneg.end());
     {
         const ToneDev lk = line_key();
         build_blocks_by((int32_t)b.direct.size(), (int32_t)b.direct.size(),
@@ -485,19 +591,24 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
                         },
                         &b.blocks);
     }
-    tile_order(b, p, n0, rows);
+    plan_items(b, p, n0, rows);
 
     // host blob: descriptors (build list, then direct list) | raw part
     // device blob: build records | direct records | raw part
-    // raw part: build map | blocks | tile order | segments | folds
+    // raw part: build map | blocks | work items | pieces | split tiles | segments | folds
     const int32_t n_built = (int32_t)b.build_map.size();
     const int32_t n_be = (int32_t)b.build_list.size();
     const int32_t n_direct = (int32_t)b.direct.size();
     const int32_t n_seg = (int32_t)b.segs.size();
     const int32_t n_fold = (int32_t)b.fold_slots.size();
+    const int32_t n_items = (int32_t)b.items.size();
+    const int32_t n_split = (int32_t)b.splits.size();
     const size_t r_b = align_up(sizeof(int32_t) * (size_t)n_built, 256);
     const size_t r_o = r_b + align_up(sizeof(Block) * b.blocks.size(), 256);
-    const size_t r_s = r_o + align_up(sizeof(uint32_t) * rows, 256);
+    const size_t r_p = r_o + align_up(sizeof(PlbItem) * (size_t)n_items, 256);
+    const size_t r_x = r_p + align_up(sizeof(PlbPiece) * b.pieces.size(), 256);
+    const size_t r_y = r_x + align_up(sizeof(PlbSplit) * (size_t)n_split, 256);
+    const size_t r_s = r_y + align_up(sizeof(int32_t) * b.span.size(), 256);
     const size_t r_f = r_s + align_up(sizeof(PlbSeg) * (size_t)n_seg, 256);
     const size_t raw = align_up(r_f + sizeof(PlbFold) * (size_t)n_fold, 16);
     const size_t h_raw = align_up(sizeof(PlbDesc) * (size_t)(n_be + n_direct), 256);
@@ -518,7 +629,10 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     char *hr = hb + h_raw;
     if (n_built) std::memcpy(hr, b.build_map.data(), sizeof(int32_t) * (size_t)n_built);
     std::memcpy(hr + r_b, b.blocks.data(), sizeof(Block) * b.blocks.size());
-    std::memcpy(hr + r_o, b.order.data(), sizeof(uint32_t) * rows);
+    std::memcpy(hr + r_o, b.items.data(), sizeof(PlbItem) * (size_t)n_items);
+    if (!b.pieces.empty()) std::memcpy(hr + r_p, b.pieces.data(), sizeof(PlbPiece) * b.pieces.size());
+    if (n_split) std::memcpy(hr + r_x, b.splits.data(), sizeof(PlbSplit) * (size_t)n_split);
+    if (!b.span.empty()) std::memcpy(hr + r_y, b.span.data(), sizeof(int32_t) * b.span.size());
     PlbSeg *sg = (PlbSeg *)(hr + r_s);
     for (int32_t i = 0; i < n_seg; ++i) {
         sg[i] = b.segs[i];
@@ -552,8 +666,10 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     // S to the call's next versions, then the call
     if (e == hipSuccess) e = launch_plb_fold(p, b.d_S, b.L, (const PlbFold *)(dr + r_f), n_fold, s);
     if (e == hipSuccess)
-        e = launch_plb(p, (const ToneDev *)(db + d_dir), (const Block *)(dr + r_b), (const uint32_t *)(dr + r_o),
-                       n0, count, b.d_S, b.L, (const PlbSeg *)(dr + r_s), n_seg, out_i16, out_f32, s, direct_work);
+        e = launch_plb(p, (const ToneDev *)(db + d_dir), (const Block *)(dr + r_b), (const PlbItem *)(dr + r_o), n_items,
+                       (const PlbPiece *)(dr + r_p), (const int2 *)(dr + r_y), b.d_part, (const PlbSplit *)(dr + r_x),
+                       n_split, n0, count,
+                       b.d_S, b.L, (const PlbSeg *)(dr + r_s), n_seg, out_i16, out_f32, s, direct_work);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     if (e == hipSuccess) {
         slot.used = true;
@@ -600,6 +716,7 @@ void plb_release(awg_plan *p)
     if (b->d_S) (void)hipFree(b->d_S);
     if (b->d_Q) (void)hipFree(b->d_Q);
     if (b->d_bwork) (void)hipFree(b->d_bwork);
+    if (b->d_part) (void)hipFree(b->d_part);
     delete b;
     p->plb = nullptr;
 }
