@@ -418,6 +418,10 @@ awg_status plb_reserve(awg_plan *p, uint32_t method);
 awg_status plb_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32,
                      hipStream_t s);
 void plb_release(awg_plan *p);
+// Tones changed on the host since the line buffer's last pass (device
+// positions): retunes and amplitude ramps tell it, so that its passes need
+// look only at those and at tones whose windows are still ahead or open.
+void plb_note_changed(awg_plan *p, const int32_t *dev_pos, int32_t n);
 size_t plb_bytes_of(const awg_plan *p);
 // Its two launches (mfma.hip, direct.hip). Line entries: bits 0..28 the tone's
 // device position, bits 29..31 the mode (kLine*; kLineNone: no rows, zero amplitude).

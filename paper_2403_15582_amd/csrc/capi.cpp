@@ -583,6 +583,11 @@ static awg_status ensure_retune_slots(awg_plan *p)
 
 static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, hipStream_t s)
 {
+    if (p->plb) {
+        int32_t pos[kSlotRecords];
+        for (int32_t i = 0; i < n_ev; ++i) pos[i] = p->inv[changed[i]];
+        plb_note_changed(p, pos, n_ev);
+    }
     if (!p->ctx) {
         build_blocks(p->dev_mirror, -1, &p->blocks);
         return AWG_OK;
@@ -685,8 +690,10 @@ awg_status awg_synth_static(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d
     if (count == 0) return AWG_OK;
     if ((st = check_out(p, d_out, count, sizeof(int16_t))) != AWG_OK) return st;
     const uint32_t method = p->params.flags & AWG_F_METHOD_MASK;
-    if (method == AWG_F_METHOD_DIRECT)
+    if (method == AWG_F_METHOD_DIRECT) {
+        if ((st = sync_blocks(p, (hipStream_t)hip_stream)) != AWG_OK) return st;
         return hip_status(launch_direct_i16(p, n0, count, d_out, (hipStream_t)hip_stream));
+    }
     return mfma_static(p, method, n0, count, d_out, nullptr, (hipStream_t)hip_stream);
 }
 

@@ -712,11 +712,23 @@ __global__ __launch_bounds__(256) void plb_combine_kernel(const PlbSplit *__rest
     const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
     const uint32_t i0 = threadIdx.x * PER;
     const float *pp = partials + (size_t)sp.first * T + i0;
-    float4 v = *(const float4 *)pp;
-    float y[PER] = {v.x, v.y, v.z, v.w};
-    for (uint32_t q = 1; q < sp.n; ++q) {
-        v = *(const float4 *)(pp + (size_t)q * T);
-        y[0] += v.x; y[1] += v.y; y[2] += v.z; y[3] += v.w;
+    float y[PER] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // loads of up to 8 parts in flight together, added in part order
+    constexpr uint32_t kBatch = 8;
+    for (uint32_t q0 = 0; q0 < sp.n; q0 += kBatch) {
+        float4 u[kBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kBatch; ++q)
+            if (q0 + q < sp.n) u[q] = *(const float4 *)(pp + (size_t)(q0 + q) * T);
+#pragma unroll
+        for (uint32_t q = 0; q < kBatch; ++q) {
+            if (q0 + q >= sp.n) break;
+            if (q0 + q == 0) {
+                y[0] = u[q].x; y[1] = u[q].y; y[2] = u[q].z; y[3] = u[q].w;
+            } else {
+                y[0] += u[q].x; y[1] += u[q].y; y[2] += u[q].z; y[3] += u[q].w;
+            }
+        }
     }
     const PlbIn plb{S_sum, mask, segs, n_seg, sp.row, nullptr, 0, nullptr, nullptr};
     float g[PER];

@@ -51,7 +51,7 @@ constexpr int kSlots = 4;                             // pinned staging slots in
 constexpr size_t kMaxBytes = 16ull << 30;             // device memory of the buffer and its cache
 constexpr int32_t kMaxParts = 1024;                   // partial sums of split tiles per pass (4 MiB)
 constexpr int32_t kPartPieces = 4;                    // pieces per part: one per wave
-constexpr int32_t kPieceTones = 8;                    // tones per piece of a block with a window edge in the row
+constexpr int32_t kPieceTones = 2;                    // tones per piece of a block with a window edge in the row
 constexpr int32_t kMaxPieces = kMaxParts * kPartPieces;
 
 awg_status hst(hipError_t e)
@@ -123,6 +123,13 @@ struct LineBuf {
     // host scratch of one pass
     std::vector<Line> next;               // per tone: the line at the last sample of the latest pass
     bool next_held = false;               // S holds exactly the versions of `next` (the latest pass completed)
+    // a pass looks at every tone (full), or at the tones whose windows were
+    // ahead or open at the previous pass (live) and those changed since
+    bool full = true;
+    uint64_t prev_n0 = 0;
+    std::vector<int32_t> live, live2, changed, todo;   // device positions
+    std::vector<uint32_t> seen;
+    uint32_t seen_gen = 0;
     std::vector<uint8_t> dirty;           // per group: a tone's next line changed in this pass
     // per tone whose windows meet the pass (wlo >= 0): its window rows and its
     // lines before (l1) and after (l2) them
@@ -317,7 +324,9 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
 // mean are split into parts of kPartPieces pieces (one per wave), a piece
 // being a block or, for a block with a window edge in the row, kPieceTones of
 // its tones; the parts run first and write partial sums that the combine
-// kernel adds in part order. Whole rows follow, costliest first. Costs are
+// kernel adds in part order. Whole rows follow, costliest first: those that
+// find no free slot start when the first parts end, so small parts keep the
+// launch near the time of one whole row. Costs are
 // multiples of 1/2, so the order is a counting sort on twice the cost, rows of
 // equal cost in row order.
 void plan_items(LineBuf &b, const awg_plan *p, uint64_t n0, uint64_t rows)
@@ -472,14 +481,44 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     const int32_t stamp = (int32_t)(b.tick & 0x7fffffff);
     // the previous pass's next lines are what S holds only if it completed
     const bool held = b.next_held && (int32_t)b.next.size() == K;
+    const bool incremental = held && !b.full && n0 >= b.prev_n0 && (int32_t)b.wlo.size() == K;
     b.next_held = false;
+    b.full = true;                 // until this pass completes
     b.next.resize(K);
     b.dirty.assign(b.n_groups, held ? 0 : 1);
-    b.wlo.assign(K, -1);
+    if ((int32_t)b.wlo.size() != K) b.wlo.assign(K, -1);
+    for (const LineBuf::Win &w : b.win) b.wlo[w.k] = -1;
     b.whi.resize(K);
     b.l1.resize(K);
     b.l2.resize(K);
     b.win.clear();
+    // the tones to look at, in device order: on a forward call after a
+    // completed pass, those whose windows were ahead or open then and those
+    // changed since (every other tone is on the line it was on, before any
+    // window or after its last one); else every tone
+    b.todo.clear();
+    if (incremental) {
+        b.seen.resize(K);
+        if (++b.seen_gen == 0) {
+            std::fill(b.seen.begin(), b.seen.end(), 0u);
+            b.seen_gen = 1;
+        }
+        for (const int32_t i : b.live) {
+            b.seen[i] = b.seen_gen;
+            b.todo.push_back(i);
+        }
+        for (const int32_t i : b.changed)
+            if (b.seen[i] != b.seen_gen) {
+                b.seen[i] = b.seen_gen;
+                b.todo.push_back(i);
+            }
+        std::sort(b.todo.begin(), b.todo.end());
+    } else {
+        b.todo.resize(K);
+        for (int32_t i = 0; i < K; ++i) b.todo[i] = i;
+    }
+    b.changed.clear();
+    b.live2.clear();
     b.gsw.clear();
     b.build_list.clear();
     b.build_map.clear();
@@ -489,10 +528,11 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     b.seg_next.clear();
     b.fold_slots.clear();
     double direct_work = 0.0;
-    for (int32_t i = 0; i < K; ++i) {              // device order
+    for (const int32_t i : b.todo) {               // device order
         const ToneDev &t = p->dev_mirror[i];
         const int32_t k = p->perm[i];
         const bool windowed = t.lo <= t.hi;
+        if (windowed && t.hi >= n0) b.live2.push_back(i);
         const bool meets = windowed && t.hi >= n0 && t.lo <= last;
         const Line nx = meets                        ? kNoLine
                         : !windowed || last < t.lo ? line_of(t.p0 - kPhaseBias, t.f0, t.amp)
@@ -517,6 +557,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
             direct_work += (double)(std::min(n0 + hi * kRow + (kRow - 1), last) - (n0 + lo * kRow) + 1);
         }
     }
+    b.live.swap(b.live2);
     // segments of the pass: per group, the runs of rows between the rows where
     // a line starts or ends (at most one more than those rows; counted before
     // the cache is touched)
@@ -690,6 +731,8 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     }
     for (const auto &f : b.fold_slots) b.s_slot[b.slot_entry[f.first].group] = f.first;
     b.next_held = true;
+    b.full = false;
+    b.prev_n0 = n0;
     return AWG_OK;
 }
 
@@ -744,6 +787,20 @@ static awg_status plb_state(awg_plan *p, uint32_t method, LineBuf **out)
     }
     *out = p->plb;
     return AWG_OK;
+}
+
+void plb_note_changed(awg_plan *p, const int32_t *dev_pos, int32_t n)
+{
+    LineBuf *b = p->plb;
+    if (!b || n <= 0) return;
+    std::lock_guard<std::mutex> lock(b->mu);
+    if (b->full) return;                          // the next pass looks at every tone anyway
+    if (b->changed.size() + (size_t)n > (size_t)b->K) {
+        b->full = true;
+        b->changed.clear();
+        return;
+    }
+    b->changed.insert(b->changed.end(), dev_pos, dev_pos + n);
 }
 
 awg_status plb_reserve(awg_plan *p, uint32_t method)
