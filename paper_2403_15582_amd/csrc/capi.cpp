@@ -208,11 +208,12 @@ awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d
     Table t;
     t.shape = shape;
     t.n = n;
-    // tag for the kernels: never decreasing, steps below 2^23 (the smooth shapes
-    // step by at most 2^16 + 1)
+    // tag for the kernels: never decreasing, steps below 2^19, so that the
+    // rise over a lane's 16 samples stays below 2^23 (the smooth shapes step by
+    // at most 2^16 + 1)
     t.monotone = true;
     for (uint64_t d = 0; d < n && t.monotone; ++d)
-        t.monotone = h[d + 1] >= h[d] && h[d + 1] - h[d] < (1ull << 23);
+        t.monotone = h[d + 1] >= h[d] && h[d + 1] - h[d] < (1ull << 19);
     hipError_t e = hipMalloc((void **)&t.d_data, (n + 1) * sizeof(uint64_t));
     if (e != hipSuccess) return hip_status(e);
     e = hipMemcpy(t.d_data, h.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);

@@ -46,7 +46,8 @@ __device__ __forceinline__ uint64_t smooth_term(int64_t dF, uint64_t H)
 }
 
 // Table pointers carry a tag in bit 0: set when the table never decreases and
-// its steps are below 2^23, which the incremental smooth path relies on.
+// its steps are below 2^19 (a lane's rise over 16 samples below 2^23), which
+// the incremental smooth paths rely on.
 __device__ __forceinline__ const uint64_t *table_of(const uint64_t *const *tables, uint32_t i)
 {
     return (const uint64_t *)((uintptr_t)tables[i] & ~(uintptr_t)1);
@@ -398,7 +399,7 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                     const bool tagged = table_monotone(tables, r.table);
                     const bool step16 = (bk.flags & kBlockStep16) && tagged;
                     // the lane's first table value and the successive differences
-                    // (non-negative, below 2^23 when tagged)
+                    // (non-negative, below 2^19 when tagged)
                     const uint64_t hv0 = H[0];
                     uint32_t dh[S];
                     if (step16) {
@@ -462,40 +463,41 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                         }
                     } else if (tagged) {
                         // any dF = m 2^16 + r (m = floor(dF / 2^16), 0 <= r < 2^16): the chirp
-                        // term floor(dF H / 2^16) is m H + floor(r H / 2^16). The word steps
-                        // by f0 + m dh as in the loop above plus the carry out of the 16-bit
-                        // fraction q of r H / 2^16 (q + r dh < 2^40), all exact.
-                        uint64_t prev = hv0;
+                        // term floor(dF H / 2^16) is m H + floor(r H / 2^16). With the lane's
+                        // rise dH_s = H[s] - H[0] (below 2^23 for a tagged table) and
+                        // r H[0] = A_hi 2^16 + A_lo, the word of sample s is
+                        //   P + f0 s + m dH_s + floor((A_lo + r dH_s) / 2^16),
+                        //   P = p0 + f0 n + m H[0] + A_hi   (n the lane's first sample),
+                        // every term exact mod 2^64 and no chain from sample to sample.
+                        uint32_t dH[S];
+                        dH[0] = 0;
 #pragma unroll
-                        for (int s = 0; s + 1 < S; ++s) {
-                            const uint64_t cur = H[s + 1];
-                            dh[s] = (uint32_t)(cur - prev);
-                            prev = cur;
-                        }
+                        for (int s = 1; s < S; ++s) dH[s] = (uint32_t)(H[s] - hv0);
                         for (int k = k0; k < k1; ++k) {
-                            const uint64_t p0 = tones[k].p0, f0 = tones[k].f0;
+                            const uint64_t f0 = tones[k].f0;
                             const int64_t dF = tones[k].coef;
                             const float amp = tones[k].amp;
                             const uint64_t m = (uint64_t)(dF >> 16);
                             const uint32_t rr = (uint32_t)dF & 0xffffu;
                             const uint32_t m_lo = (uint32_t)m;
                             const int32_t m_hi = (int32_t)(m >> 32);            // |m_hi| <= 2^15
-                            const uint64_t u0 = (uint64_t)rr * hv0;             // < 2^62
-                            uint64_t ph = p0 + f0 * tile0 + f0 * (uint64_t)j + m * hv0 + (u0 >> 16);
-                            uint32_t q = (uint32_t)u0 & 0xffffu;
+                            const uint64_t A = (uint64_t)rr * hv0;              // < 2^63
+                            // the line part P + f0 s, advanced by f0 per sample
+                            uint64_t ps = tones[k].p0 + f0 * tile0 + f0 * (uint64_t)j + m * hv0 + (A >> 16);
+                            const uint32_t a_lo = (uint32_t)A & 0xffffu;
 #pragma unroll
                             for (int s = 0; s < S; ++s) {
-                                blk[s] = __builtin_fmaf(amp, word_sin(ph), blk[s]);
-                                if (s + 1 < S) {
-                                    const uint64_t t = (uint64_t)rr * dh[s] + q;
-                                    q = (uint32_t)t & 0xffffu;
-                                    const uint64_t lo = (uint64_t)m_lo * dh[s] + (f0 + (t >> 16));
-                                    const uint32_t hi = (uint32_t)(lo >> 32) + (uint32_t)__mul24(m_hi, (int32_t)dh[s]);
-                                    ph += ((uint64_t)hi << 32) | (uint32_t)lo;
-                                }
-                                // one sample at a time: hoisting the r dh products of later
-                                // samples ahead would cost registers (waves) for no gain
-                                __builtin_amdgcn_sched_barrier(0);
+                                const uint64_t lo = (uint64_t)m_lo * dH[s] + ps;
+                                const uint64_t t = (uint64_t)rr * dH[s] + a_lo;                 // < 2^40
+                                const uint32_t c = __builtin_amdgcn_alignbit((uint32_t)(t >> 32), (uint32_t)t, 16u);
+                                // only the word's high half feeds the sine: the low half
+                                // gives its carry
+                                unsigned int cy0, cy1;
+                                (void)__builtin_addc((uint32_t)lo, c, 0u, &cy0);
+                                const uint32_t whi = __builtin_addc((uint32_t)(lo >> 32),
+                                                                    (uint32_t)__mul24(m_hi, (int32_t)dH[s]), cy0, &cy1);
+                                blk[s] = __builtin_fmaf(amp, word_sin((uint64_t)whi << 32), blk[s]);
+                                ps += f0;
                             }
                         }
                     } else {
@@ -551,6 +553,47 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                             const uint32_t hi = (uint32_t)(lo >> 32) + (uint32_t)__mul24(m_hi, (int32_t)dh[s]);
                             ph += ((uint64_t)hi << 32) | (uint32_t)lo;
                         }
+                    }
+                }
+            } else if (r.shape != AWG_RAMP_LINEAR && table_monotone(tables, r.table)) {
+                // a smooth window's edge inside the tile, any dF: the in-window
+                // closed form with the clamped table, H_c(d) = H[clamp(d, 0, N)]:
+                // word = L_s + floor(dF H_c / 2^16), where the line part L_s moves by
+                // f0 (d < N) or f1, the lane's rise dH_s = H_c(d0 + s) - H_c(d0) is
+                // below 2^23, and dF = m 2^16 + r as in the in-window loop
+                const uint64_t n = tile0 + j;
+                const int64_t d0 = (int64_t)(n - r.a), N = (int64_t)r.n;
+                const int32_t s_hi = (int32_t)(d0 >= N ? 0 : (N - d0 >= S ? S : N - d0));
+                const uint64_t *H = table_of(tables, r.table);
+                auto at = [&](int64_t d) { return H[d < 0 ? 0 : (d < N ? d : N)]; };
+                const uint64_t hv0 = at(d0);
+                uint32_t dH[S];
+                dH[0] = 0;
+#pragma unroll
+                for (int s = 1; s < S; ++s) dH[s] = (uint32_t)(at(d0 + s) - hv0);
+                for (int k = k0; k < k1; ++k) {
+                    const uint64_t p0 = tones[k].p0, f0 = tones[k].f0, f1 = tones[k].f1;
+                    const int64_t dF = tones[k].coef;
+                    const float amp = tones[k].amp;
+                    const uint64_t m = (uint64_t)(dF >> 16);
+                    const uint32_t rr = (uint32_t)dF & 0xffffu;
+                    const uint32_t m_lo = (uint32_t)m;
+                    const int32_t m_hi = (int32_t)(m >> 32);            // |m_hi| <= 2^15
+                    const uint64_t A = (uint64_t)rr * hv0;              // < 2^63
+                    uint64_t ps = (d0 < N ? p0 + f0 * n : p0 + f0 * (r.a + r.n) + f1 * (uint64_t)(d0 - N)) + m * hv0 +
+                                  (A >> 16);
+                    const uint32_t a_lo = (uint32_t)A & 0xffffu;
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        const uint64_t lo = (uint64_t)m_lo * dH[s] + ps;
+                        const uint64_t t = (uint64_t)rr * dH[s] + a_lo;                 // < 2^40
+                        const uint32_t c = __builtin_amdgcn_alignbit((uint32_t)(t >> 32), (uint32_t)t, 16u);
+                        unsigned int cy0, cy1;
+                        (void)__builtin_addc((uint32_t)lo, c, 0u, &cy0);
+                        const uint32_t whi = __builtin_addc((uint32_t)(lo >> 32), (uint32_t)__mul24(m_hi, (int32_t)dH[s]),
+                                                            cy0, &cy1);
+                        blk[s] = __builtin_fmaf(amp, word_sin((uint64_t)whi << 32), blk[s]);
+                        ps += s < s_hi ? f0 : f1;
                     }
                 }
             } else {

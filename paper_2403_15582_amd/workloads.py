@@ -255,14 +255,15 @@ def rearrangement(seed=14, K=100, off_frac=0.5, fs_hz=FS_280, f_lo=75e6, f_hi=12
     return w
 
 
-def edge_blocks(seed=15, group=8, fs_hz=FS_280):
+def edge_blocks(seed=15, group=8, fs_hz=FS_280, period_log2=20):
     """Groups of ``group`` tones sharing one window and shape (so the kernels
     take a group's regime once per 1024-sample tile), with window edges at
     chosen offsets inside tiles (first sample, second, just before and after a
     lane's 16 samples, the last sample) and windows of 1 sample up to several
     tiles; each (offset, length) pair is carried by one linear, one
-    raised-cosine and one minimum-jerk group. Bin frequencies (L = 2^20), so
-    every frequency step is a multiple of 2^16 of the word."""
+    raised-cosine and one minimum-jerk group. With bin frequencies (L = 2^20,
+    the default) every frequency step is a multiple of 2^16 of the word;
+    period_log2 = 0 gives free frequencies (any step)."""
     offsets = [0, 1, 7, 15, 16, 17, 500, 1023]
     lens = [1, 2, 5, 15, 16, 17, 1000, 3000]
     specs = [(1024 * (2 + 3 * i) + off, n) for i, (off, n) in enumerate(zip(offsets, lens))]
@@ -280,7 +281,8 @@ def edge_blocks(seed=15, group=8, fs_hz=FS_280):
                 t[k]["ramp_start"] = a
                 t[k]["ramp_len"] = n
                 k += 1
-    return Workload("edge-blocks", fs_hz, 0.0, 20, t, 0, 1024 * (2 + 3 * len(specs)) + 333)
+    return Workload("edge-blocks" if period_log2 else "edge-blocks-free", fs_hz, 0.0, period_log2, t, 0,
+                    1024 * (2 + 3 * len(specs)) + 333)
 
 
 def small_mixed(seed=11, K=24, fs_hz=FS_280, n_total=5000, period_log2=0):

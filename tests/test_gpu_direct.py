@@ -80,13 +80,15 @@ def test_small_mixed_int16_and_f32(n0, count):
     compare(q, y, qo, yo, "small_mixed n0=%d count=%d" % (n0, count))
 
 
+@pytest.mark.parametrize("period_log2", [20, 0])
 @pytest.mark.parametrize("n0,count", [(0, None), (2000, 9000), (1024 * 7 + 15, 1024 * 5 + 3)])
-def test_window_edges_in_shared_blocks(n0, count):
+def test_window_edges_in_shared_blocks(n0, count, period_log2):
     """Groups of tones sharing a window whose edges fall at every awkward
-    offset inside a tile (linear, raised-cosine and minimum-jerk groups with
-    bin frequencies), every sample against the oracle."""
+    offset inside a tile (linear, raised-cosine and minimum-jerk groups), with
+    bin frequencies (smooth steps a multiple of 2^16 of the word) and free ones
+    (any step), every sample against the oracle."""
     torch = need_gpu()
-    w = W.edge_blocks()
+    w = W.edge_blocks(period_log2=period_log2)
     count = w.count - n0 if count is None else count
     op = oracle_plan(w)
     lp = lib_plan(w)
