@@ -20,14 +20,15 @@
 // Each call over [n0, n0 + count) in rows of 1024 samples is evaluated from
 // the call alone (the plan's state and the range), so equal calls give equal
 // samples whatever the plan computed before:
-//  * a tone's "next" line is none (zero amplitude) if its windows meet the
-//    call, else the one it is on over the whole call; each group's version of
-//    next lines is folded into S before the call is summed;
+//  * a tone's "next" line is the one it is on at the call's last row: the
+//    line before or after its windows, or none (zero amplitude) while they are
+//    open there; each group's version of next lines is folded into S before
+//    the call is summed;
 //  * on the rows its windows meet, a tone runs on the direct kernel with its
-//    exact phase (S and the segments hold nothing for it there);
-//  * on the call's rows before and after those, where it is on its line before
-//    or after its windows, the group holds a different version: for each run
-//    of rows with one version the call adds Q(row version) - Q(next version)
+//    exact phase and holds no line;
+//  * on the call's rows where a group holds another version than its next one
+//    (lines before a window, none on window rows, lines after), each run of
+//    rows with one version adds Q(row version) - Q(next version)
 //    ("segments").
 // The direct kernel adds, per tile, S, the segments and its own sum, and rounds.
 #include <algorithm>
@@ -534,9 +535,11 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
         const bool windowed = t.lo <= t.hi;
         if (windowed && t.hi >= n0) b.live2.push_back(i);
         const bool meets = windowed && t.hi >= n0 && t.lo <= last;
-        const Line nx = meets                        ? kNoLine
-                        : !windowed || last < t.lo ? line_of(t.p0 - kPhaseBias, t.f0, t.amp)
-                                                   : line_of(t.p1 - kPhaseBias, t.f1, t.amp1);
+        // the line the tone is on at the call's last row: none while its
+        // windows are open there (it runs on the direct kernel)
+        const Line nx = !windowed || last < t.lo ? line_of(t.p0 - kPhaseBias, t.f0, t.amp)
+                        : last > t.hi             ? line_of(t.p1 - kPhaseBias, t.f1, t.amp1)
+                                                  : kNoLine;
         if (nx != b.next[k]) {
             b.next[k] = nx;
             b.dirty[k / kGroupTones] = 1;
@@ -549,8 +552,10 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
             b.whi[k] = (int32_t)hi;
             b.l1[k] = line_of(t.p0 - kPhaseBias, t.f0, t.amp);
             b.l2[k] = line_of(t.p1 - kPhaseBias, t.f1, t.amp1);
-            // rows before and after the window rows that the call covers
-            if (lo > 0 && b.l1[k] != kNoLine) b.gsw.emplace_back(k / kGroupTones, (uint32_t)lo);
+            // rows before and after the window rows that the call covers; a
+            // tone whose next line is l2 also needs its window rows' run (its
+            // group has a run even when those rows are all of the call's)
+            if ((lo > 0 && b.l1[k] != kNoLine) || nx != kNoLine) b.gsw.emplace_back(k / kGroupTones, (uint32_t)lo);
             if (hi + 1 < rows && b.l2[k] != kNoLine) b.gsw.emplace_back(k / kGroupTones, (uint32_t)(hi + 1));
             // the tone on its window rows
             b.direct.push_back(PlbDesc{0, 0, 0.0f, i, (int32_t)lo, (int32_t)hi});
@@ -604,13 +609,13 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
             const uint32_t end = x < g_end ? b.gsw[x].second : (uint32_t)rows;
             if (end <= begin) continue;
             b.ver.assign(&b.next[k0], &b.next[k0] + n);
-            bool differs = false;
+            bool differs = false;          // from the group's next version
             for (int32_t i = 0; i < n; ++i) {
                 const int32_t k = k0 + i;
                 if (b.wlo[k] < 0) continue;
                 const Line l = (int32_t)begin < b.wlo[k] ? b.l1[k] : ((int32_t)begin > b.whi[k] ? b.l2[k] : kNoLine);
                 b.ver[i] = l;
-                differs = differs || l != kNoLine;
+                differs = differs || l != b.next[k];
             }
             if (differs) {
                 const int32_t sv = need(b, g, b.ver.data(), n, stamp);
