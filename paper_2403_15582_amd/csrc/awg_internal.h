@@ -378,12 +378,14 @@ struct PlbSplit {
 // The line-buffer launch: n_items work items, then (n_split > 0) one combine
 // workgroup per split tile. d_partials holds 1024 floats per partial slot;
 // d_span[i] = (first row, last row) the tones of block i are summed on.
+// n_fold > 0 (only when count == L, so that each m = n mod L is one thread's):
+// the folds d_folds[0 .. n_fold) are applied to S by the kernels that read it.
 hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const PlbItem *d_items,
                       int32_t n_items, const PlbPiece *d_pieces, const int2 *d_span, float *d_partials,
                       const PlbSplit *d_splits,
-                      int32_t n_split, uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L,
-                      const PlbSeg *d_segs, int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s,
-                      double work);
+                      int32_t n_split, uint64_t n0, uint64_t count, int64_t *d_S, uint64_t L,
+                      const PlbSeg *d_segs, int32_t n_seg, const PlbFold *d_folds, int32_t n_fold,
+                      int16_t *out_i16, float *out_f32, hipStream_t s, double work);
 hipError_t launch_plb_fold(const awg_plan *p, int64_t *d_S, uint64_t L, const PlbFold *d_folds, int32_t n_fold,
                            hipStream_t s);
 hipError_t launch_plb_zero(int64_t *d_S, uint64_t L, hipStream_t s);

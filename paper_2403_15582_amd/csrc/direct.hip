@@ -255,7 +255,7 @@ struct HybridIn {
 // tone of a split-flagged block is summed only on the tiles in [t.lo, t.hi]
 // (window tiles and lines alike). Segments are applied in list order.
 struct PlbIn {
-    const int64_t *S;            // nullptr: not the line-buffer path
+    int64_t *S;                  // nullptr: not the line-buffer path
     uint64_t mask;               // L - 1
     const PlbSeg *segs;
     int32_t n_seg;
@@ -269,7 +269,42 @@ struct PlbIn {
     // per block: the first and last row its tones are summed on (blocks whose
     // span misses this row are skipped whole)
     const int2 *span;
+    // folds applied here, when the launch covers each m = n mod L exactly once:
+    // the thread that reads S[m] first adds them and writes S[m] back
+    const PlbFold *folds;
+    int32_t n_fold;
 };
+
+// fix(x) = x * 2^32 rounded to an integer (the fixed point of S)
+__device__ __forceinline__ int64_t plb_fix(float x) { return (int64_t)__builtin_rint((double)x * 0x1p32); }
+
+// sum over the folds f of fix(q_new_f[m]) - fix(q_old_f[m]) at four consecutive m
+// (loads of up to four folds in flight together; integer sums, so the order of
+// the terms does not matter)
+__device__ __forceinline__ void plb_fold4(const PlbFold *folds, int32_t n_fold, uint64_t m0, int64_t (&acc)[4])
+{
+    constexpr int32_t kBatch = 4;
+    for (int32_t f0 = 0; f0 < n_fold; f0 += kBatch) {
+        float4 a[kBatch], b[kBatch];
+#pragma unroll
+        for (int32_t j = 0; j < kBatch; ++j) {
+            a[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            b[j] = a[j];
+            if (f0 + j < n_fold) {
+                const PlbFold fd = folds[f0 + j];
+                a[j] = *(const float4 *)(fd.q_new + m0);
+                if (fd.q_old) b[j] = *(const float4 *)(fd.q_old + m0);
+            }
+        }
+#pragma unroll
+        for (int32_t j = 0; j < kBatch; ++j) {
+            acc[0] += plb_fix(a[j].x) - plb_fix(b[j].x);
+            acc[1] += plb_fix(a[j].y) - plb_fix(b[j].y);
+            acc[2] += plb_fix(a[j].z) - plb_fix(b[j].z);
+            acc[3] += plb_fix(a[j].w) - plb_fix(b[j].w);
+        }
+    }
+}
 
 // The line tones of samples tile0 + i0 .. i0 + PER - 1: S and the segments'
 // group differences at m = n mod L, in list order.
@@ -279,7 +314,14 @@ __device__ __forceinline__ void plb_lines(const PlbIn &plb, uint64_t tile0, uint
 {
     const uint64_t m0 = (tile0 + i0) & plb.mask;
     if (PER == 4 && i0 + PER <= valid && (m0 & 3) == 0 && m0 + 3 <= plb.mask) {
-        const longlong2 sa = *(const longlong2 *)(plb.S + m0), sb = *(const longlong2 *)(plb.S + m0 + 2);
+        longlong2 sa = *(const longlong2 *)(plb.S + m0), sb = *(const longlong2 *)(plb.S + m0 + 2);
+        if (plb.n_fold > 0) {
+            int64_t acc[4] = {0, 0, 0, 0};
+            plb_fold4(plb.folds, plb.n_fold, m0, acc);
+            sa.x += acc[0]; sa.y += acc[1]; sb.x += acc[2]; sb.y += acc[3];
+            *(longlong2 *)(plb.S + m0) = sa;
+            *(longlong2 *)(plb.S + m0 + 2) = sb;
+        }
         g[0] = (float)((double)sa.x * 0x1p-32);
         g[1] = (float)((double)sa.y * 0x1p-32);
         g[2] = (float)((double)sb.x * 0x1p-32);
@@ -294,7 +336,16 @@ __device__ __forceinline__ void plb_lines(const PlbIn &plb, uint64_t tile0, uint
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const uint64_t m = (m0 + (uint64_t)e) & plb.mask;
-            g[e] = (float)((double)plb.S[m] * 0x1p-32);
+            int64_t v = plb.S[m];
+            if (plb.n_fold > 0 && i0 + e < valid) {       // samples past the call: another thread's m
+                for (int32_t f = 0; f < plb.n_fold; ++f) {
+                    const PlbFold fd = plb.folds[f];
+                    v += plb_fix(fd.q_new[m]);
+                    if (fd.q_old) v -= plb_fix(fd.q_old[m]);
+                }
+                plb.S[m] = v;
+            }
+            g[e] = (float)((double)v * 0x1p-32);
         }
         for (int32_t q = 0; q < plb.n_seg; ++q) {
             const PlbSeg sg = plb.segs[q];
@@ -319,7 +370,7 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
                                            const uint64_t *const *__restrict__ tables, uint64_t tile0,
                                            uint32_t valid, void *__restrict__ out, float (*part)[kLanes * S],
                                            const HybridIn &hyb = HybridIn{0, nullptr, 0}, uint32_t ostride = 1,
-                                           const PlbIn &plb = PlbIn{nullptr, 0, nullptr, 0, 0, nullptr, 0, nullptr, nullptr})
+                                           const PlbIn &plb = PlbIn{nullptr, 0, nullptr, 0, 0, nullptr, 0, nullptr, nullptr, nullptr, 0})
 {
     constexpr int T = kLanes * S;                 // samples per tile
     const uint32_t lane = threadIdx.x & 63u;
@@ -743,10 +794,11 @@ template <int S, bool F32OUT>
 __global__ __launch_bounds__(256) void plb_kernel(const ToneDev *__restrict__ tones, const Block *__restrict__ blocks,
                                                   const PlbItem *__restrict__ items,
                                                   const uint64_t *const *__restrict__ tables, uint64_t n0,
-                                                  uint64_t count, void *__restrict__ out, const int64_t *__restrict__ S_sum,
+                                                  uint64_t count, void *__restrict__ out, int64_t *__restrict__ S_sum,
                                                   uint64_t mask, const PlbSeg *__restrict__ segs, int32_t n_seg,
                                                   const PlbPiece *__restrict__ pieces, float *__restrict__ partials,
-                                                  const int2 *__restrict__ span)
+                                                  const int2 *__restrict__ span, const PlbFold *__restrict__ folds,
+                                                  int32_t n_fold)
 {
     constexpr int T = kLanes * S;
     __shared__ float part[kWaves][T];
@@ -758,7 +810,7 @@ __global__ __launch_bounds__(256) void plb_kernel(const ToneDev *__restrict__ to
     void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
     const bool is_part = item.part >= 0;
     const PlbIn plb{S_sum, mask, segs, n_seg, row, is_part ? pieces + item.first : nullptr, item.count,
-                    is_part ? partials + (size_t)item.part * T : nullptr, span};
+                    is_part ? partials + (size_t)item.part * T : nullptr, span, folds, n_fold};
     synth_tile<S, F32OUT, false, true, true>(tones, blocks, tables, n0 + rel, valid, o, part,
                                              HybridIn{0, nullptr, 0}, 1, plb);
 }
@@ -770,8 +822,9 @@ template <bool F32OUT>
 __global__ __launch_bounds__(256) void plb_combine_kernel(const PlbSplit *__restrict__ splits,
                                                           const float *__restrict__ partials, uint64_t n0,
                                                           uint64_t count, void *__restrict__ out,
-                                                          const int64_t *__restrict__ S_sum, uint64_t mask,
-                                                          const PlbSeg *__restrict__ segs, int32_t n_seg)
+                                                          int64_t *__restrict__ S_sum, uint64_t mask,
+                                                          const PlbSeg *__restrict__ segs, int32_t n_seg,
+                                                          const PlbFold *__restrict__ folds, int32_t n_fold)
 {
     constexpr int T = kTileSamples;
     constexpr int PER = T / 256;
@@ -799,7 +852,7 @@ __global__ __launch_bounds__(256) void plb_combine_kernel(const PlbSplit *__rest
             }
         }
     }
-    const PlbIn plb{S_sum, mask, segs, n_seg, sp.row, nullptr, 0, nullptr, nullptr};
+    const PlbIn plb{S_sum, mask, segs, n_seg, sp.row, nullptr, 0, nullptr, nullptr, folds, n_fold};
     float g[PER];
     plb_lines<PER>(plb, n0 + rel, i0, valid, g);
 #pragma unroll
@@ -823,21 +876,7 @@ __global__ __launch_bounds__(256) void plb_fold_kernel(int64_t *__restrict__ S_s
     const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (i0 >= L) return;
     int64_t acc[4] = {0, 0, 0, 0};
-    for (int32_t f = 0; f < n_fold; ++f) {
-        const PlbFold fd = folds[f];
-        const float4 a = *(const float4 *)(fd.q_new + i0);
-        acc[0] += (int64_t)__builtin_rint((double)a.x * 0x1p32);
-        acc[1] += (int64_t)__builtin_rint((double)a.y * 0x1p32);
-        acc[2] += (int64_t)__builtin_rint((double)a.z * 0x1p32);
-        acc[3] += (int64_t)__builtin_rint((double)a.w * 0x1p32);
-        if (fd.q_old) {
-            const float4 b = *(const float4 *)(fd.q_old + i0);
-            acc[0] -= (int64_t)__builtin_rint((double)b.x * 0x1p32);
-            acc[1] -= (int64_t)__builtin_rint((double)b.y * 0x1p32);
-            acc[2] -= (int64_t)__builtin_rint((double)b.z * 0x1p32);
-            acc[3] -= (int64_t)__builtin_rint((double)b.w * 0x1p32);
-        }
-    }
+    plb_fold4(folds, n_fold, i0, acc);
 #pragma unroll
     for (int e = 0; e < 4; ++e) S_sum[i0 + e] += acc[e];
 }
@@ -1019,9 +1058,9 @@ hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const
 hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const PlbItem *d_items,
                       int32_t n_items, const PlbPiece *d_pieces, const int2 *d_span, float *d_partials,
                       const PlbSplit *d_splits,
-                      int32_t n_split, uint64_t n0, uint64_t count, const int64_t *d_S, uint64_t L,
-                      const PlbSeg *d_segs, int32_t n_seg, int16_t *out_i16, float *out_f32, hipStream_t s,
-                      double work)
+                      int32_t n_split, uint64_t n0, uint64_t count, int64_t *d_S, uint64_t L,
+                      const PlbSeg *d_segs, int32_t n_seg, const PlbFold *d_folds, int32_t n_fold,
+                      int16_t *out_i16, float *out_f32, hipStream_t s, double work)
 {
     constexpr uint64_t T = kLanes * kS;
     static_assert(T == kTileSamples, "line-buffer rows are direct-kernel tiles");
@@ -1029,27 +1068,28 @@ hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_
     if (tiles == 0) return hipSuccess;
     if (tiles > kMaxTilesPerLaunch || L < T || (L & (L - 1)) != 0 || n_items <= 0 || n_split < 0)
         return hipErrorInvalidValue;
+    if (n_fold > 0 && count != L) return hipErrorInvalidValue;      // each m once: see PlbIn
     {
         ProfScope prof(p->ctx, s, out_f32 ? "plb_kernel_f32" : "plb_kernel");
         prof.add_work(work);
         if (out_f32)
             prof.launch(plb_kernel<kS, true>, dim3((uint32_t)n_items), dim3(256), 0, d_tones, d_blocks, d_items,
                         p->d_table_ptrs, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg, d_pieces, d_partials,
-                        d_span);
+                        d_span, d_folds, n_fold);
         else
             prof.launch(plb_kernel<kS, false>, dim3((uint32_t)n_items), dim3(256), 0, d_tones, d_blocks, d_items,
                         p->d_table_ptrs, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg, d_pieces, d_partials,
-                        d_span);
+                        d_span, d_folds, n_fold);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess || n_split == 0) return e;
     }
     ProfScope prof(p->ctx, s, "plb_combine_kernel");
     if (out_f32)
         prof.launch(plb_combine_kernel<true>, dim3((uint32_t)n_split), dim3(256), 0, d_splits,
-                    (const float *)d_partials, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg);
+                    (const float *)d_partials, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg, d_folds, n_fold);
     else
         prof.launch(plb_combine_kernel<false>, dim3((uint32_t)n_split), dim3(256), 0, d_splits,
-                    (const float *)d_partials, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg);
+                    (const float *)d_partials, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg, d_folds, n_fold);
     return hipGetLastError();
 }
 

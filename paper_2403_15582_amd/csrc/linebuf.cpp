@@ -709,13 +709,15 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
         e = launch_group_sums(p, b.method, (const ToneDev *)db + (size_t)i * kGroupTones, nb, kGroupTones, b.L,
                               b.d_bwork, b.d_Q, (const int32_t *)dr + i, s, work);
     }
-    // S to the call's next versions, then the call
-    if (e == hipSuccess) e = launch_plb_fold(p, b.d_S, b.L, (const PlbFold *)(dr + r_f), n_fold, s);
+    // S to the call's next versions, then the call; a call of exactly one
+    // period folds in the kernels that read S (each m is read once)
+    const bool fused = count == b.L;
+    if (e == hipSuccess && !fused) e = launch_plb_fold(p, b.d_S, b.L, (const PlbFold *)(dr + r_f), n_fold, s);
     if (e == hipSuccess)
         e = launch_plb(p, (const ToneDev *)(db + d_dir), (const Block *)(dr + r_b), (const PlbItem *)(dr + r_o), n_items,
                        (const PlbPiece *)(dr + r_p), (const int2 *)(dr + r_y), b.d_part, (const PlbSplit *)(dr + r_x),
-                       n_split, n0, count,
-                       b.d_S, b.L, (const PlbSeg *)(dr + r_s), n_seg, out_i16, out_f32, s, direct_work);
+                       n_split, n0, count, b.d_S, b.L, (const PlbSeg *)(dr + r_s), n_seg,
+                       (const PlbFold *)(dr + r_f), fused ? n_fold : 0, out_i16, out_f32, s, direct_work);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     if (e == hipSuccess) {
         slot.used = true;

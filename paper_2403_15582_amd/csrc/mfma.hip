@@ -117,13 +117,10 @@ __device__ __forceinline__ bool entry_line(const ToneDev *__restrict__ tones, co
 // groups from g_base on); the group is the workgroup's y index, so the
 // entries' words are uniform (scalar loads). rows = 32 rb_pad is a multiple of 256.
 template <typename T, bool ENTRIES>
-__global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ tones,
-                                                    const uint32_t *__restrict__ entries, int32_t n_entries,
-                                                    int32_t g_base, uint64_t n0, uint64_t mcols, int32_t rb_pad,
-                                                    T *__restrict__ a_hi, T *__restrict__ a_lo)
+__device__ __forceinline__ void gen_a_at(const ToneDev *__restrict__ tones, const uint32_t *__restrict__ entries,
+                                         int32_t n_entries, int32_t g, int64_t c, uint64_t n0, uint64_t mcols,
+                                         int32_t rb_pad, T *__restrict__ a_hi, T *__restrict__ a_lo)
 {
-    const int32_t g = g_base + (int32_t)blockIdx.y;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n = n0 + (uint64_t)c * mcols;
     typename Split<T>::vec hv, lv;
 #pragma unroll
@@ -148,16 +145,24 @@ __global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ 
     ((typename Split<T>::vec *)a_lo)[off] = lv;
 }
 
+template <typename T, bool ENTRIES>
+__global__ __launch_bounds__(256) void gen_a_kernel(const ToneDev *__restrict__ tones,
+                                                    const uint32_t *__restrict__ entries, int32_t n_entries,
+                                                    int32_t g_base, uint64_t n0, uint64_t mcols, int32_t rb_pad,
+                                                    T *__restrict__ a_hi, T *__restrict__ a_lo)
+{
+    gen_a_at<T, ENTRIES>(tones, entries, n_entries, g_base + (int32_t)blockIdx.y,
+                         (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n0, mcols, rb_pad, a_hi, a_lo);
+}
+
 // B operand: one thread per (column m, group g of 4 entries); the frequency
 // word of the entry's line (its rows do not matter here). With kb_list the
 // groups are those of the listed k-blocks only (2 groups per k-block).
 template <typename T>
-__global__ __launch_bounds__(256) void gen_b_kernel(const ToneDev *__restrict__ tones,
-                                                    const uint32_t *__restrict__ entries, int32_t n_entries,
-                                                    int32_t n_groups, int32_t cb_n, T *__restrict__ b_hi,
-                                                    T *__restrict__ b_lo, const int32_t *__restrict__ kb_list = nullptr)
+__device__ __forceinline__ void gen_b_at(const ToneDev *__restrict__ tones, const uint32_t *__restrict__ entries,
+                                         int32_t n_entries, int32_t n_groups, int32_t cb_n, T *__restrict__ b_hi,
+                                         T *__restrict__ b_lo, const int32_t *__restrict__ kb_list, int64_t gid)
 {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cols = (int64_t)cb_n * 32;
     if (gid >= cols * n_groups) return;
     const int32_t gi = (int32_t)(gid / cols);
@@ -188,6 +193,36 @@ __global__ __launch_bounds__(256) void gen_b_kernel(const ToneDev *__restrict__ 
     const int64_t off = (((int64_t)kb * cb_n + cb) * 64 + lane);
     ((typename Split<T>::vec *)b_hi)[off] = hv;
     ((typename Split<T>::vec *)b_lo)[off] = lv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gen_b_kernel(const ToneDev *__restrict__ tones,
+                                                    const uint32_t *__restrict__ entries, int32_t n_entries,
+                                                    int32_t n_groups, int32_t cb_n, T *__restrict__ b_hi,
+                                                    T *__restrict__ b_lo, const int32_t *__restrict__ kb_list = nullptr)
+{
+    gen_b_at<T>(tones, entries, n_entries, n_groups, cb_n, b_hi, b_lo, kb_list,
+                (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Both operands of the group sums in one launch: workgroups [0, a_blocks) make
+// A (a_per_group of them per group of 4 tones, rows of mcols samples from 0),
+// the rest make B. Each part runs the same code as gen_a_kernel / gen_b_kernel.
+template <typename T>
+__global__ __launch_bounds__(256) void gen_ab_kernel(const ToneDev *__restrict__ tones, int32_t n_entries,
+                                                     uint32_t a_per_group, uint32_t a_blocks, uint64_t mcols,
+                                                     int32_t rb_pad, T *__restrict__ a_hi, T *__restrict__ a_lo,
+                                                     int32_t n_groups, int32_t cb_n, T *__restrict__ b_hi,
+                                                     T *__restrict__ b_lo)
+{
+    const uint32_t bx = blockIdx.x;
+    if (bx < a_blocks) {
+        gen_a_at<T, false>(tones, nullptr, n_entries, (int32_t)(bx / a_per_group),
+                           (int64_t)(bx % a_per_group) * blockDim.x + threadIdx.x, 0, mcols, rb_pad, a_hi, a_lo);
+    } else {
+        gen_b_at<T>(tones, nullptr, n_entries, n_groups, cb_n, b_hi, b_lo, nullptr,
+                    (int64_t)(bx - a_blocks) * blockDim.x + threadIdx.x);
+    }
 }
 
 template <typename T>
@@ -710,16 +745,15 @@ static hipError_t group_run(const awg_plan *p, const ToneDev *d_list, int32_t n_
     const int32_t n_entries = n_built * group_tones;
     hipError_t e;
     {
-        ProfScope prof(p->ctx, s, f16 ? "plb_gen_a_f16" : "plb_gen_a_bf16");
-        launch_gen_a<T>(prof, d_list, nullptr, n_entries, 2 * g.kb_n, 0, kTileSamples, g.rb_pad, a_hi, a_lo);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    {
-        const int64_t b_threads = (int64_t)g.cb_n * 32 * (2 * g.kb_n);
-        ProfScope prof(p->ctx, s, f16 ? "plb_gen_b_f16" : "plb_gen_b_bf16");
-        prof.launch(gen_b_kernel<T>, dim3((uint32_t)((b_threads + 255) / 256)), dim3(256), 0, d_list,
-                    (const uint32_t *)nullptr, n_entries, 2 * g.kb_n, g.cb_n, b_hi, b_lo, (const int32_t *)nullptr);
+        // A: 2 kb_n groups of 4 tones x rb_pad * 32 rows; B: the same groups x cb_n * 32 columns
+        const int64_t a_per_group = (int64_t)g.rb_pad * 32 / 256;
+        const int64_t a_blocks = a_per_group * (2 * g.kb_n);
+        const int64_t b_blocks = ((int64_t)g.cb_n * 32 * (2 * g.kb_n) + 255) / 256;
+        if (a_blocks + b_blocks > INT32_MAX) return hipErrorInvalidValue;
+        ProfScope prof(p->ctx, s, f16 ? "plb_gen_f16" : "plb_gen_bf16");
+        prof.launch(gen_ab_kernel<T>, dim3((uint32_t)(a_blocks + b_blocks)), dim3(256), 0, d_list, n_entries,
+                    (uint32_t)a_per_group, (uint32_t)a_blocks, (uint64_t)kTileSamples, g.rb_pad, a_hi, a_lo,
+                    2 * g.kb_n, g.cb_n, b_hi, b_lo);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;

@@ -16,6 +16,14 @@ typedef __int128 i128;
 // x = m * 2^e with m < 2^53 an integer (x > 0, finite).
 static void decompose(double x, uint64_t *m, int *e)
 {
+    uint64_t bits;
+    std::memcpy(&bits, &x, sizeof bits);
+    const int be = (int)((bits >> 52) & 0x7ff);
+    if (be != 0 && be != 0x7ff) {                  // normal: the stored fields
+        *m = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+        *e = be - 1075;
+        return;
+    }
     int ex;
     double fr = std::frexp(x, &ex);
     *m = (uint64_t)std::ldexp(fr, 53);
@@ -30,6 +38,31 @@ bool rne_ratio_shift(double num, double den, int shift, uint64_t *out)
     decompose(num, &mn, &en);
     decompose(den, &md, &ed);
     const int e = en - ed + shift;           // value = mn * 2^e / md
+    // usual case: the FP64 quotient as a first guess, settled exactly: q is
+    // nint(value) iff (2q - 1) md <= 2 mn 2^e <= (2q + 1) md (ties to even);
+    // products, no 128-bit division
+    if (e >= 0 && e <= 70) {
+        double scale = 0.0;                        // 2^shift
+        if (shift >= -1022 && shift <= 1023) {
+            const uint64_t sb = (uint64_t)(shift + 1023) << 52;
+            std::memcpy(&scale, &sb, sizeof scale);
+        }
+        const double v = (num / den) * scale;
+        if (scale > 0.0 && v >= 0.0 && v < 0x1p63) {
+            const u128 A = (u128)mn << (e + 1), D = md;
+            uint64_t q = (uint64_t)(v + 0.5);
+            for (int it = 0; it < 4; ++it) {
+                const u128 hi = ((u128)q * 2 + 1) * D;
+                if (A > hi || (A == hi && (q & 1))) { ++q; continue; }
+                if (q > 0) {
+                    const u128 lo = ((u128)q * 2 - 1) * D;
+                    if (A < lo || (A == lo && (q & 1))) { --q; continue; }
+                }
+                *out = q;
+                return true;
+            }
+        }
+    }
     u128 n, d;
     if (e >= 0) {
         if (e > 74) return false;            // value >= 2^73
@@ -87,6 +120,14 @@ uint64_t phase_word(double turns)
 // nint(num / den), ties to even, den >= 1.
 int64_t rne_div(int64_t num, uint64_t den)
 {
+    if (den <= (uint64_t)INT64_MAX) {               // the same in 64-bit arithmetic
+        const int64_t d = (int64_t)den;
+        int64_t q = num / d, r = num % d;
+        if (r < 0) { q -= 1; r += d; }               // floor division, r in [0, d)
+        const uint64_t r2 = (uint64_t)r * 2;         // < 2^64
+        if (r2 > den || (r2 == den && (q & 1))) q += 1;
+        return q;
+    }
     const i128 d = (i128)den;
     i128 q = (i128)num / d, r = (i128)num % d;
     if (r < 0) { q -= 1; r += d; }                   // floor division, r in [0, d)

@@ -156,6 +156,46 @@ def test_array_group_chirps_stream_against_direct_and_oracle(method):
     say("array hybrid: all %d chunks within %d LSB of the direct method" % (n_chunks, TOL_Q))
 
 
+@pytest.mark.parametrize("method", [F16, BF16])
+def test_one_period_calls_at_odd_offsets(method):
+    """Calls of exactly one period (2^20 samples) that start off a row and off a
+    multiple of four, so that the folds of S run in the kernels that read it on
+    the per-sample path, and the call wraps round m = L - 1: every sample against
+    the direct method, a sample of each against the oracle, and the first call
+    repeated after the second (S and the cache brought back) gives the same codes."""
+    torch = need_gpu()
+    w = W.array_group_chirps(K=2000, seconds=0.012)
+    L = 1 << w.period_log2
+    hp, dp = _plans(w, method)
+    op = words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones, build_tables=False)
+    starts = [12345, 12345 + L + 999]
+    batch = []
+    for k, a, n, shape, f in sorted(w.retunes, key=lambda e: e[1]):
+        if a < starts[-1] + L:
+            batch.append((k, shape, a, n, f))
+            op.add_ramp(k, a, n, shape, f)
+    hp.retune(batch)
+    dp.retune(batch)
+    first = None
+    for j, n0 in enumerate(starts + starts[:1]):
+        say("one-period hybrid call method=%d n0=%d count=%d" % (method, n0, L))
+        q = to_np(hp.synth_chirp(n0, L))
+        y = to_np(hp.synth_f32(n0, L, method=method))
+        qd = to_np(dp.synth_chirp(n0, L))
+        torch.cuda.synchronize()
+        assert int(np.abs(q.astype(np.int32) - qd).max()) <= TOL_Q, n0
+        if j == 0:
+            first = q
+        elif j == len(starts):
+            assert np.array_equal(q, first)
+            continue
+        rng = np.random.default_rng(n0)
+        wrap = L - (n0 % L)                    # the sample at m = 0
+        ns = np.unique(np.concatenate([rng.integers(0, L, 500), [0, 1, 2, 3, L - 1, wrap - 1, wrap]]))
+        qo, yo = csynth.synth_at(op, ns + n0)
+        compare(q[ns], y[ns], qo, yo, "one-period call at n0=%d (sampled %d)" % (n0, len(ns)))
+
+
 def test_static_plan_chirp_call_uses_matrix_cores():
     torch = need_gpu()
     w = W.static_100tone_chunk()

@@ -82,6 +82,38 @@ def test_plan_words_random_extremes():
         _compare_words(W.Workload("rand", fs, 1.5, 40, t))
 
 
+@pytest.mark.parametrize("period_log2", [0, 10, 20, 24])
+def test_frequency_words_at_exact_ties(period_log2):
+    """Frequencies whose word is exactly half-way between two integers (fs a
+    power of two, f = (k + 1/2) fs / 2^s with s the word's shift), and the
+    doubles either side of them: the rounding to nearest, ties to even, of
+    Eq. (4) for both parities of k, against the oracle's tuning word."""
+    fs = 2.0 ** 28
+    s = period_log2 if period_log2 else 64
+    top = (1 << (period_log2 - 1)) - 2 if period_log2 else (1 << 52)
+    rng = np.random.default_rng(period_log2 + 1)
+    ks = np.concatenate([[1, 2, 3, top - 1, top], rng.integers(1, top, 27)])
+    f = []
+    for k in ks.tolist():
+        x = (k + 0.5) * 2.0 ** (28 - s)
+        f += [x, np.nextafter(x, 0.0), np.nextafter(x, np.inf)]
+    t = awg.make_tones(len(f))
+    t["f_start_hz"] = f
+    t["f_end_hz"] = f
+    t["amplitude"] = 1.0
+    w = W.Workload("ties", fs, 0.0, period_log2, t)
+    _compare_words(w)
+    plan, _ = _host_plan(w)
+    try:
+        lw = awg.awg_plan_words(plan, len(f))
+    finally:
+        awg.awg_plan_destroy(plan)
+    shift = 64 - s
+    for j, k in enumerate(ks.tolist()):           # the tie itself goes to the even neighbour
+        even = k if k % 2 == 0 else k + 1
+        assert int(lw["f0"][3 * j]) >> shift == even, (k, period_log2)
+
+
 @pytest.mark.parametrize("shape", [awg.RAMP_COSINE, awg.RAMP_MINJERK])
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 100, 4097, 65537])
 def test_ramp_tables_equal_oracle(shape, n):
