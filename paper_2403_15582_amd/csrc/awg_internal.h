@@ -393,10 +393,14 @@ hipError_t launch_plb_zero(int64_t *d_S, uint64_t L, hipStream_t s);
 // group_tones static line records each (amplitude 0 for padding); the sum of
 // group z over samples [0, L) goes to q_base + plane_map[z] * L (d_plane_map:
 // device, n_built entries). d_work: at least group_work_bytes(...) bytes.
+// d_ranges (device, n_built entries, or nullptr for whole sums): group z is
+// made only on the samples [x * 2^18, (x + y) * 2^18) of (x, y) = d_ranges[z]
+// (tile rows of 256 rows of 1024 samples), y >= 1, max_tiles the largest y.
 size_t group_work_bytes(int32_t n_built, int32_t group_tones, uint64_t L);
 hipError_t launch_group_sums(const awg_plan *p, uint32_t method, const ToneDev *d_list, int32_t n_built,
                              int32_t group_tones, uint64_t L, void *d_work, float *q_base,
-                             const int32_t *d_plane_map, hipStream_t s, double work);
+                             const int32_t *d_plane_map, const int2 *d_ranges, int32_t max_tiles, hipStream_t s,
+                             double work);
 // Multiplexed channels: items[c] (c < n, n <= kMaxChannels) each cover the same
 // count samples; one launch, items passed by value.
 constexpr int kMaxChannels = 4;

@@ -44,6 +44,7 @@ namespace awg {
 namespace {
 
 constexpr int32_t kGroupTones = 128;                 // tones per group (16 k-blocks)
+constexpr int kTileLog2 = 18;                        // samples per tile row of the group product (256 rows)
 constexpr uint64_t kRow = kTileSamples;
 constexpr uint64_t kPiece = 1ull << 22;               // samples per pass
 constexpr int32_t kMaxSegs = 64;                      // segments of one pass (more: the pass is halved)
@@ -106,7 +107,9 @@ struct LineBuf {
     int last_slot = -1;                   // staging slot of the latest pass (its event ends that pass)
     hipStream_t last_stream = nullptr;
     // cache of group sums: per group, version hash -> slot; the slot's words
-    struct Entry { int32_t group; uint64_t hash; uint64_t last_use; bool live; std::vector<Line> words; };
+    // valid: the tile rows of the period (2^18 samples each) that the slot's
+    // sum holds; a version that only segments need is made on their rows only
+    struct Entry { int32_t group; uint64_t hash; uint64_t last_use; bool live; std::vector<Line> words; uint64_t valid = 0; };
     std::vector<Entry> slot_entry;        // per slot
     std::vector<std::unordered_multimap<uint64_t, int32_t>> index;   // per group
     std::vector<int32_t> free_slots;
@@ -151,6 +154,9 @@ struct LineBuf {
     std::vector<PlbSplit> splits;
     std::vector<uint8_t> is_split;        // per row
     std::vector<int32_t> build_map;
+    std::vector<int32_t> build_rng;       // per build: first tile row, tile rows
+    int32_t n_tiles = 1;                  // tile rows of the period
+    uint64_t all_tiles = 1;
     std::vector<PlbSeg> segs;
     std::vector<PlbFold> folds;
     std::vector<int32_t> seg_slot;        // slots of the segments (pointers filled at staging)
@@ -182,7 +188,8 @@ size_t max_entries(const LineBuf &b) { return (size_t)(b.n_groups + kMaxSegs) * 
 size_t raw_cap(const LineBuf &b)
 {
     const size_t ng = (size_t)b.n_groups, K = (size_t)b.K, nb = ng + kMaxSegs, rows = kPiece / kRow;
-    return align_up(sizeof(int32_t) * nb, 256) + align_up(sizeof(Block) * (2 * K + 1), 256) +
+    return align_up(sizeof(int32_t) * nb, 256) + align_up(sizeof(int32_t) * 2 * nb, 256) +
+           align_up(sizeof(Block) * (2 * K + 1), 256) +
            align_up(sizeof(PlbItem) * (rows + kMaxParts), 256) + align_up(sizeof(PlbPiece) * kMaxPieces, 256) +
            align_up(sizeof(int32_t) * 2 * (2 * K + 1), 256) +
            align_up(sizeof(PlbSplit) * rows, 256) + align_up(sizeof(PlbSeg) * kMaxSegs, 256) +
@@ -262,9 +269,25 @@ int32_t take_slot(LineBuf &b, int32_t stamp)
     return best;
 }
 
-// Slot of group g's version w for this pass (stamp): cached, or a new one added
-// to the build list.
-int32_t need(LineBuf &b, int32_t g, const Line *w, int32_t n, int32_t stamp)
+// The tile rows of the period (2^18 samples each) that the call rows
+// [begin, end) of a pass from n0 cover (m = n mod L; they may wrap round).
+uint64_t tiles_of_rows(const LineBuf &b, uint64_t n0, uint32_t begin, uint32_t end)
+{
+    const uint64_t len = (uint64_t)(end - begin) * kRow;
+    if (len >= b.L || b.n_tiles == 1) return b.all_tiles;
+    const uint64_t m0 = (n0 + (uint64_t)begin * kRow) & (b.L - 1), m1 = m0 + len - 1;
+    const int32_t t0 = (int32_t)(m0 >> kTileLog2);
+    auto span = [](int32_t lo, int32_t hi) {
+        return (hi == 63 ? ~0ull : (1ull << (hi + 1)) - 1) & ~((1ull << lo) - 1);
+    };
+    if (m1 < b.L) return span(t0, (int32_t)(m1 >> kTileLog2));
+    return span(t0, b.n_tiles - 1) | span(0, (int32_t)((m1 - b.L) >> kTileLog2));
+}
+
+// Slot of group g's version w for this pass (stamp), with at least the tile
+// rows `want`: cached, or a new one; the tile rows it lacks (their hull) are
+// added to the build list.
+int32_t need(LineBuf &b, int32_t g, const Line *w, int32_t n, int32_t stamp, uint64_t want)
 {
     const uint64_t h = version_hash(w, n);
     int32_t s = find_version(b, g, w, n, h);
@@ -275,11 +298,21 @@ int32_t need(LineBuf &b, int32_t g, const Line *w, int32_t n, int32_t stamp)
         e.group = g;
         e.hash = h;
         e.live = true;
+        e.valid = 0;
         e.words.assign(w, w + n);
         b.index[g].emplace(h, s);
+    }
+    LineBuf::Entry &e = b.slot_entry[s];
+    const uint64_t make = want & ~e.valid;
+    if (make) {
+        const int32_t lo = __builtin_ctzll(make), hi = 63 - __builtin_clzll(make);
+        const uint64_t hull = (hi == 63 ? ~0ull : (1ull << (hi + 1)) - 1) & ~((1ull << lo) - 1);
         for (int32_t i = 0; i < kGroupTones; ++i)
-            b.build_list.push_back(i < n ? line_desc(w[i], 1.0f) : line_desc(kNoLine, 0.0f));
+            b.build_list.push_back(i < n ? line_desc(e.words[i], 1.0f) : line_desc(kNoLine, 0.0f));
         b.build_map.push_back(s);
+        b.build_rng.push_back(lo);
+        b.build_rng.push_back(hi - lo + 1);
+        e.valid |= hull;
     }
     b.slot_entry[s].last_use = b.tick;
     b.pinned[s] = stamp;
@@ -294,6 +327,8 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
     b.n_groups = groups_of(b.K);
     b.n_slots = 2 * b.n_groups + kMaxSegs;
     b.bwork_bytes = group_work_bytes(kBuildBatch, kGroupTones, b.L);
+    b.n_tiles = (int32_t)std::max<uint64_t>(1, b.L >> kTileLog2);
+    b.all_tiles = b.n_tiles >= 64 ? ~0ull : (1ull << b.n_tiles) - 1;
     hipError_t e = hipMalloc(&b.d_S, sizeof(int64_t) * b.L);
     if (e == hipSuccess) e = hipMalloc(&b.d_Q, sizeof(float) * b.L * (size_t)b.n_slots);
     if (e == hipSuccess) e = hipMalloc(&b.d_bwork, b.bwork_bytes);
@@ -523,6 +558,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     b.gsw.clear();
     b.build_list.clear();
     b.build_map.clear();
+    b.build_rng.clear();
     b.direct.clear();
     b.segs.clear();
     b.seg_slot.clear();
@@ -591,7 +627,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
             b.slot_entry[snext].last_use = b.tick;
             b.pinned[snext] = stamp;
         } else {
-            snext = need(b, g, &b.next[k0], n, stamp);
+            snext = need(b, g, &b.next[k0], n, stamp, b.all_tiles);
         }
         if (snext < 0) return AWG_E_NOMEM;
         if (b.s_slot[g] != snext) b.fold_slots.emplace_back(snext, b.s_slot[g]);
@@ -618,7 +654,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
                 differs = differs || l != b.next[k];
             }
             if (differs) {
-                const int32_t sv = need(b, g, b.ver.data(), n, stamp);
+                const int32_t sv = need(b, g, b.ver.data(), n, stamp, tiles_of_rows(b, n0, begin, end));
                 if (sv < 0) return AWG_E_NOMEM;
                 b.segs.push_back(PlbSeg{begin, end - 1, nullptr, nullptr});
                 b.seg_slot.push_back(sv);
@@ -649,7 +685,8 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     const int32_t n_fold = (int32_t)b.fold_slots.size();
     const int32_t n_items = (int32_t)b.items.size();
     const int32_t n_split = (int32_t)b.splits.size();
-    const size_t r_b = align_up(sizeof(int32_t) * (size_t)n_built, 256);
+    const size_t r_g = align_up(sizeof(int32_t) * (size_t)n_built, 256);
+    const size_t r_b = r_g + align_up(sizeof(int32_t) * 2 * (size_t)n_built, 256);
     const size_t r_o = r_b + align_up(sizeof(Block) * b.blocks.size(), 256);
     const size_t r_p = r_o + align_up(sizeof(PlbItem) * (size_t)n_items, 256);
     const size_t r_x = r_p + align_up(sizeof(PlbPiece) * b.pieces.size(), 256);
@@ -674,6 +711,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     if (n_direct) std::memcpy(hd + n_be, b.direct.data(), sizeof(PlbDesc) * (size_t)n_direct);
     char *hr = hb + h_raw;
     if (n_built) std::memcpy(hr, b.build_map.data(), sizeof(int32_t) * (size_t)n_built);
+    if (n_built) std::memcpy(hr + r_g, b.build_rng.data(), sizeof(int32_t) * 2 * (size_t)n_built);
     std::memcpy(hr + r_b, b.blocks.data(), sizeof(Block) * b.blocks.size());
     std::memcpy(hr + r_o, b.items.data(), sizeof(PlbItem) * (size_t)n_items);
     if (!b.pieces.empty()) std::memcpy(hr + r_p, b.pieces.data(), sizeof(PlbPiece) * b.pieces.size());
@@ -704,10 +742,16 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     for (int32_t i = 0; e == hipSuccess && i < n_built; i += kBuildBatch) {
         const int32_t nb = std::min(kBuildBatch, n_built - i);
         double work = 0.0;
-        for (int32_t z = i; z < i + nb; ++z)
-            work += (double)std::min(kGroupTones, K - b.slot_entry[b.build_map[z]].group * kGroupTones) * (double)b.L;
+        int32_t max_tiles = 1;
+        for (int32_t z = i; z < i + nb; ++z) {
+            const int32_t cnt = b.build_rng[2 * z + 1];
+            max_tiles = std::max(max_tiles, cnt);
+            work += (double)std::min(kGroupTones, K - b.slot_entry[b.build_map[z]].group * kGroupTones) *
+                    (double)std::min<uint64_t>(b.L, (uint64_t)cnt << kTileLog2);
+        }
         e = launch_group_sums(p, b.method, (const ToneDev *)db + (size_t)i * kGroupTones, nb, kGroupTones, b.L,
-                              b.d_bwork, b.d_Q, (const int32_t *)dr + i, s, work);
+                              b.d_bwork, b.d_Q, (const int32_t *)dr + i, (const int2 *)(dr + r_g) + i, max_tiles, s,
+                              work);
     }
     // S to the call's next versions, then the call; a call of exactly one
     // period folds in the kernels that read S (each m is read once)

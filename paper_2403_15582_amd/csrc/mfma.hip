@@ -213,10 +213,18 @@ __global__ __launch_bounds__(256) void gen_ab_kernel(const ToneDev *__restrict__
                                                      uint32_t a_per_group, uint32_t a_blocks, uint64_t mcols,
                                                      int32_t rb_pad, T *__restrict__ a_hi, T *__restrict__ a_lo,
                                                      int32_t n_groups, int32_t cb_n, T *__restrict__ b_hi,
-                                                     T *__restrict__ b_lo)
+                                                     T *__restrict__ b_lo, const int2 *__restrict__ ty_range,
+                                                     int32_t groups_per_slice)
 {
     const uint32_t bx = blockIdx.x;
     if (bx < a_blocks) {
+        // one workgroup = 256 rows = one tile row of the product: rows of tile
+        // rows that the slice does not make are not needed
+        if (ty_range) {
+            const int2 rr = ty_range[(int32_t)(bx / a_per_group) / groups_per_slice];
+            const int tr = (int)(bx % a_per_group);
+            if (tr < rr.x || tr >= rr.x + rr.y) return;
+        }
         gen_a_at<T, false>(tones, nullptr, n_entries, (int32_t)(bx / a_per_group),
                            (int64_t)(bx % a_per_group) * blockDim.x + threadIdx.x, 0, mcols, rb_pad, a_hi, a_lo);
     } else {
@@ -262,12 +270,13 @@ constexpr int vmcnt_imm(int v) { return (v & 0xf) | ((v >> 4) << 14) | (0x7 << 4
 // Split K: the grid's z index z sums k-blocks [z*kb_split, (z+1)*kb_split) and
 // writes its partial sums to plane z of the FP32 output (plane elements apart),
 // or to plane plane_map[z] when a map is given (group products written straight
-// into their slots of a cache).
+// into their slots of a cache). With ty_range, slice z covers only the tile rows
+// ty_range[z].x .. + ty_range[z].y - 1, grid y being the largest such count.
 template <typename T, bool F32OUT, int WR, int WC, int NST>
 __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
     const T *__restrict__ a_hi, const T *__restrict__ a_lo, const T *__restrict__ b_hi, const T *__restrict__ b_lo,
     int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split, uint64_t plane, uint64_t mcols, uint64_t count,
-    void *__restrict__ out, const int32_t *__restrict__ plane_map)
+    void *__restrict__ out, const int32_t *__restrict__ plane_map, const int2 *__restrict__ ty_range)
 {
     typedef typename Split<T>::vec V;
     constexpr int W = WR * WC;
@@ -302,6 +311,11 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void angle_gemm_kernel(
         const uint32_t r = b - full * gx, rows = gy - full;
         ty = full + r % rows;
         tx = r / rows;
+    }
+    if (ty_range) {                    // slice z makes tile rows [x, x + y) only (whole workgroup)
+        const int2 rr = ty_range[z];
+        if ((int)ty >= rr.y) return;
+        ty += (uint32_t)rr.x;
     }
     const int rb0 = ty * kTileRB, cb0 = tx * kTileCB;
 
@@ -399,7 +413,7 @@ template <typename T, int WR, int WC, int NST>
 static hipError_t launch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T *a_lo, const T *b_hi,
                               const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
                               uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32,
-                              const int32_t *plane_map)
+                              const int32_t *plane_map, const int2 *ty_range)
 {
     constexpr int kLds = NST * 4 * kTileRB * kFragBytes;
     // the dynamic LDS limit is raised once per device (calls may come from
@@ -424,11 +438,12 @@ static hipError_t launch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T
     }
     if (out_f32)
         prof.launch(angle_gemm_kernel<T, true, WR, WC, NST>, grid, dim3(64 * WR * WC), (uint32_t)kLds, a_hi,
-                    a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_f32, plane_map);
+                    a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_f32, plane_map,
+                    ty_range);
     else
         prof.launch(angle_gemm_kernel<T, false, WR, WC, NST>, grid, dim3(64 * WR * WC), (uint32_t)kLds, a_hi,
                     a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, mcols, count, (void *)out_i16,
-                    (const int32_t *)nullptr);
+                    (const int32_t *)nullptr, ty_range);
     return hipGetLastError();
 }
 
@@ -464,11 +479,11 @@ template <typename T>
 static hipError_t dispatch_gemm(dim3 grid, ProfScope &prof, const T *a_hi, const T *a_lo, const T *b_hi,
                                 const T *b_lo, int32_t kb_n, int32_t rb_pad, int32_t cb_n, int32_t kb_split,
                                 uint64_t plane, uint64_t mcols, uint64_t count, int16_t *out_i16, float *out_f32,
-                                const int32_t *plane_map = nullptr)
+                                const int32_t *plane_map = nullptr, const int2 *ty_range = nullptr)
 {
 #define AWG_GEMM(WR, WC, NST)                                                                                  \
     return launch_gemm<T, WR, WC, NST>(grid, prof, a_hi, a_lo, b_hi, b_lo, kb_n, rb_pad, cb_n, kb_split, plane, \
-                                       mcols, count, out_i16, out_f32, plane_map)
+                                       mcols, count, out_i16, out_f32, plane_map, ty_range)
     switch (gemm_variant()) {
     case 0: AWG_GEMM(2, 2, 2);
     case 1: AWG_GEMM(2, 2, 3);
@@ -735,9 +750,10 @@ size_t group_work_bytes(int32_t n_built, int32_t group_tones, uint64_t L)
 
 template <typename T>
 static hipError_t group_run(const awg_plan *p, const ToneDev *d_list, int32_t n_built, int32_t group_tones,
-                            uint64_t L, char *w, float *q_base, const int32_t *d_plane_map, hipStream_t s,
-                            double work)
+                            uint64_t L, char *w, float *q_base, const int32_t *d_plane_map, const int2 *d_ranges,
+                            int32_t max_tiles, hipStream_t s, double work)
 {
+    static_assert(kTileRB * 32 == 256, "a workgroup of gen_ab makes one tile row of A");
     const bool f16 = std::is_same<T, _Float16>::value;
     const GroupGeom g = group_geometry(n_built, group_tones, L);
     T *b_hi = (T *)w, *b_lo = (T *)(w + g.b_bytes);
@@ -753,28 +769,33 @@ static hipError_t group_run(const awg_plan *p, const ToneDev *d_list, int32_t n_
         ProfScope prof(p->ctx, s, f16 ? "plb_gen_f16" : "plb_gen_bf16");
         prof.launch(gen_ab_kernel<T>, dim3((uint32_t)(a_blocks + b_blocks)), dim3(256), 0, d_list, n_entries,
                     (uint32_t)a_per_group, (uint32_t)a_blocks, (uint64_t)kTileSamples, g.rb_pad, a_hi, a_lo,
-                    2 * g.kb_n, g.cb_n, b_hi, b_lo);
+                    2 * g.kb_n, g.cb_n, b_hi, b_lo, d_ranges, group_tones / 4);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    dim3 grid((uint32_t)(g.cb_n / kTileCB), (uint32_t)(g.rb_pad / kTileRB), (uint32_t)n_built);
+    const int32_t ty_n = d_ranges ? max_tiles : g.rb_pad / kTileRB;
+    if (ty_n <= 0 || ty_n > g.rb_pad / kTileRB) return hipErrorInvalidValue;
+    dim3 grid((uint32_t)(g.cb_n / kTileCB), (uint32_t)ty_n, (uint32_t)n_built);
     ProfScope prof(p->ctx, s, f16 ? "plb_gemm_f16" : "plb_gemm_bf16");
     prof.add_work(work);
     return dispatch_gemm<T>(grid, prof, a_hi, a_lo, b_hi, b_lo, g.kb_n, g.rb_pad, g.cb_n, g.kpg, L, kTileSamples, L,
-                            nullptr, q_base, d_plane_map);
+                            nullptr, q_base, d_plane_map, d_ranges);
 }
 
 hipError_t launch_group_sums(const awg_plan *p, uint32_t method, const ToneDev *d_list, int32_t n_built,
                              int32_t group_tones, uint64_t L, void *d_work, float *q_base,
-                             const int32_t *d_plane_map, hipStream_t s, double work)
+                             const int32_t *d_plane_map, const int2 *d_ranges, int32_t max_tiles, hipStream_t s,
+                             double work)
 {
     if (n_built <= 0) return hipSuccess;
     if (group_tones % 8 != 0 || L < kTileSamples || L % kTileSamples != 0 || n_built > 65535)
         return hipErrorInvalidValue;
     if (method == AWG_F_METHOD_MFMA_F16X3)
-        return group_run<_Float16>(p, d_list, n_built, group_tones, L, (char *)d_work, q_base, d_plane_map, s, work);
+        return group_run<_Float16>(p, d_list, n_built, group_tones, L, (char *)d_work, q_base, d_plane_map, d_ranges,
+                                   max_tiles, s, work);
     if (method == AWG_F_METHOD_MFMA_BF16X3)
-        return group_run<__bf16>(p, d_list, n_built, group_tones, L, (char *)d_work, q_base, d_plane_map, s, work);
+        return group_run<__bf16>(p, d_list, n_built, group_tones, L, (char *)d_work, q_base, d_plane_map, d_ranges,
+                                 max_tiles, s, work);
     return hipErrorInvalidValue;
 }
 

@@ -156,6 +156,44 @@ def test_array_group_chirps_stream_against_direct_and_oracle(method):
     say("array hybrid: all %d chunks within %d LSB of the direct method" % (n_chunks, TOL_Q))
 
 
+def test_array_stream_period_longer_than_chunk():
+    """The array stream on bins of 2^22 streamed in 2^20-sample chunks: each
+    call covers a quarter of the period (S folded by its own launch), group
+    sums that only segments need are made on their tile rows of the period
+    alone, and the stream wraps round the period after four chunks: every
+    sample against the direct method, two chunks sampled against the oracle."""
+    import dataclasses
+    torch = need_gpu()
+    w = dataclasses.replace(W.array_group_chirps(K=3000, seconds=0.026), period_log2=22)
+    hp, dp = _plans(w, BF16)
+    op = words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones, build_tables=False)
+    events = sorted(w.retunes, key=lambda e: e[1])
+    n_chunks = 7
+    i = 0
+    for c in range(n_chunks):
+        end = (c + 1) * w.chunk
+        batch = []
+        while i < len(events) and events[i][1] < end:
+            k, a, n, shape, f = events[i]
+            batch.append((k, shape, a, n, f))
+            op.add_ramp(k, a, n, shape, f)
+            i += 1
+        if batch:
+            hp.retune(batch)
+            dp.retune(batch)
+        say("array period 2^22 chunk %d" % c)
+        n0, qh = hp.stream_next(w.chunk)
+        _, qd = dp.stream_next(w.chunk)
+        yh = hp.synth_f32(n0, w.chunk, method=BF16) if c in (3, 5) else None
+        torch.cuda.synchronize()
+        a, b = to_np(qh), to_np(qd)
+        assert int(np.abs(a.astype(np.int32) - b).max()) <= TOL_Q, c
+        if yh is not None:
+            ns = np.unique(np.concatenate([np.random.default_rng(c).integers(0, w.chunk, 500), [0, w.chunk - 1]]))
+            qo, yo = csynth.synth_at(op, ns + n0)
+            compare(a[ns], to_np(yh)[ns], qo, yo, "array period 2^22 chunk %d (sampled %d)" % (c, len(ns)))
+
+
 @pytest.mark.parametrize("method", [F16, BF16])
 def test_one_period_calls_at_odd_offsets(method):
     """Calls of exactly one period (2^20 samples) that start off a row and off a
