@@ -366,8 +366,9 @@ struct PlbPiece {
 // pieces [first, first + count), its sum into partial slot `part`).
 struct PlbItem {
     uint32_t row;
-    int32_t part;
-    uint32_t first, count;
+    int32_t part;                // partial slot of a part of a split tile (-1: a whole tile)
+    uint32_t first, count;       // a part's pieces
+    int32_t split;               // a part's split tile (index into the split tiles)
 };
 // A split tile: its parts' sums sit in partial slots first .. first + n - 1.
 struct PlbSplit {
@@ -375,14 +376,15 @@ struct PlbSplit {
     uint32_t first, n;
     uint32_t pad;
 };
-// The line-buffer launch: n_items work items, then (n_split > 0) one combine
-// workgroup per split tile. d_partials holds 1024 floats per partial slot;
+// The line-buffer launch: n_items work items; the last part of a split tile to
+// finish adds its parts (d_counts: one counter per split tile, zero before the
+// launch and after it). d_partials holds 1024 floats per partial slot;
 // d_span[i] = (first row, last row) the tones of block i are summed on.
 // n_fold > 0 (only when count == L, so that each m = n mod L is one thread's):
 // the folds d_folds[0 .. n_fold) are applied to S by the kernels that read it.
 hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const PlbItem *d_items,
                       int32_t n_items, const PlbPiece *d_pieces, const int2 *d_span, float *d_partials,
-                      const PlbSplit *d_splits,
+                      const PlbSplit *d_splits, int32_t *d_counts,
                       int32_t n_split, uint64_t n0, uint64_t count, int64_t *d_S, uint64_t L,
                       const PlbSeg *d_segs, int32_t n_seg, const PlbFold *d_folds, int32_t n_fold,
                       int16_t *out_i16, float *out_f32, hipStream_t s, double work);

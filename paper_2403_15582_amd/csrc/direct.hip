@@ -788,47 +788,17 @@ __global__ __launch_bounds__(256) void direct_hybrid_kernel(const ToneDev *__res
     synth_tile<S, F32OUT, false, true>(tones, blocks, tables, n0 + rel, valid, o, part, hyb);
 }
 
-// Periodic line-buffer path: tile order[b] of the range, the direct list's
-// tones on their own tiles, the line tones from S and the segments (PlbIn).
-template <int S, bool F32OUT>
-__global__ __launch_bounds__(256) void plb_kernel(const ToneDev *__restrict__ tones, const Block *__restrict__ blocks,
-                                                  const PlbItem *__restrict__ items,
-                                                  const uint64_t *const *__restrict__ tables, uint64_t n0,
-                                                  uint64_t count, void *__restrict__ out, int64_t *__restrict__ S_sum,
-                                                  uint64_t mask, const PlbSeg *__restrict__ segs, int32_t n_seg,
-                                                  const PlbPiece *__restrict__ pieces, float *__restrict__ partials,
-                                                  const int2 *__restrict__ span, const PlbFold *__restrict__ folds,
-                                                  int32_t n_fold)
-{
-    constexpr int T = kLanes * S;
-    __shared__ float part[kWaves][T];
-    const PlbItem item = items[blockIdx.x];
-    const uint32_t row = item.row;
-    const uint64_t rel = (uint64_t)row * T;
-    const uint64_t left = count - rel;
-    const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
-    void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
-    const bool is_part = item.part >= 0;
-    const PlbIn plb{S_sum, mask, segs, n_seg, row, is_part ? pieces + item.first : nullptr, item.count,
-                    is_part ? partials + (size_t)item.part * T : nullptr, span, folds, n_fold};
-    synth_tile<S, F32OUT, false, true, true>(tones, blocks, tables, n0 + rel, valid, o, part,
-                                             HybridIn{0, nullptr, 0}, 1, plb);
-}
-
-// The split tiles of a line-buffer launch: the parts' sums added in part order,
-// then the line tones and the rounding, as the tile epilogue does for a whole
-// tile (y = lines + sum).
+// A split tile of a line-buffer launch, by the workgroup of its last part: the
+// parts' sums added in part order, then the line tones and the rounding, as
+// the tile epilogue does for a whole tile (y = lines + sum).
 template <bool F32OUT>
-__global__ __launch_bounds__(256) void plb_combine_kernel(const PlbSplit *__restrict__ splits,
-                                                          const float *__restrict__ partials, uint64_t n0,
-                                                          uint64_t count, void *__restrict__ out,
-                                                          int64_t *__restrict__ S_sum, uint64_t mask,
-                                                          const PlbSeg *__restrict__ segs, int32_t n_seg,
-                                                          const PlbFold *__restrict__ folds, int32_t n_fold)
+__device__ __forceinline__ void plb_finish(const PlbSplit sp, const float *__restrict__ partials, uint64_t n0,
+                                           uint64_t count, void *__restrict__ out, int64_t *__restrict__ S_sum,
+                                           uint64_t mask, const PlbSeg *__restrict__ segs, int32_t n_seg,
+                                           const PlbFold *__restrict__ folds, int32_t n_fold)
 {
     constexpr int T = kTileSamples;
     constexpr int PER = T / 256;
-    const PlbSplit sp = splits[blockIdx.x];
     const uint64_t rel = (uint64_t)sp.row * T;
     const uint64_t left = count - rel;
     const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
@@ -864,6 +834,46 @@ __global__ __launch_bounds__(256) void plb_combine_kernel(const PlbSplit *__rest
             else ((int16_t *)out)[rel + i] = quantise(z);
         }
     }
+}
+
+// Periodic line-buffer path: tile order[b] of the range, the direct list's
+// tones on their own tiles, the line tones from S and the segments (PlbIn).
+template <int S, bool F32OUT>
+__global__ __launch_bounds__(256) void plb_kernel(const ToneDev *__restrict__ tones, const Block *__restrict__ blocks,
+                                                  const PlbItem *__restrict__ items,
+                                                  const uint64_t *const *__restrict__ tables, uint64_t n0,
+                                                  uint64_t count, void *__restrict__ out, int64_t *__restrict__ S_sum,
+                                                  uint64_t mask, const PlbSeg *__restrict__ segs, int32_t n_seg,
+                                                  const PlbPiece *__restrict__ pieces, float *__restrict__ partials,
+                                                  const int2 *__restrict__ span, const PlbFold *__restrict__ folds,
+                                                  int32_t n_fold, const PlbSplit *__restrict__ splits,
+                                                  int32_t *__restrict__ counts)
+{
+    constexpr int T = kLanes * S;
+    __shared__ float part[kWaves][T];
+    __shared__ int32_t last;
+    const PlbItem item = items[blockIdx.x];
+    const uint32_t row = item.row;
+    const uint64_t rel = (uint64_t)row * T;
+    const uint64_t left = count - rel;
+    const uint32_t valid = left < (uint64_t)T ? (uint32_t)left : (uint32_t)T;
+    void *o = F32OUT ? (void *)((float *)out + rel) : (void *)((int16_t *)out + rel);
+    const bool is_part = item.part >= 0;
+    const PlbIn plb{S_sum, mask, segs, n_seg, row, is_part ? pieces + item.first : nullptr, item.count,
+                    is_part ? partials + (size_t)item.part * T : nullptr, span, folds, n_fold};
+    synth_tile<S, F32OUT, false, true, true>(tones, blocks, tables, n0 + rel, valid, o, part,
+                                             HybridIn{0, nullptr, 0}, 1, plb);
+    if (!is_part) return;
+    // count the part done (its sums released first); the part that completes
+    // its tile acquires the others' sums and adds them
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&counts[item.split], 1) == (int32_t)splits[item.split].n - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    plb_finish<F32OUT>(splits[item.split], partials, n0, count, out, S_sum, mask, segs, n_seg, folds, n_fold);
+    if (threadIdx.x == 0) counts[item.split] = 0;        // ready for the next launch
 }
 
 // S[m] += sum over the folds f of fix(q_new_f[m]) - fix(q_old_f[m]) (q_old_f may
@@ -1057,7 +1067,7 @@ hipError_t launch_direct_hybrid(const awg_plan *p, const ToneDev *d_tones, const
 
 hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_blocks, const PlbItem *d_items,
                       int32_t n_items, const PlbPiece *d_pieces, const int2 *d_span, float *d_partials,
-                      const PlbSplit *d_splits,
+                      const PlbSplit *d_splits, int32_t *d_counts,
                       int32_t n_split, uint64_t n0, uint64_t count, int64_t *d_S, uint64_t L,
                       const PlbSeg *d_segs, int32_t n_seg, const PlbFold *d_folds, int32_t n_fold,
                       int16_t *out_i16, float *out_f32, hipStream_t s, double work)
@@ -1075,21 +1085,12 @@ hipError_t launch_plb(const awg_plan *p, const ToneDev *d_tones, const Block *d_
         if (out_f32)
             prof.launch(plb_kernel<kS, true>, dim3((uint32_t)n_items), dim3(256), 0, d_tones, d_blocks, d_items,
                         p->d_table_ptrs, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg, d_pieces, d_partials,
-                        d_span, d_folds, n_fold);
+                        d_span, d_folds, n_fold, d_splits, d_counts);
         else
             prof.launch(plb_kernel<kS, false>, dim3((uint32_t)n_items), dim3(256), 0, d_tones, d_blocks, d_items,
                         p->d_table_ptrs, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg, d_pieces, d_partials,
-                        d_span, d_folds, n_fold);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess || n_split == 0) return e;
+                        d_span, d_folds, n_fold, d_splits, d_counts);
     }
-    ProfScope prof(p->ctx, s, "plb_combine_kernel");
-    if (out_f32)
-        prof.launch(plb_combine_kernel<true>, dim3((uint32_t)n_split), dim3(256), 0, d_splits,
-                    (const float *)d_partials, n0, count, (void *)out_f32, d_S, L - 1, d_segs, n_seg, d_folds, n_fold);
-    else
-        prof.launch(plb_combine_kernel<false>, dim3((uint32_t)n_split), dim3(256), 0, d_splits,
-                    (const float *)d_partials, n0, count, (void *)out_i16, d_S, L - 1, d_segs, n_seg, d_folds, n_fold);
     return hipGetLastError();
 }
 

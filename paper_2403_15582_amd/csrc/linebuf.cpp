@@ -47,6 +47,7 @@ constexpr int32_t kGroupTones = 128;                 // tones per group (16 k-bl
 constexpr int kTileLog2 = 18;                        // samples per tile row of the group product (256 rows)
 constexpr uint64_t kRow = kTileSamples;
 constexpr uint64_t kPiece = 1ull << 22;               // samples per pass
+constexpr uint64_t kCntWords = kPiece / kTileSamples / 2;   // split-tile counters (int32, two per word)
 constexpr int32_t kMaxSegs = 64;                      // segments of one pass (more: the pass is halved)
 constexpr int32_t kBuildBatch = 32;                   // groups per product launch
 constexpr int kSlots = 4;                             // pinned staging slots in flight
@@ -101,6 +102,7 @@ struct LineBuf {
     int64_t *d_S = nullptr;
     float *d_Q = nullptr;                 // n_slots period sums
     float *d_part = nullptr;              // kMaxParts partial tile sums
+    int32_t *d_cnt = nullptr;             // per split tile of a launch: parts done (zero between launches)
     void *d_bwork = nullptr;              // product operands of one batch of groups
     size_t bwork_bytes = 0;
     bool s_zeroed = false;
@@ -333,6 +335,7 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
     if (e == hipSuccess) e = hipMalloc(&b.d_Q, sizeof(float) * b.L * (size_t)b.n_slots);
     if (e == hipSuccess) e = hipMalloc(&b.d_bwork, b.bwork_bytes);
     if (e == hipSuccess) e = hipMalloc(&b.d_part, sizeof(float) * kRow * kMaxParts);
+    if (e == hipSuccess) e = hipMalloc(&b.d_cnt, sizeof(int64_t) * kCntWords);
     const size_t ch = host_cap(b), cd = dev_cap(b);
     for (auto &sl : b.slots) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
@@ -455,15 +458,16 @@ void plan_items(LineBuf &b, const awg_plan *p, uint64_t n0, uint64_t rows)
             b.pieces.resize(first);
             continue;
         }
+        const int32_t si = (int32_t)b.splits.size();
         b.splits.push_back(PlbSplit{r, (uint32_t)slots, (uint32_t)P, 0});
         for (int32_t q = 0; q < P; ++q)
             b.items.push_back(PlbItem{r, slots + q, (uint32_t)(first + (size_t)q * kPartPieces),
-                                      (uint32_t)std::min<int32_t>(kPartPieces, n_pc - q * kPartPieces)});
+                                      (uint32_t)std::min<int32_t>(kPartPieces, n_pc - q * kPartPieces), si});
         slots += P;
         b.is_split[r] = 1;
     }
     for (uint64_t oi = 0; oi < rows; ++oi)
-        if (!b.is_split[b.order[oi]]) b.items.push_back(PlbItem{b.order[oi], -1, 0, 0});
+        if (!b.is_split[b.order[oi]]) b.items.push_back(PlbItem{b.order[oi], -1, 0, 0, -1});
 }
 
 // Order of the direct list: plan tones (ramped ones first, then by window,
@@ -735,6 +739,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
                              (ToneDev *)(db + d_dir), (const char *)slot.mapped + h_raw, db + d_raw, raw, s);
     if (e == hipSuccess && !b.s_zeroed) {
         e = launch_plb_zero(b.d_S, b.L, s);
+        if (e == hipSuccess) e = launch_plb_zero((int64_t *)b.d_cnt, kCntWords, s);
         if (e == hipSuccess) b.s_zeroed = true;
     }
     char *dr = db + d_raw;
@@ -760,7 +765,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     if (e == hipSuccess)
         e = launch_plb(p, (const ToneDev *)(db + d_dir), (const Block *)(dr + r_b), (const PlbItem *)(dr + r_o), n_items,
                        (const PlbPiece *)(dr + r_p), (const int2 *)(dr + r_y), b.d_part, (const PlbSplit *)(dr + r_x),
-                       n_split, n0, count, b.d_S, b.L, (const PlbSeg *)(dr + r_s), n_seg,
+                       b.d_cnt, n_split, n0, count, b.d_S, b.L, (const PlbSeg *)(dr + r_s), n_seg,
                        (const PlbFold *)(dr + r_f), fused ? n_fold : 0, out_i16, out_f32, s, direct_work);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
     if (e == hipSuccess) {
@@ -811,6 +816,7 @@ void plb_release(awg_plan *p)
     if (b->d_Q) (void)hipFree(b->d_Q);
     if (b->d_bwork) (void)hipFree(b->d_bwork);
     if (b->d_part) (void)hipFree(b->d_part);
+    if (b->d_cnt) (void)hipFree(b->d_cnt);
     delete b;
     p->plb = nullptr;
 }
