@@ -399,10 +399,21 @@ hipError_t launch_plb_zero(int64_t *d_S, uint64_t L, hipStream_t s);
 // made only on the samples [x * 2^18, (x + y) * 2^18) of (x, y) = d_ranges[z]
 // (tile rows of 256 rows of 1024 samples), y >= 1, max_tiles the largest y.
 size_t group_work_bytes(int32_t n_built, int32_t group_tones, uint64_t L);
+// operands_ready: the operands are already in d_work (launch_plb_prep).
 hipError_t launch_group_sums(const awg_plan *p, uint32_t method, const ToneDev *d_list, int32_t n_built,
                              int32_t group_tones, uint64_t L, void *d_work, float *q_base,
-                             const int32_t *d_plane_map, const int2 *d_ranges, int32_t max_tiles, hipStream_t s,
-                             double work);
+                             const int32_t *d_plane_map, const int2 *d_ranges, int32_t max_tiles,
+                             bool operands_ready, hipStream_t s, double work);
+// One launch for a line-buffer pass whose versions to build fit one product
+// launch: the product operands of the n_built versions (bdesc: their line
+// descriptors, group_tones per version, and ranges: their tile rows, both
+// read in place from pinned memory) into d_work, and the staging of the
+// descriptors sdesc[0 .. n_sdesc) to sdst and of raw_bytes (a multiple of 16)
+// from raw_src to raw_dst, as launch_plb_stage does.
+hipError_t launch_plb_prep(const awg_plan *p, uint32_t method, const PlbDesc *bdesc, int32_t n_built,
+                           int32_t group_tones, uint64_t L, const int2 *ranges, void *d_work, const PlbDesc *sdesc,
+                           int32_t n_sdesc, uint64_t n0, ToneDev *sdst, const void *raw_src, void *raw_dst,
+                           size_t raw_bytes, hipStream_t s);
 // Multiplexed channels: items[c] (c < n, n <= kMaxChannels) each cover the same
 // count samples; one launch, items passed by value.
 constexpr int kMaxChannels = 4;

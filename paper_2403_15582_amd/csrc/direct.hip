@@ -23,6 +23,7 @@
 #include <mutex>
 
 #include "awg_internal.h"
+#include "plb_stage.h"
 #include "prof_launch.h"
 
 namespace awg {
@@ -1225,38 +1226,8 @@ __global__ __launch_bounds__(256) void plb_stage_kernel(const PlbDesc *__restric
                                                         const uint4 *__restrict__ raw_src, uint4 *__restrict__ raw_dst,
                                                         uint64_t n16)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (uint64_t i = tid; i < (uint64_t)n_desc; i += stride) {
-        const PlbDesc d = desc[i];
-        ToneDev t;
-        if (d.src >= 0) {
-            t = plan_tones[d.src];
-        } else {
-            t.p0 = t.p1 = d.p + kPhaseBias;
-            t.f0 = t.f1 = d.f;
-            t.a = UINT64_MAX;
-            t.coef = 0;
-            t.n = 0;
-            t.amp = t.amp1 = d.a;
-            t.shape = AWG_RAMP_NONE;
-            t.table = 0;
-            t.ashape = AWG_RAMP_NONE;
-            t.pad = 0;
-            t.b = 0;
-            t.m = 0;
-        }
-        if (d.lo_row >= 0) {
-            t.lo = n0 + (uint64_t)d.lo_row * kTileSamples;
-            t.hi = n0 + (uint64_t)d.hi_row * kTileSamples + (kTileSamples - 1);
-        } else {
-            t.lo = 1;
-            t.hi = 0;
-        }
-        if (i < (uint64_t)n_first) dst_first[i] = t;
-        else dst_rest[i - (uint64_t)n_first] = t;
-    }
-    for (uint64_t i = tid; i < n16; i += stride) raw_dst[i] = raw_src[i];
+    plb_stage_range(desc, n_first, n_desc, plan_tones, n0, dst_first, dst_rest, raw_src, raw_dst, n16,
+                    (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x);
 }
 
 hipError_t launch_plb_stage(const PlbDesc *desc, int32_t n_first, int32_t n_desc, const ToneDev *plan_tones,

@@ -734,7 +734,16 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     }
     // the previous pass's work (S, the cache) precedes this one on s
     if (b.last_slot >= 0 && b.last_stream != s) e = hipStreamWaitEvent(s, b.slots[b.last_slot].done, 0);
-    if (e == hipSuccess)
+    // one product launch's worth of versions: their operands are made from the
+    // descriptors in place, in the launch that stages the rest; else the build
+    // list is staged too and the operands made per product launch
+    const bool prep = n_built > 0 && n_built <= kBuildBatch;
+    if (e == hipSuccess && prep)
+        e = launch_plb_prep(p, b.method, (const PlbDesc *)slot.mapped, n_built, kGroupTones, b.L,
+                            (const int2 *)((const char *)slot.mapped + h_raw + r_g), b.d_bwork,
+                            (const PlbDesc *)slot.mapped + n_be, n_direct, n0, (ToneDev *)(db + d_dir),
+                            (const char *)slot.mapped + h_raw, db + d_raw, raw, s);
+    else if (e == hipSuccess)
         e = launch_plb_stage((const PlbDesc *)slot.mapped, n_be, n_be + n_direct, p->d_tones, n0, (ToneDev *)db,
                              (ToneDev *)(db + d_dir), (const char *)slot.mapped + h_raw, db + d_raw, raw, s);
     if (e == hipSuccess && !b.s_zeroed) {
@@ -755,8 +764,8 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
                     (double)std::min<uint64_t>(b.L, (uint64_t)cnt << kTileLog2);
         }
         e = launch_group_sums(p, b.method, (const ToneDev *)db + (size_t)i * kGroupTones, nb, kGroupTones, b.L,
-                              b.d_bwork, b.d_Q, (const int32_t *)dr + i, (const int2 *)(dr + r_g) + i, max_tiles, s,
-                              work);
+                              b.d_bwork, b.d_Q, (const int32_t *)dr + i, (const int2 *)(dr + r_g) + i, max_tiles, prep,
+                              s, work);
     }
     // S to the call's next versions, then the call; a call of exactly one
     // period folds in the kernels that read S (each m is read once)

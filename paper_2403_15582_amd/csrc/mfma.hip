@@ -32,6 +32,7 @@
 #include <type_traits>
 
 #include "awg_internal.h"
+#include "plb_stage.h"
 #include "prof_launch.h"
 
 namespace awg {
@@ -230,6 +231,77 @@ __global__ __launch_bounds__(256) void gen_ab_kernel(const ToneDev *__restrict__
     } else {
         gen_b_at<T>(tones, nullptr, n_entries, n_groups, cb_n, b_hi, b_lo, nullptr,
                     (int64_t)(bx - a_blocks) * blockDim.x + threadIdx.x);
+    }
+}
+
+// A line-buffer pass's preparation in one launch. Workgroup g < n_gen takes
+// the group g of 4 line descriptors of the versions to build (read once from
+// pinned memory: p, f and amplitude of each line) and writes the A operand of
+// its rows on the tile rows its version is made on, and the B operand of its
+// columns, with the arithmetic of gen_ab_kernel on staged records (rows of
+// 1024 samples from 0), so the operands are the same. The other workgroups
+// stage the pass (plb_stage_range) for the kernels that follow the product.
+template <typename T>
+__global__ __launch_bounds__(256) void plb_prep_kernel(const PlbDesc *__restrict__ bdesc, int32_t n_gen,
+                                                       int32_t groups_per_slice, const int2 *__restrict__ ranges,
+                                                       int32_t rb_pad, int32_t cb_n, T *__restrict__ a_hi,
+                                                       T *__restrict__ a_lo, T *__restrict__ b_hi,
+                                                       T *__restrict__ b_lo, const PlbDesc *__restrict__ sdesc,
+                                                       int32_t n_sdesc, const ToneDev *__restrict__ plan_tones,
+                                                       uint64_t n0, ToneDev *__restrict__ sdst,
+                                                       const uint4 *__restrict__ raw_src, uint4 *__restrict__ raw_dst,
+                                                       uint64_t n16)
+{
+    typedef typename Split<T>::vec V;
+    const int32_t bx = (int32_t)blockIdx.x;
+    if (bx >= n_gen) {
+        plb_stage_range(sdesc, 0, n_sdesc, plan_tones, n0, sdst, sdst, raw_src, raw_dst, n16,
+                        (uint64_t)(bx - n_gen) * blockDim.x + threadIdx.x,
+                        (uint64_t)(gridDim.x - (uint32_t)n_gen) * blockDim.x);
+        return;
+    }
+    const int32_t g = bx;
+    uint64_t P[4], Fw[4];
+    float amp[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const PlbDesc d = bdesc[4 * g + t];
+        P[t] = d.p;
+        Fw[t] = d.f;
+        amp[t] = d.a;
+    }
+    const int2 rr = ranges[g / groups_per_slice];
+    const int32_t kb = g >> 1, half = 32 * (g & 1);
+    const int32_t r1 = min((rr.x + rr.y) * 256, rb_pad * 32);
+    for (int32_t c = rr.x * 256 + (int32_t)threadIdx.x; c < r1; c += 256) {
+        const uint64_t n = (uint64_t)c * kTileSamples;
+        V hv, lv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float sn, co;
+            word_sincos(P[t] + Fw[t] * n, sn, co);
+            const float xs = amp[t] * sn, xc = amp[t] * co;
+            T h, l;
+            Split<T>::run(xs, h, l); hv[2 * t] = h; lv[2 * t] = l;
+            Split<T>::run(xc, h, l); hv[2 * t + 1] = h; lv[2 * t + 1] = l;
+        }
+        const int64_t off = ((int64_t)kb * rb_pad + (c >> 5)) * 64 + (c & 31) + half;
+        ((V *)a_hi)[off] = hv;
+        ((V *)a_lo)[off] = lv;
+    }
+    for (int32_t m = (int32_t)threadIdx.x; m < cb_n * 32; m += 256) {
+        V hv, lv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float xs, xc;
+            word_sincos(Fw[t] * (uint64_t)m, xs, xc);
+            T h, l;
+            Split<T>::run(xc, h, l); hv[2 * t] = h; lv[2 * t] = l;
+            Split<T>::run(xs, h, l); hv[2 * t + 1] = h; lv[2 * t + 1] = l;
+        }
+        const int64_t off = ((int64_t)kb * cb_n + (m >> 5)) * 64 + (m & 31) + half;
+        ((V *)b_hi)[off] = hv;
+        ((V *)b_lo)[off] = lv;
     }
 }
 
@@ -751,7 +823,7 @@ size_t group_work_bytes(int32_t n_built, int32_t group_tones, uint64_t L)
 template <typename T>
 static hipError_t group_run(const awg_plan *p, const ToneDev *d_list, int32_t n_built, int32_t group_tones,
                             uint64_t L, char *w, float *q_base, const int32_t *d_plane_map, const int2 *d_ranges,
-                            int32_t max_tiles, hipStream_t s, double work)
+                            int32_t max_tiles, bool operands_ready, hipStream_t s, double work)
 {
     static_assert(kTileRB * 32 == 256, "a workgroup of gen_ab makes one tile row of A");
     const bool f16 = std::is_same<T, _Float16>::value;
@@ -759,8 +831,8 @@ static hipError_t group_run(const awg_plan *p, const ToneDev *d_list, int32_t n_
     T *b_hi = (T *)w, *b_lo = (T *)(w + g.b_bytes);
     T *a_hi = (T *)(w + 2 * g.b_bytes), *a_lo = (T *)(w + 2 * g.b_bytes + g.a_bytes);
     const int32_t n_entries = n_built * group_tones;
-    hipError_t e;
-    {
+    hipError_t e = hipSuccess;
+    if (!operands_ready) {
         // A: 2 kb_n groups of 4 tones x rb_pad * 32 rows; B: the same groups x cb_n * 32 columns
         const int64_t a_per_group = (int64_t)g.rb_pad * 32 / 256;
         const int64_t a_blocks = a_per_group * (2 * g.kb_n);
@@ -784,18 +856,57 @@ static hipError_t group_run(const awg_plan *p, const ToneDev *d_list, int32_t n_
 
 hipError_t launch_group_sums(const awg_plan *p, uint32_t method, const ToneDev *d_list, int32_t n_built,
                              int32_t group_tones, uint64_t L, void *d_work, float *q_base,
-                             const int32_t *d_plane_map, const int2 *d_ranges, int32_t max_tiles, hipStream_t s,
-                             double work)
+                             const int32_t *d_plane_map, const int2 *d_ranges, int32_t max_tiles,
+                             bool operands_ready, hipStream_t s, double work)
 {
     if (n_built <= 0) return hipSuccess;
     if (group_tones % 8 != 0 || L < kTileSamples || L % kTileSamples != 0 || n_built > 65535)
         return hipErrorInvalidValue;
     if (method == AWG_F_METHOD_MFMA_F16X3)
         return group_run<_Float16>(p, d_list, n_built, group_tones, L, (char *)d_work, q_base, d_plane_map, d_ranges,
-                                   max_tiles, s, work);
+                                   max_tiles, operands_ready, s, work);
     if (method == AWG_F_METHOD_MFMA_BF16X3)
         return group_run<__bf16>(p, d_list, n_built, group_tones, L, (char *)d_work, q_base, d_plane_map, d_ranges,
-                                 max_tiles, s, work);
+                                 max_tiles, operands_ready, s, work);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t plb_prep_run(const awg_plan *p, const PlbDesc *bdesc, int32_t n_built, int32_t group_tones,
+                               uint64_t L, const int2 *ranges, char *w, const PlbDesc *sdesc, int32_t n_sdesc,
+                               uint64_t n0, ToneDev *sdst, const void *raw_src, void *raw_dst, uint64_t n16,
+                               hipStream_t s)
+{
+    const bool f16 = std::is_same<T, _Float16>::value;
+    const GroupGeom g = group_geometry(n_built, group_tones, L);
+    T *b_hi = (T *)w, *b_lo = (T *)(w + g.b_bytes);
+    T *a_hi = (T *)(w + 2 * g.b_bytes), *a_lo = (T *)(w + 2 * g.b_bytes + g.a_bytes);
+    const int32_t n_gen = n_built * (group_tones / 4);
+    const uint64_t stage = std::max<uint64_t>((uint64_t)n_sdesc, n16);
+    const uint64_t n_stage = std::min<uint64_t>(std::max<uint64_t>((stage + 255) / 256, 1), 1024);
+    ProfScope prof(p->ctx, s, f16 ? "plb_prep_f16" : "plb_prep_bf16");
+    prof.launch(plb_prep_kernel<T>, dim3((uint32_t)(n_gen + (int64_t)n_stage)), dim3(256), 0, bdesc, n_gen,
+                group_tones / 4, ranges, g.rb_pad, g.cb_n, a_hi, a_lo, b_hi, b_lo, sdesc, n_sdesc, p->d_tones, n0,
+                sdst, (const uint4 *)raw_src, (uint4 *)raw_dst, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_plb_prep(const awg_plan *p, uint32_t method, const PlbDesc *bdesc, int32_t n_built,
+                           int32_t group_tones, uint64_t L, const int2 *ranges, void *d_work, const PlbDesc *sdesc,
+                           int32_t n_sdesc, uint64_t n0, ToneDev *sdst, const void *raw_src, void *raw_dst,
+                           size_t raw_bytes, hipStream_t s)
+{
+    if (n_built <= 0 || group_tones % 8 != 0 || L < kTileSamples || L % kTileSamples != 0 || n_sdesc < 0)
+        return hipErrorInvalidValue;
+    if (((uintptr_t)raw_src | (uintptr_t)raw_dst | raw_bytes) & 15) return hipErrorInvalidValue;
+    if ((int64_t)n_built * (group_tones / 4) + 1024 > INT32_MAX) return hipErrorInvalidValue;
+    const uint64_t n16 = raw_bytes / 16;
+    if (method == AWG_F_METHOD_MFMA_F16X3)
+        return plb_prep_run<_Float16>(p, bdesc, n_built, group_tones, L, ranges, (char *)d_work, sdesc, n_sdesc, n0,
+                                      sdst, raw_src, raw_dst, n16, s);
+    if (method == AWG_F_METHOD_MFMA_BF16X3)
+        return plb_prep_run<__bf16>(p, bdesc, n_built, group_tones, L, ranges, (char *)d_work, sdesc, n_sdesc, n0,
+                                    sdst, raw_src, raw_dst, n16, s);
     return hipErrorInvalidValue;
 }
 
