@@ -511,7 +511,7 @@ void sort_part(LineBuf &lb, const awg_plan *p, std::vector<PlbDesc> *v)
 // One pass of at most kPiece samples. *split: the pass needs more than kMaxSegs
 // segments and nothing was done (the caller halves it).
 awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32, hipStream_t s,
-                bool *split)
+                bool through, bool *split)
 {
     *split = false;
     const uint64_t rows = (count + kRow - 1) / kRow;
@@ -576,10 +576,12 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
         if (windowed && t.hi >= n0) b.live2.push_back(i);
         const bool meets = windowed && t.hi >= n0 && t.lo <= last;
         // the line the tone is on at the call's last row: none while its
-        // windows are open there (it runs on the direct kernel)
-        const Line nx = !windowed || last < t.lo ? line_of(t.p0 - kPhaseBias, t.f0, t.amp)
-                        : last > t.hi             ? line_of(t.p1 - kPhaseBias, t.f1, t.amp1)
-                                                  : kNoLine;
+        // windows are open there (it runs on the direct kernel); without
+        // `through`, none for every tone whose windows meet the call (its window
+        // rows then need no segment)
+        const Line nx = !windowed || last < t.lo    ? line_of(t.p0 - kPhaseBias, t.f0, t.amp)
+                        : last > t.hi && (through || !meets) ? line_of(t.p1 - kPhaseBias, t.f1, t.amp1)
+                                                     : kNoLine;
         if (nx != b.next[k]) {
             b.next[k] = nx;
             b.dirty[k / kGroupTones] = 1;
@@ -881,9 +883,16 @@ static awg_status run(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int1
                       hipStream_t s)
 {
     bool split = false;
-    awg_status st = pass(p, b, n0, count, out_i16, out_f32, s, &split);
+    awg_status st = pass(p, b, n0, count, out_i16, out_f32, s, true, &split);
     if (st != AWG_OK || !split) return st;
     const uint64_t rows = (count + kRow - 1) / kRow;
+    if (rows <= 1) {
+        // one row cannot be halved: without the after-window lines it has no
+        // segments at all
+        st = pass(p, b, n0, count, out_i16, out_f32, s, false, &split);
+        if (st == AWG_OK && split) st = AWG_E_UNSUPPORTED;
+        return st;
+    }
     const uint64_t half = rows / 2 * kRow;
     st = run(p, b, n0, half, out_i16, out_f32, s);
     if (st != AWG_OK) return st;
