@@ -172,6 +172,12 @@ struct awg_plan {
     struct Slot { void *host; void *mapped; hipEvent_t done; bool used; };
     std::vector<Slot> slots;
     size_t next_slot;
+    // a line-buffer plan's retune records staged in slot pend_slot (pend_n of
+    // them) and not yet applied to d_tones: the next line-buffer pass applies
+    // them in its first launch, any other call that reads d_tones first
+    int32_t pend_slot = -1;
+    int32_t pend_n = 0;
+    std::mutex pend_mu;
     // duplicate-tone check of one retune or amplitude call: ev_stamp[tone] ==
     // ev_gen marks a tone already named in the call being validated
     std::vector<uint32_t> ev_stamp;
@@ -190,6 +196,14 @@ struct awg_plan {
 };
 
 namespace awg {
+
+// Pending retune records of a plan (line-buffer plans defer them). flush_tones
+// applies them on s (scatter kernel) if any; take_pending_tones hands them to
+// a launch that applies them itself (*slot = -1: none), after which
+// pending_tones_applied(p, slot, s) marks the slot in use until s passes it.
+awg_status flush_tones(awg_plan *p, hipStream_t s);
+void take_pending_tones(awg_plan *p, const void **mapped, int32_t *n, int32_t *slot);
+awg_status pending_tones_applied(awg_plan *p, int32_t slot, hipStream_t s);
 
 // Exact word arithmetic (plan.cpp)
 bool rne_ratio_shift(double num, double den, int shift, uint64_t *out);
@@ -407,13 +421,12 @@ hipError_t launch_group_sums(const awg_plan *p, uint32_t method, const ToneDev *
 // One launch for a line-buffer pass whose versions to build fit one product
 // launch: the product operands of the n_built versions (bdesc: their line
 // descriptors, group_tones per version, and ranges: their tile rows, both
-// read in place from pinned memory) into d_work, and the staging of the
-// descriptors sdesc[0 .. n_sdesc) to sdst and of raw_bytes (a multiple of 16)
-// from raw_src to raw_dst, as launch_plb_stage does.
+// read in place from pinned memory) into d_work, the copy of raw_bytes (a
+// multiple of 16) from raw_src to raw_dst, and the n_rec retune
+// records at rec (ScatterRecord, pinned) applied to the plan's device table.
 hipError_t launch_plb_prep(const awg_plan *p, uint32_t method, const PlbDesc *bdesc, int32_t n_built,
-                           int32_t group_tones, uint64_t L, const int2 *ranges, void *d_work, const PlbDesc *sdesc,
-                           int32_t n_sdesc, uint64_t n0, ToneDev *sdst, const void *raw_src, void *raw_dst,
-                           size_t raw_bytes, hipStream_t s);
+                           int32_t group_tones, uint64_t L, const int2 *ranges, void *d_work, const void *raw_src,
+                           void *raw_dst, size_t raw_bytes, const void *rec, int32_t n_rec, hipStream_t s);
 // Multiplexed channels: items[c] (c < n, n <= kMaxChannels) each cover the same
 // count samples; one launch, items passed by value.
 constexpr int kMaxChannels = 4;

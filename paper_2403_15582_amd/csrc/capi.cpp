@@ -190,7 +190,34 @@ bool seen_tone(awg_plan *p, int32_t t)
 
 }  // namespace
 
+static awg_status flush_locked(awg_plan *p, hipStream_t s);
+
 namespace awg {
+
+awg_status flush_tones(awg_plan *p, hipStream_t s)
+{
+    std::lock_guard<std::mutex> g(p->pend_mu);
+    return flush_locked(p, s);
+}
+
+void take_pending_tones(awg_plan *p, const void **mapped, int32_t *n, int32_t *slot)
+{
+    std::lock_guard<std::mutex> g(p->pend_mu);
+    *slot = p->pend_slot;
+    *n = p->pend_slot >= 0 ? p->pend_n : 0;
+    *mapped = p->pend_slot >= 0 ? p->slots[(size_t)p->pend_slot].mapped : nullptr;
+    p->pend_slot = -1;
+    p->pend_n = 0;
+}
+
+awg_status pending_tones_applied(awg_plan *p, int32_t slot, hipStream_t s)
+{
+    std::lock_guard<std::mutex> g(p->pend_mu);
+    auto &sl = p->slots[(size_t)slot];
+    const hipError_t e = hipEventRecord(sl.done, s);
+    sl.used = true;
+    return hip_status(e);
+}
 
 // Device table of a smooth shape, shared through the context.
 awg_status get_table(awg_ctx *ctx, int32_t shape, uint64_t n, const uint64_t **d_out)
@@ -582,6 +609,20 @@ static awg_status ensure_retune_slots(awg_plan *p)
     return AWG_OK;
 }
 
+// The pending records applied on s (p->pend_mu held).
+static awg_status flush_locked(awg_plan *p, hipStream_t s)
+{
+    if (p->pend_slot < 0) return AWG_OK;
+    auto &slot = p->slots[(size_t)p->pend_slot];
+    hipError_t e = launch_scatter_tones(p->d_tones, slot.mapped, p->pend_n, s);
+    if (e == hipSuccess) e = hipEventRecord(slot.done, s);
+    if (e != hipSuccess) return hip_status(e);
+    slot.used = true;
+    p->pend_slot = -1;
+    p->pend_n = 0;
+    return AWG_OK;
+}
+
 static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, hipStream_t s)
 {
     if (p->plb) {
@@ -596,11 +637,17 @@ static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, 
     // the block table is rebuilt by the next call that reads it: the line-buffer
     // path (a stream of retunes and chunks) never does
     p->blocks_stale = true;
-    // stage the new records and scatter them on the stream
+    // stage the new records; scatter them on the stream now, or (line-buffer
+    // plans) leave them to the next call's first launch
     hipError_t e = hipSetDevice(p->ctx->device);
     if (e != hipSuccess) return hip_status(e);
     awg_status st = ensure_retune_slots(p);
     if (st != AWG_OK) return st;
+    std::unique_lock<std::mutex> pend(p->pend_mu, std::defer_lock);
+    if (p->plb) {
+        pend.lock();
+        if ((st = flush_locked(p, s)) != AWG_OK) return st;       // one pending call at a time
+    }
     const size_t si = p->next_slot;
     p->next_slot = (p->next_slot + 1) % kSlots;
     auto &slot = p->slots[si];
@@ -613,6 +660,12 @@ static awg_status push_tones(awg_plan *p, const int32_t *changed, int32_t n_ev, 
         rec[i].index = (uint32_t)p->inv[changed[i]];
         rec[i].pad = 0;
         rec[i].tone = p->dev_mirror[p->inv[changed[i]]];
+    }
+    if (p->plb) {
+        slot.used = false;
+        p->pend_slot = (int32_t)si;
+        p->pend_n = n_ev;
+        return AWG_OK;
     }
     e = launch_scatter_tones(p->d_tones, slot.mapped, n_ev, s);
     if (e == hipSuccess) e = hipEventRecord(slot.done, s);
@@ -650,11 +703,13 @@ static awg_status sync_blocks(awg_plan *p, hipStream_t s)
 static awg_status synth_any(awg_plan *p, uint32_t method, uint64_t n0, uint64_t count, int16_t *out_i16,
                             float *out_f32, hipStream_t s)
 {
-    if (method != AWG_F_METHOD_DIRECT) {
-        if (p->n_ramped == 0) return mfma_static(p, method, n0, count, out_i16, out_f32, s);
-        if (count >= kHybridMin) return hybrid_synth(p, method, n0, count, out_i16, out_f32, s);
-    }
-    const awg_status st = sync_blocks(p, s);
+    // (the hybrid path applies pending retune records itself)
+    if (method != AWG_F_METHOD_DIRECT && p->n_ramped > 0 && count >= kHybridMin)
+        return hybrid_synth(p, method, n0, count, out_i16, out_f32, s);
+    awg_status st = flush_tones(p, s);
+    if (st != AWG_OK) return st;
+    if (method != AWG_F_METHOD_DIRECT && p->n_ramped == 0) return mfma_static(p, method, n0, count, out_i16, out_f32, s);
+    st = sync_blocks(p, s);
     if (st != AWG_OK) return st;
     return hip_status(out_f32 ? launch_direct_f32(p, n0, count, out_f32, s) : launch_direct_i16(p, n0, count, out_i16, s));
 }
@@ -690,6 +745,7 @@ awg_status awg_synth_static(awg_plan *p, uint64_t n0, uint64_t count, int16_t *d
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
     if ((st = check_out(p, d_out, count, sizeof(int16_t))) != AWG_OK) return st;
+    if ((st = flush_tones(p, (hipStream_t)hip_stream)) != AWG_OK) return st;
     const uint32_t method = p->params.flags & AWG_F_METHOD_MASK;
     if (method == AWG_F_METHOD_DIRECT) {
         if ((st = sync_blocks(p, (hipStream_t)hip_stream)) != AWG_OK) return st;
@@ -774,8 +830,10 @@ awg_status awg_synth_multiplex(awg_plan *const *plans, int32_t n_channels, uint6
     if (count == 0) return AWG_OK;
     if (count > UINT64_MAX / (uint64_t)n_channels) return AWG_E_INVALID;
     if ((st = check_out(plans[0], d_out, count * (uint64_t)n_channels, sizeof(int16_t))) != AWG_OK) return st;
-    for (int32_t c = 0; c < n_channels; ++c)
+    for (int32_t c = 0; c < n_channels; ++c) {
+        if ((st = flush_tones(plans[c], (hipStream_t)hip_stream)) != AWG_OK) return st;
         if ((st = sync_blocks(plans[c], (hipStream_t)hip_stream)) != AWG_OK) return st;
+    }
     ProfScope prof(plans[0]->ctx, (hipStream_t)hip_stream, "mux_kernel");
     for (int32_t c = 0; c < n_channels; ++c) prof.add_work((double)plans[c]->n_tones * (double)count);
     return hip_status(launch_mux(items, n_channels, count, (hipStream_t)hip_stream, prof));
@@ -804,6 +862,7 @@ awg_status awg_peak(awg_plan *p, uint64_t n0, uint64_t count, float *d_scratch, 
     if ((st = check_out(p, d_scratch, count, sizeof(float))) != AWG_OK) return st;
     if ((st = check_out(p, d_peak, 1, sizeof(float))) != AWG_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
+    if ((st = flush_tones(p, s)) != AWG_OK) return st;
     if ((st = sync_blocks(p, s)) != AWG_OK) return st;
     hipError_t e = launch_direct_f32(p, n0, count, d_scratch, s);
     if (e == hipSuccess) e = launch_peak(d_scratch, count, d_peak, s);
@@ -821,8 +880,9 @@ awg_status awg_peak_noalloc(awg_plan *p, uint64_t n0, uint64_t count, float *d_p
     float *scr = p->ctx->noalloc_scratch;      // this device's copy, never the symbol itself
     if (!scr) return AWG_E_HIP;
     hipStream_t s = (hipStream_t)hip_stream;
-    // after a retune (whose call set up the staging slots) the block table is
-    // staged in one of them: no allocation here either
+    // after a retune (whose call set up the staging slots) its pending records
+    // and the block table are staged in them: no allocation here either
+    if ((st = flush_tones(p, s)) != AWG_OK) return st;
     if ((st = sync_blocks(p, s)) != AWG_OK) return st;
     hipError_t e = launch_direct_f32(p, n0, count, scr, s, false);
     if (e == hipSuccess) e = launch_peak(scr, count, d_peak, s);
@@ -838,6 +898,7 @@ awg_status awg_phase_dump(awg_plan *p, int32_t tone, uint64_t n0, uint64_t count
     if ((st = check_range(n0, count)) != AWG_OK) return st;
     if (count == 0) return AWG_OK;
     if ((st = check_out(p, d_words, count, sizeof(uint64_t))) != AWG_OK) return st;
+    if ((st = flush_tones(p, (hipStream_t)hip_stream)) != AWG_OK) return st;
     return hip_status(launch_phase_dump(p, p->inv[tone], n0, count, d_words, (hipStream_t)hip_stream));
 }
 

@@ -973,8 +973,8 @@ __global__ __launch_bounds__(64) void phase_dump_kernel(const ToneDev *__restric
 __global__ void scatter_tones_kernel(ToneDev *__restrict__ tones, const ScatterRecord *__restrict__ rec,
                                      int32_t n)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) tones[rec[i].index] = rec[i].tone;
+    plb_scatter_range(tones, rec, n, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                      (uint64_t)gridDim.x * blockDim.x);
 }
 
 constexpr int kS = 16;                             // samples per lane

@@ -425,6 +425,10 @@ awg_status hybrid_synth(awg_plan *p, uint32_t method, uint64_t n0, uint64_t coun
 {
     if (plb_eligible(p)) return plb_synth(p, method, n0, count, out_i16, out_f32, s);
     if (p->n_tones >= (int32_t)(1u << kLineShift)) return AWG_E_UNSUPPORTED;
+    {
+        const awg_status st = flush_tones(p, s);
+        if (st != AWG_OK) return st;
+    }
     if (!p->hyb) {
         try { p->hyb = new HybridState(); } catch (...) { return AWG_E_NOMEM; }
     }

@@ -190,7 +190,8 @@ size_t max_entries(const LineBuf &b) { return (size_t)(b.n_groups + kMaxSegs) * 
 size_t raw_cap(const LineBuf &b)
 {
     const size_t ng = (size_t)b.n_groups, K = (size_t)b.K, nb = ng + kMaxSegs, rows = kPiece / kRow;
-    return align_up(sizeof(int32_t) * nb, 256) + align_up(sizeof(int32_t) * 2 * nb, 256) +
+    return align_up(sizeof(ToneDev) * K, 256) + align_up(sizeof(int32_t) * nb, 256) +
+           align_up(sizeof(int32_t) * 2 * nb, 256) +
            align_up(sizeof(Block) * (2 * K + 1), 256) +
            align_up(sizeof(PlbItem) * (rows + kMaxParts), 256) + align_up(sizeof(PlbPiece) * kMaxPieces, 256) +
            align_up(sizeof(int32_t) * 2 * (2 * K + 1), 256) +
@@ -508,6 +509,38 @@ void sort_part(LineBuf &lb, const awg_plan *p, std::vector<PlbDesc> *v)
     v->swap(lb.dsorted);
 }
 
+// The synthesis record of an entry of the direct list, as the staging kernel
+// makes it from the descriptor: a plan tone (the host mirror of the plan's
+// device table) or a static line, with the window rows from n0.
+ToneDev direct_record(const awg_plan *p, const PlbDesc &d, uint64_t n0)
+{
+    ToneDev t;
+    if (d.src >= 0) {
+        t = p->dev_mirror[d.src];
+    } else {
+        t.p0 = t.p1 = d.p + kPhaseBias;
+        t.f0 = t.f1 = d.f;
+        t.a = UINT64_MAX;
+        t.coef = 0;
+        t.n = 0;
+        t.amp = t.amp1 = d.a;
+        t.shape = AWG_RAMP_NONE;
+        t.table = 0;
+        t.ashape = AWG_RAMP_NONE;
+        t.pad = 0;
+        t.b = 0;
+        t.m = 0;
+    }
+    if (d.lo_row >= 0) {
+        t.lo = n0 + (uint64_t)d.lo_row * kTileSamples;
+        t.hi = n0 + (uint64_t)d.hi_row * kTileSamples + (kTileSamples - 1);
+    } else {
+        t.lo = 1;
+        t.hi = 0;
+    }
+    return t;
+}
+
 // One pass of at most kPiece samples. *split: the pass needs more than kMaxSegs
 // segments and nothing was done (the caller halves it).
 awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *out_i16, float *out_f32, hipStream_t s,
@@ -684,14 +717,18 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     // host blob: descriptors (build list, then direct list) | raw part
     // device blob: build records | direct records | raw part
     // raw part: build map | blocks | work items | pieces | split tiles | segments | folds
+    // With the prep launch (below) the direct list goes as records made here,
+    // at the head of the raw part, and no descriptor of it is staged.
     const int32_t n_built = (int32_t)b.build_map.size();
+    const bool prep = n_built > 0 && n_built <= kBuildBatch;
     const int32_t n_be = (int32_t)b.build_list.size();
     const int32_t n_direct = (int32_t)b.direct.size();
     const int32_t n_seg = (int32_t)b.segs.size();
     const int32_t n_fold = (int32_t)b.fold_slots.size();
     const int32_t n_items = (int32_t)b.items.size();
     const int32_t n_split = (int32_t)b.splits.size();
-    const size_t r_g = align_up(sizeof(int32_t) * (size_t)n_built, 256);
+    const size_t r_m = prep ? align_up(sizeof(ToneDev) * (size_t)n_direct, 256) : 0;
+    const size_t r_g = r_m + align_up(sizeof(int32_t) * (size_t)n_built, 256);
     const size_t r_b = r_g + align_up(sizeof(int32_t) * 2 * (size_t)n_built, 256);
     const size_t r_o = r_b + align_up(sizeof(Block) * b.blocks.size(), 256);
     const size_t r_p = r_o + align_up(sizeof(PlbItem) * (size_t)n_items, 256);
@@ -700,7 +737,7 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     const size_t r_s = r_y + align_up(sizeof(int32_t) * b.span.size(), 256);
     const size_t r_f = r_s + align_up(sizeof(PlbSeg) * (size_t)n_seg, 256);
     const size_t raw = align_up(r_f + sizeof(PlbFold) * (size_t)n_fold, 16);
-    const size_t h_raw = align_up(sizeof(PlbDesc) * (size_t)(n_be + n_direct), 256);
+    const size_t h_raw = align_up(sizeof(PlbDesc) * (size_t)(n_be + (prep ? 0 : n_direct)), 256);
     const size_t d_dir = align_up(sizeof(ToneDev) * (size_t)n_be, 256);
     const size_t d_raw = align_up(d_dir + sizeof(ToneDev) * (size_t)n_direct, 256);
     LineBuf::Slot &slot = b.slots[b.next_slot];
@@ -714,9 +751,14 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     char *db = (char *)slot.dev;
     PlbDesc *hd = (PlbDesc *)hb;
     if (n_be) std::memcpy(hd, b.build_list.data(), sizeof(PlbDesc) * (size_t)n_be);
-    if (n_direct) std::memcpy(hd + n_be, b.direct.data(), sizeof(PlbDesc) * (size_t)n_direct);
     char *hr = hb + h_raw;
-    if (n_built) std::memcpy(hr, b.build_map.data(), sizeof(int32_t) * (size_t)n_built);
+    if (prep) {
+        ToneDev *dr_h = (ToneDev *)hr;
+        for (int32_t i = 0; i < n_direct; ++i) dr_h[i] = direct_record(p, b.direct[i], n0);
+    } else if (n_direct) {
+        std::memcpy(hd + n_be, b.direct.data(), sizeof(PlbDesc) * (size_t)n_direct);
+    }
+    if (n_built) std::memcpy(hr + r_m, b.build_map.data(), sizeof(int32_t) * (size_t)n_built);
     if (n_built) std::memcpy(hr + r_g, b.build_rng.data(), sizeof(int32_t) * 2 * (size_t)n_built);
     std::memcpy(hr + r_b, b.blocks.data(), sizeof(Block) * b.blocks.size());
     std::memcpy(hr + r_o, b.items.data(), sizeof(PlbItem) * (size_t)n_items);
@@ -737,17 +779,27 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
     // the previous pass's work (S, the cache) precedes this one on s
     if (b.last_slot >= 0 && b.last_stream != s) e = hipStreamWaitEvent(s, b.slots[b.last_slot].done, 0);
     // one product launch's worth of versions: their operands are made from the
-    // descriptors in place, in the launch that stages the rest; else the build
-    // list is staged too and the operands made per product launch
-    const bool prep = n_built > 0 && n_built <= kBuildBatch;
-    if (e == hipSuccess && prep)
+    // descriptors in place, in the launch that stages the rest and applies a
+    // retune's pending records to the plan's device table (nothing in that
+    // launch reads the table); else the pending records are applied first, the
+    // build list is staged too and the operands made per product launch
+    if (e == hipSuccess && prep) {
+        const void *rec = nullptr;
+        int32_t n_rec = 0, rec_slot = -1;
+        take_pending_tones(p, &rec, &n_rec, &rec_slot);
         e = launch_plb_prep(p, b.method, (const PlbDesc *)slot.mapped, n_built, kGroupTones, b.L,
                             (const int2 *)((const char *)slot.mapped + h_raw + r_g), b.d_bwork,
-                            (const PlbDesc *)slot.mapped + n_be, n_direct, n0, (ToneDev *)(db + d_dir),
-                            (const char *)slot.mapped + h_raw, db + d_raw, raw, s);
-    else if (e == hipSuccess)
+                            (const char *)slot.mapped + h_raw, db + d_raw, raw, rec, n_rec, s);
+        if (rec_slot >= 0) {
+            const awg_status st = pending_tones_applied(p, rec_slot, s);
+            if (e == hipSuccess && st != AWG_OK) return st;
+        }
+    } else if (e == hipSuccess) {
+        const awg_status st = flush_tones(p, s);
+        if (st != AWG_OK) return st;
         e = launch_plb_stage((const PlbDesc *)slot.mapped, n_be, n_be + n_direct, p->d_tones, n0, (ToneDev *)db,
                              (ToneDev *)(db + d_dir), (const char *)slot.mapped + h_raw, db + d_raw, raw, s);
+    }
     if (e == hipSuccess && !b.s_zeroed) {
         e = launch_plb_zero(b.d_S, b.L, s);
         if (e == hipSuccess) e = launch_plb_zero((int64_t *)b.d_cnt, kCntWords, s);
@@ -766,15 +818,16 @@ awg_status pass(awg_plan *p, LineBuf &b, uint64_t n0, uint64_t count, int16_t *o
                     (double)std::min<uint64_t>(b.L, (uint64_t)cnt << kTileLog2);
         }
         e = launch_group_sums(p, b.method, (const ToneDev *)db + (size_t)i * kGroupTones, nb, kGroupTones, b.L,
-                              b.d_bwork, b.d_Q, (const int32_t *)dr + i, (const int2 *)(dr + r_g) + i, max_tiles, prep,
-                              s, work);
+                              b.d_bwork, b.d_Q, (const int32_t *)(dr + r_m) + i, (const int2 *)(dr + r_g) + i, max_tiles,
+                              prep, s, work);
     }
     // S to the call's next versions, then the call; a call of exactly one
     // period folds in the kernels that read S (each m is read once)
     const bool fused = count == b.L;
     if (e == hipSuccess && !fused) e = launch_plb_fold(p, b.d_S, b.L, (const PlbFold *)(dr + r_f), n_fold, s);
     if (e == hipSuccess)
-        e = launch_plb(p, (const ToneDev *)(db + d_dir), (const Block *)(dr + r_b), (const PlbItem *)(dr + r_o), n_items,
+        e = launch_plb(p, prep ? (const ToneDev *)dr : (const ToneDev *)(db + d_dir), (const Block *)(dr + r_b),
+                       (const PlbItem *)(dr + r_o), n_items,
                        (const PlbPiece *)(dr + r_p), (const int2 *)(dr + r_y), b.d_part, (const PlbSplit *)(dr + r_x),
                        b.d_cnt, n_split, n0, count, b.d_S, b.L, (const PlbSeg *)(dr + r_s), n_seg,
                        (const PlbFold *)(dr + r_f), fused ? n_fold : 0, out_i16, out_f32, s, direct_work);

@@ -240,24 +240,26 @@ __global__ __launch_bounds__(256) void gen_ab_kernel(const ToneDev *__restrict__
 // its rows on the tile rows its version is made on, and the B operand of its
 // columns, with the arithmetic of gen_ab_kernel on staged records (rows of
 // 1024 samples from 0), so the operands are the same. The other workgroups
-// stage the pass (plb_stage_range) for the kernels that follow the product.
+// copy the pass's staged blob (its records made on the host) and apply a
+// retune's records to the plan's device table, which nothing else in the
+// launch reads.
 template <typename T>
 __global__ __launch_bounds__(256) void plb_prep_kernel(const PlbDesc *__restrict__ bdesc, int32_t n_gen,
                                                        int32_t groups_per_slice, const int2 *__restrict__ ranges,
                                                        int32_t rb_pad, int32_t cb_n, T *__restrict__ a_hi,
                                                        T *__restrict__ a_lo, T *__restrict__ b_hi,
-                                                       T *__restrict__ b_lo, const PlbDesc *__restrict__ sdesc,
-                                                       int32_t n_sdesc, const ToneDev *__restrict__ plan_tones,
-                                                       uint64_t n0, ToneDev *__restrict__ sdst,
-                                                       const uint4 *__restrict__ raw_src, uint4 *__restrict__ raw_dst,
-                                                       uint64_t n16)
+                                                       T *__restrict__ b_lo, const uint4 *__restrict__ raw_src,
+                                                       uint4 *__restrict__ raw_dst, uint64_t n16,
+                                                       const ScatterRecord *__restrict__ rec, int32_t n_rec,
+                                                       ToneDev *__restrict__ plan_tones)
 {
     typedef typename Split<T>::vec V;
     const int32_t bx = (int32_t)blockIdx.x;
     if (bx >= n_gen) {
-        plb_stage_range(sdesc, 0, n_sdesc, plan_tones, n0, sdst, sdst, raw_src, raw_dst, n16,
-                        (uint64_t)(bx - n_gen) * blockDim.x + threadIdx.x,
-                        (uint64_t)(gridDim.x - (uint32_t)n_gen) * blockDim.x);
+        const uint64_t tid = (uint64_t)(bx - n_gen) * blockDim.x + threadIdx.x;
+        const uint64_t stride = (uint64_t)(gridDim.x - (uint32_t)n_gen) * blockDim.x;
+        plb_stage_range(nullptr, 0, 0, nullptr, 0, nullptr, nullptr, raw_src, raw_dst, n16, tid, stride);
+        plb_scatter_range(plan_tones, rec, n_rec, tid, stride);
         return;
     }
     const int32_t g = bx;
@@ -873,40 +875,39 @@ hipError_t launch_group_sums(const awg_plan *p, uint32_t method, const ToneDev *
 
 template <typename T>
 static hipError_t plb_prep_run(const awg_plan *p, const PlbDesc *bdesc, int32_t n_built, int32_t group_tones,
-                               uint64_t L, const int2 *ranges, char *w, const PlbDesc *sdesc, int32_t n_sdesc,
-                               uint64_t n0, ToneDev *sdst, const void *raw_src, void *raw_dst, uint64_t n16,
-                               hipStream_t s)
+                               uint64_t L, const int2 *ranges, char *w, const void *raw_src, void *raw_dst,
+                               uint64_t n16, const void *rec, int32_t n_rec, hipStream_t s)
 {
     const bool f16 = std::is_same<T, _Float16>::value;
     const GroupGeom g = group_geometry(n_built, group_tones, L);
     T *b_hi = (T *)w, *b_lo = (T *)(w + g.b_bytes);
     T *a_hi = (T *)(w + 2 * g.b_bytes), *a_lo = (T *)(w + 2 * g.b_bytes + g.a_bytes);
     const int32_t n_gen = n_built * (group_tones / 4);
-    const uint64_t stage = std::max<uint64_t>((uint64_t)n_sdesc, n16);
+    const uint64_t stage = std::max<uint64_t>((uint64_t)n_rec, n16);
     const uint64_t n_stage = std::min<uint64_t>(std::max<uint64_t>((stage + 255) / 256, 1), 1024);
     ProfScope prof(p->ctx, s, f16 ? "plb_prep_f16" : "plb_prep_bf16");
     prof.launch(plb_prep_kernel<T>, dim3((uint32_t)(n_gen + (int64_t)n_stage)), dim3(256), 0, bdesc, n_gen,
-                group_tones / 4, ranges, g.rb_pad, g.cb_n, a_hi, a_lo, b_hi, b_lo, sdesc, n_sdesc, p->d_tones, n0,
-                sdst, (const uint4 *)raw_src, (uint4 *)raw_dst, n16);
+                group_tones / 4, ranges, g.rb_pad, g.cb_n, a_hi, a_lo, b_hi, b_lo, (const uint4 *)raw_src,
+                (uint4 *)raw_dst, n16, (const ScatterRecord *)rec, n_rec, p->d_tones);
     return hipGetLastError();
 }
 
 hipError_t launch_plb_prep(const awg_plan *p, uint32_t method, const PlbDesc *bdesc, int32_t n_built,
-                           int32_t group_tones, uint64_t L, const int2 *ranges, void *d_work, const PlbDesc *sdesc,
-                           int32_t n_sdesc, uint64_t n0, ToneDev *sdst, const void *raw_src, void *raw_dst,
-                           size_t raw_bytes, hipStream_t s)
+                           int32_t group_tones, uint64_t L, const int2 *ranges, void *d_work, const void *raw_src,
+                           void *raw_dst, size_t raw_bytes, const void *rec, int32_t n_rec, hipStream_t s)
 {
-    if (n_built <= 0 || group_tones % 8 != 0 || L < kTileSamples || L % kTileSamples != 0 || n_sdesc < 0)
+    if (n_built <= 0 || group_tones % 8 != 0 || L < kTileSamples || L % kTileSamples != 0 || n_rec < 0 ||
+        (n_rec > 0 && !rec))
         return hipErrorInvalidValue;
     if (((uintptr_t)raw_src | (uintptr_t)raw_dst | raw_bytes) & 15) return hipErrorInvalidValue;
     if ((int64_t)n_built * (group_tones / 4) + 1024 > INT32_MAX) return hipErrorInvalidValue;
     const uint64_t n16 = raw_bytes / 16;
     if (method == AWG_F_METHOD_MFMA_F16X3)
-        return plb_prep_run<_Float16>(p, bdesc, n_built, group_tones, L, ranges, (char *)d_work, sdesc, n_sdesc, n0,
-                                      sdst, raw_src, raw_dst, n16, s);
+        return plb_prep_run<_Float16>(p, bdesc, n_built, group_tones, L, ranges, (char *)d_work, raw_src, raw_dst,
+                                      n16, rec, n_rec, s);
     if (method == AWG_F_METHOD_MFMA_BF16X3)
-        return plb_prep_run<__bf16>(p, bdesc, n_built, group_tones, L, ranges, (char *)d_work, sdesc, n_sdesc, n0,
-                                    sdst, raw_src, raw_dst, n16, s);
+        return plb_prep_run<__bf16>(p, bdesc, n_built, group_tones, L, ranges, (char *)d_work, raw_src, raw_dst,
+                                    n16, rec, n_rec, s);
     return hipErrorInvalidValue;
 }
 

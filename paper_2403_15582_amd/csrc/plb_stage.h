@@ -1,6 +1,7 @@
 // Staging of a line-buffer pass on the device (HIP sources only): descriptor
-// records to synthesis records, and the plain copy of the pass's raw part, as a
-// grid-stride loop over threads tid .. of stride.
+// records to synthesis records, the plain copy of the pass's raw part, and a
+// retune's records to the plan's table, as grid-stride loops over threads
+// tid .. of stride.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -48,6 +49,13 @@ __device__ __forceinline__ void plb_stage_range(const PlbDesc *__restrict__ desc
         else dst_rest[i - (uint64_t)n_first] = t;
     }
     for (uint64_t i = tid; i < n16; i += stride) raw_dst[i] = raw_src[i];
+}
+
+// A retune's records to the plan's device table: tones[rec[i].index] = rec[i].tone.
+__device__ __forceinline__ void plb_scatter_range(ToneDev *__restrict__ tones, const ScatterRecord *__restrict__ rec,
+                                                  int32_t n, uint64_t tid, uint64_t stride)
+{
+    for (uint64_t i = tid; i < (uint64_t)n; i += stride) tones[rec[i].index] = rec[i].tone;
 }
 
 }  // namespace awg

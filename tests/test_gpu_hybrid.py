@@ -234,6 +234,76 @@ def test_one_period_calls_at_odd_offsets(method):
         compare(q[ns], y[ns], qo, yo, "one-period call at n0=%d (sampled %d)" % (n0, len(ns)))
 
 
+def test_retune_records_reach_every_reader():
+    """A plan on the line buffer leaves a retune's records to the next call that
+    reads its device tone table: the line buffer's own pass applies them in its
+    first launch, and every other reader (direct method, peak, phase words,
+    multiplexed output) applies them first. After each retune the plan's output
+    through that reader equals a direct-method plan retuned the same way."""
+    torch = need_gpu()
+    w = W.array_group_chirps(K=2000, seconds=0.02)
+    hp, dp = _plans(w, BF16)
+    C = w.chunk
+    events = sorted(w.retunes, key=lambda e: e[1])
+    i = 0
+
+    def retune_upto(end):
+        nonlocal i
+        batch = []
+        while i < len(events) and events[i][1] < end:
+            k, a, n, shape, f = events[i]
+            batch.append((k, shape, a, n, f))
+            i += 1
+        if batch:
+            hp.retune(batch)
+            dp.retune(batch)
+        return len(batch)
+
+    retune_upto(C)
+    a, b = hp.stream_next(C)[1], dp.stream_next(C)[1]          # the line buffer now exists
+    torch.cuda.synchronize()
+    assert int(np.abs(to_np(a).astype(np.int32) - to_np(b)).max()) <= TOL_Q
+    # direct method on the line-buffer plan
+    assert retune_upto(2 * C) > 0
+    say("pending records: direct-method call")
+    ya = hp.synth_f32(C, C, method=awg.AWG_F_METHOD_DIRECT)
+    yb = dp.synth_f32(C, C, method=awg.AWG_F_METHOD_DIRECT)
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yb)
+    # peak
+    assert retune_upto(3 * C) > 0
+    say("pending records: peak")
+    scr = torch.empty(C, dtype=torch.float32, device="cuda")
+    pk = torch.zeros(2, dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    awg.awg_peak(hp.handle, 2 * C, C, scr.data_ptr(), pk.data_ptr(), s)
+    awg.awg_peak(dp.handle, 2 * C, C, scr.data_ptr(), pk.data_ptr() + 4, s)
+    torch.cuda.synchronize()
+    assert pk[0].item() == pk[1].item()
+    # phase words of a retuned tone
+    assert retune_upto(4 * C) > 0
+    k = events[i - 1][0]
+    say("pending records: phase words of tone %d" % k)
+    wa, wb = hp.phase_dump(k, 3 * C, C), dp.phase_dump(k, 3 * C, C)
+    torch.cuda.synchronize()
+    assert torch.equal(wa, wb)
+    # multiplexed output
+    assert retune_upto(5 * C) > 0
+    say("pending records: multiplexed channels")
+    m = awg.multiplex([hp, dp], 4 * C, C)
+    torch.cuda.synchronize()
+    assert torch.equal(m[:, 0], m[:, 1])
+    # and the line buffer's own pass, after a retune and after none
+    for c in (5, 6):
+        retune_upto((c + 1) * C)
+        say("pending records: line-buffer chunk %d" % c)
+        hp.seek(c * C)
+        dp.seek(c * C)
+        a, b = hp.stream_next(C)[1], dp.stream_next(C)[1]
+        torch.cuda.synchronize()
+        assert int(np.abs(to_np(a).astype(np.int32) - to_np(b)).max()) <= TOL_Q, c
+
+
 def test_static_plan_chirp_call_uses_matrix_cores():
     torch = need_gpu()
     w = W.static_100tone_chunk()
