@@ -580,8 +580,8 @@ awg_status awg_plan_amplitude(awg_plan *p, const awg_amp_ramp *ev, int32_t n_ev,
 
 // Device copy of the tones changed on the host (caller indices), in stream order:
 // their records are written to a pinned slot that the scatter kernel reads in
-// place, and the rebuilt block table is uploaded from the same slot by a kernel
-// (no DMA engine in the chain).
+// place (for a plan on the line buffer, later: see flush_tones), and the rebuilt
+// block table is uploaded from a slot by a kernel (no DMA engine in the chain).
 // The retune staging slots, all at once on first use (or awg_plan_reserve);
 // when an allocation fails none are kept, so a later call starts over.
 static awg_status ensure_retune_slots(awg_plan *p)

@@ -263,7 +263,7 @@ struct PlbIn {
     uint32_t row;                // this tile's row in the call
     // one part of a split tile: only the pieces pieces[0 .. n_pieces) (piece j
     // on wave j mod 4), and the tile's sum goes to partial[0 .. 64 S) without
-    // the line tones and the rounding (the combine kernel adds them)
+    // the line tones and the rounding (added by the part that finishes last)
     const PlbPiece *pieces;      // nullptr: every block, then the full epilogue
     uint32_t n_pieces;
     float *partial;

@@ -31,6 +31,10 @@
 //    rows with one version adds Q(row version) - Q(next version)
 //    ("segments").
 // The direct kernel adds, per tile, S, the segments and its own sum, and rounds.
+// Versions that only segments need are made on the tile rows of the period
+// (2^18 samples each) their segments cover. A one-row pass that would need more
+// segments than a pass takes runs with next lines of none for every tone whose
+// windows meet it (no segments at all).
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -363,8 +367,8 @@ awg_status setup(LineBuf &b, const awg_plan *p, uint32_t method)
 // so the costliest rows would set the launch time: rows above 1.5 times the
 // mean are split into parts of kPartPieces pieces (one per wave), a piece
 // being a block or, for a block with a window edge in the row, kPieceTones of
-// its tones; the parts run first and write partial sums that the combine
-// kernel adds in part order. Whole rows follow, costliest first: those that
+// its tones; the parts run first and write partial sums, which the part that
+// finishes last adds in part order. Whole rows follow, costliest first: those that
 // find no free slot start when the first parts end, so small parts keep the
 // launch near the time of one whole row. Costs are
 // multiples of 1/2, so the order is a counting sort on twice the cost, rows of
