@@ -171,7 +171,10 @@ awg_status awg_ramp_table(int32_t shape, uint64_t n, uint64_t *out);
 /* Append chirps to tones of a planned stream (Streaming pathway with groups of
  * tones chirped in turn). The device tables are updated in stream order on
  * hip_stream: synthesis enqueued earlier on that stream sees the old tones,
- * synthesis enqueued later the new ones. A tone keeps one window on the device,
+ * synthesis enqueued later the new ones. (A plan that has run on the periodic
+ * line buffer, a ramped plan on bins with a matrix-core method, stages the
+ * update and leaves it to the next call that reads its tones, which applies it
+ * first on that call's stream.) A tone keeps one window on the device,
  * so after a retune its samples are exact from the end of its previous window
  * on (the new window must not start earlier); samples before that end are no
  * longer reproducible from this plan. At most one event per tone per call.
