@@ -156,6 +156,52 @@ def test_array_group_chirps_stream_against_direct_and_oracle(method):
     say("array hybrid: all %d chunks within %d LSB of the direct method" % (n_chunks, TOL_Q))
 
 
+def test_array_full_second_line_buffer_against_direct_and_oracle():
+    """The benchmark's headline workload for one whole second: 10,000 tones, a
+    group of 100 retuned every 1 ms, 268 chunks of 2^20 on the BF16 line buffer
+    (the configuration the benchmark times) beside the direct method, every
+    sample of every chunk within 1 LSB of it, and five chunks sampled against
+    the oracle with the unquantised sum."""
+    torch = need_gpu()
+    w = W.array_group_chirps(K=10000)
+    hp, dp = _plans(w, BF16)
+    op = words.Plan(w.fs_hz, w.gain_lsb, w.period_log2, w.tones, build_tables=False)
+    events = sorted(w.retunes, key=lambda e: e[1])
+    n_chunks = w.count // w.chunk
+    picks = {1, 67, 133, 200, n_chunks - 1}
+    say("array K=10000 line buffer, %d chunks, %d retunes" % (n_chunks, len(events)))
+    worst, differ, i = 0, 0, 0
+    for c in range(n_chunks):
+        end = (c + 1) * w.chunk
+        batch = []
+        while i < len(events) and events[i][1] < end:
+            k, a, n, shape, f = events[i]
+            batch.append((k, shape, a, n, f))
+            op.add_ramp(k, a, n, shape, f)
+            i += 1
+        if batch:
+            hp.retune(batch)
+            dp.retune(batch)
+        n0, qh = hp.stream_next(w.chunk)
+        _, qd = dp.stream_next(w.chunk)
+        yh = hp.synth_f32(n0, w.chunk, method=BF16) if c in picks else None
+        torch.cuda.synchronize()
+        a, b = to_np(qh), to_np(qd)
+        dq = np.abs(a.astype(np.int32) - b)
+        worst = max(worst, int(dq.max()))
+        differ += int((dq > 0).sum())
+        assert worst <= TOL_Q, c
+        if c in picks:
+            rng = np.random.default_rng(c)
+            ns = np.unique(np.concatenate([rng.integers(0, w.chunk, 400), [0, w.chunk - 1],
+                                           [e[1] - n0 + d for e in events for d in (-1, 0, 1, e[2])
+                                            if 0 <= e[1] - n0 + d < w.chunk][:200]]))
+            qo, yo = csynth.synth_at(op, ns + n0)
+            compare(a[ns], to_np(yh)[ns], qo, yo, "array line buffer chunk %d (sampled %d)" % (c, len(ns)))
+    say("array line buffer: %d chunks within %d LSB of the direct method (%d samples differ)"
+        % (n_chunks, worst, differ))
+
+
 def test_array_stream_period_longer_than_chunk():
     """The array stream on bins of 2^22 streamed in 2^20-sample chunks: each
     call covers a quarter of the period (S folded by its own launch), group
