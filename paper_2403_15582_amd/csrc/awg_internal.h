@@ -137,7 +137,6 @@ struct awg_ctx {
     std::mutex prof_mu;
     std::map<std::string, uint64_t> prof_seen;   // launches per kernel since enable
     std::vector<awg::ProfRecord> prof_pending;
-    std::vector<hipEvent_t> prof_pool;
     std::map<std::string, awg::ProfTotal> prof_totals;
     // smooth-ramp tables shared by all plans of the context, keyed by (shape, N)
     std::map<std::pair<int32_t, uint64_t>, awg::Table> tables;

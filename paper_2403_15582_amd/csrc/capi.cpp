@@ -301,7 +301,6 @@ void awg_ctx_destroy(awg_ctx *ctx)
         (void)hipEventDestroy(r.start);
         (void)hipEventDestroy(r.stop);
     }
-    for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 

@@ -14,14 +14,12 @@ namespace awg {
 // next awg_profile_read folds the held ones into the totals
 constexpr size_t kMaxPending = 65536;
 
-static hipEvent_t take_event(awg_ctx *c)
+// A fresh pair of events per timed launch, destroyed once read: an event that
+// already took a launch's timestamps and is handed to hipExtLaunchKernel again
+// stalls that dispatch (by up to a millisecond) and returns a wrong interval.
+static hipEvent_t take_event()
 {
     hipEvent_t e = nullptr;
-    if (!c->prof_pool.empty()) {
-        e = c->prof_pool.back();
-        c->prof_pool.pop_back();
-        return e;
-    }
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
@@ -35,10 +33,10 @@ ProfScope::ProfScope(awg_ctx *ctx, hipStream_t s, const char *name)
     std::lock_guard<std::mutex> g(ctx_->prof_mu);
     if (ctx_->prof_seen[name_]++ % (uint64_t)period != 0) return;
     if (ctx_->prof_pending.size() >= kMaxPending) return;
-    start_ = take_event(ctx_);
-    stop_ = start_ ? take_event(ctx_) : nullptr;
+    start_ = take_event();
+    stop_ = start_ ? take_event() : nullptr;
     if (!stop_ && start_) {
-        ctx_->prof_pool.push_back(start_);
+        (void)hipEventDestroy(start_);
         start_ = nullptr;
     }
 }
@@ -48,8 +46,8 @@ ProfScope::~ProfScope()
     if (!stop_) return;
     std::lock_guard<std::mutex> g(ctx_->prof_mu);
     if (!launched_) {
-        ctx_->prof_pool.push_back(start_);
-        ctx_->prof_pool.push_back(stop_);
+        (void)hipEventDestroy(start_);
+        (void)hipEventDestroy(stop_);
         return;
     }
     ctx_->prof_pending.push_back(ProfRecord{name_, start_, stop_, work_});
@@ -87,8 +85,8 @@ awg_status awg_profile_read(awg_ctx *ctx, awg_kernel_stat *out, int32_t max_stat
         t.total_ms += ms;
         t.work += r.work;
         if (ms > t.max_ms) t.max_ms = ms;
-        ctx->prof_pool.push_back(r.start);
-        ctx->prof_pool.push_back(r.stop);
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
     }
     ctx->prof_pending.clear();
     int32_t i = 0;
