@@ -344,6 +344,19 @@ def awg_stream_next_multiplex(plans, count, d_out, stream=0):
     return n0.value
 
 
+def current_stream_handle(device, stream=None):
+    """The HIP stream handle for a call on `device`: `stream`'s, else that of
+    torch's current stream on the device (torch's own raw query, about ten
+    times cheaper per call than building a Stream object)."""
+    if stream is not None:
+        return stream.cuda_stream
+    import torch
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return raw(device)
+    return torch.cuda.current_stream(device).cuda_stream
+
+
 def multiplex(plans, n0, count, out=None, stream=None):
     """Channels of `plans` (Plan objects) interleaved into an int16 tensor of
     shape (count, len(plans)): out[i, c] is channel c's sample n0 + i."""
@@ -353,7 +366,7 @@ def multiplex(plans, n0, count, out=None, stream=None):
     if out.dtype != torch.int16 or not out.is_contiguous() or out.numel() < count * len(plans):
         raise ValueError("out must be a contiguous int16 tensor of at least %d elements" % (count * len(plans)))
     awg_synth_multiplex([p.handle for p in plans], n0, count, out.data_ptr(),
-                        (stream or torch.cuda.current_stream()).cuda_stream)
+                        current_stream_handle(plans[0].device, stream))
     return out
 
 
@@ -530,10 +543,8 @@ class Plan:
             raise ValueError("out must be a contiguous %s tensor of at least %d elements" % (dtype, count))
         return out
 
-    @staticmethod
-    def _stream(stream):
-        import torch
-        return (stream or torch.cuda.current_stream()).cuda_stream
+    def _stream(self, stream):
+        return current_stream_handle(self.device, stream)
 
     def synth_static(self, n0, count, out=None, stream=None):
         import torch

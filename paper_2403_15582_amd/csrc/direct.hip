@@ -307,6 +307,31 @@ __device__ __forceinline__ void plb_fold4(const PlbFold *folds, int32_t n_fold, 
     }
 }
 
+// A split tile's parts hand their partial sums to the part that finishes last,
+// which may run on another XCD, whose L2 is not coherent with this one's. The
+// sums travel as agent-scope relaxed atomic stores and loads, which are
+// coherent at device scope on their own, so no agent-scope fence (on this chip
+// a writeback or an invalidation of a whole L2, which stalls every workgroup
+// on it) is needed: a part's stores have completed before its workgroup counts
+// itself done, and the last part loads the sums after it has read that count.
+__device__ __forceinline__ void plb_put_partial(float *dst, const float (&y)[4])
+{
+    uint64_t *d = (uint64_t *)dst;
+    const uint64_t lo = (uint64_t)__float_as_uint(y[0]) | ((uint64_t)__float_as_uint(y[1]) << 32);
+    const uint64_t hi = (uint64_t)__float_as_uint(y[2]) | ((uint64_t)__float_as_uint(y[3]) << 32);
+    __hip_atomic_store(d, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(d + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float4 plb_get_partial(const float *src)
+{
+    uint64_t *s = (uint64_t *)src;
+    const uint64_t lo = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t hi = __hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float4(__uint_as_float((uint32_t)lo), __uint_as_float((uint32_t)(lo >> 32)),
+                       __uint_as_float((uint32_t)hi), __uint_as_float((uint32_t)(hi >> 32)));
+}
+
 // The line tones of samples tile0 + i0 .. i0 + PER - 1: S and the segments'
 // group differences at m = n mod L, in list order.
 template <int PER>
@@ -732,7 +757,7 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
             const uint32_t i = i0 + e;
             y[e] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
         }
-        *(float4 *)(plb.partial + i0) = make_float4(y[0], y[1], y[2], y[3]);
+        plb_put_partial(plb.partial + i0, y);
         __syncthreads();
         return;
     }
@@ -812,7 +837,7 @@ __device__ __forceinline__ void plb_finish(const PlbSplit sp, const float *__res
         float4 u[kBatch];
 #pragma unroll
         for (uint32_t q = 0; q < kBatch; ++q)
-            if (q0 + q < sp.n) u[q] = *(const float4 *)(pp + (size_t)(q0 + q) * T);
+            if (q0 + q < sp.n) u[q] = plb_get_partial(pp + (size_t)(q0 + q) * T);
 #pragma unroll
         for (uint32_t q = 0; q < kBatch; ++q) {
             if (q0 + q >= sp.n) break;
@@ -865,14 +890,15 @@ __global__ __launch_bounds__(256) void plb_kernel(const ToneDev *__restrict__ to
     synth_tile<S, F32OUT, false, true, true>(tones, blocks, tables, n0 + rel, valid, o, part,
                                              HybridIn{0, nullptr, 0}, 1, plb);
     if (!is_part) return;
-    // count the part done (its sums released first); the part that completes
-    // its tile acquires the others' sums and adds them
-    __threadfence();
+    // count the part done once every thread's partial stores have completed;
+    // the part that completes its tile loads the others' sums and adds them
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&counts[item.split], 1) == (int32_t)splits[item.split].n - 1;
+    if (threadIdx.x == 0)
+        last = __hip_atomic_fetch_add(&counts[item.split], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               (int32_t)splits[item.split].n - 1;
     __syncthreads();
     if (!last) return;
-    __threadfence();
     plb_finish<F32OUT>(splits[item.split], partials, n0, count, out, S_sum, mask, segs, n_seg, folds, n_fold);
     if (threadIdx.x == 0) counts[item.split] = 0;        // ready for the next launch
 }
