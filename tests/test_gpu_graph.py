@@ -64,3 +64,26 @@ def test_captured_chirp_synthesis_replays():
         assert np.array_equal(to_np(out), ref), rep
     del g
     p.close()
+
+
+def test_calls_follow_the_current_stream():
+    """With no stream given, a call goes on torch's current stream of the plan's
+    device (the binding's raw query names the same handle as torch's Stream
+    object, inside and outside a stream context), and its result is ordered on
+    that stream."""
+    torch = need_gpu()
+    w = W.static_100tone_chunk()
+    p = awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, awg.AWG_F_METHOD_DIRECT)
+    ref = to_np(p.synth_static(0, w.count))
+    assert awg.current_stream_handle(p.device) == torch.cuda.current_stream(p.device).cuda_stream
+    s = torch.cuda.Stream()
+    say("synthesis inside a stream context")
+    with torch.cuda.stream(s):
+        assert awg.current_stream_handle(p.device) == s.cuda_stream
+        assert awg.current_stream_handle(p.device, s) == s.cuda_stream
+        out = p.synth_static(0, w.count)
+        q = out.to(torch.int32)                       # a consumer on the same stream, no synchronisation
+    s.synchronize()
+    assert np.array_equal(q.cpu().numpy().astype(np.int16), ref)
+    assert awg.current_stream_handle(p.device) == torch.cuda.current_stream(p.device).cuda_stream
+    p.close()
