@@ -288,8 +288,10 @@ __global__ __launch_bounds__(256) void plb_prep_kernel(const PlbDesc *__restrict
             Split<T>::run(xc, h, l); hv[2 * t + 1] = h; lv[2 * t + 1] = l;
         }
         const int64_t off = ((int64_t)kb * rb_pad + (c >> 5)) * 64 + (c & 31) + half;
-        ((V *)a_hi)[off] = hv;
-        ((V *)a_lo)[off] = lv;
+        // the operands are read by the next launch only: stored non-temporal, so
+        // that this launch's end has no L2 full of them to write back
+        __builtin_nontemporal_store(hv, &((V *)a_hi)[off]);
+        __builtin_nontemporal_store(lv, &((V *)a_lo)[off]);
     }
     for (int32_t m = (int32_t)threadIdx.x; m < cb_n * 32; m += 256) {
         V hv, lv;
@@ -302,8 +304,8 @@ __global__ __launch_bounds__(256) void plb_prep_kernel(const PlbDesc *__restrict
             Split<T>::run(xs, h, l); hv[2 * t + 1] = h; lv[2 * t + 1] = l;
         }
         const int64_t off = ((int64_t)kb * cb_n + (m >> 5)) * 64 + (m & 31) + half;
-        ((V *)b_hi)[off] = hv;
-        ((V *)b_lo)[off] = lv;
+        __builtin_nontemporal_store(hv, &((V *)b_hi)[off]);
+        __builtin_nontemporal_store(lv, &((V *)b_lo)[off]);
     }
 }
 
