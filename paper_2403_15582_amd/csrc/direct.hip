@@ -276,6 +276,8 @@ struct PlbIn {
     int32_t n_fold;
 };
 
+typedef long long s64x2 __attribute__((ext_vector_type(2)));
+
 // fix(x) = x * 2^32 rounded to an integer (the fixed point of S)
 __device__ __forceinline__ int64_t plb_fix(float x) { return (int64_t)__builtin_rint((double)x * 0x1p32); }
 
@@ -345,8 +347,10 @@ __device__ __forceinline__ void plb_lines(const PlbIn &plb, uint64_t tile0, uint
             int64_t acc[4] = {0, 0, 0, 0};
             plb_fold4(plb.folds, plb.n_fold, m0, acc);
             sa.x += acc[0]; sa.y += acc[1]; sb.x += acc[2]; sb.y += acc[3];
-            *(longlong2 *)(plb.S + m0) = sa;
-            *(longlong2 *)(plb.S + m0 + 2) = sb;
+            // S is read again a whole pass later: stored non-temporal, so that
+            // the launch's end has no L2 full of it to write back
+            __builtin_nontemporal_store((s64x2){sa.x, sa.y}, (s64x2 *)(plb.S + m0));
+            __builtin_nontemporal_store((s64x2){sb.x, sb.y}, (s64x2 *)(plb.S + m0 + 2));
         }
         g[0] = (float)((double)sa.x * 0x1p-32);
         g[1] = (float)((double)sa.y * 0x1p-32);
