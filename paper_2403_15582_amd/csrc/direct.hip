@@ -766,15 +766,29 @@ __device__ __forceinline__ void synth_tile(const ToneDev *__restrict__ tones, co
         return;
     }
     if (PLB) plb_lines<PER>(plb, tile0, i0, valid, g);
+    int16_t *const o16 = (int16_t *)out + i0;
+    if (PLB && !F32OUT && ostride == 1 && i0 + PER <= valid && ((uintptr_t)o16 & 7) == 0) {
+        // a line-buffer thread's four codes in one 8-byte store, non-temporal:
+        // nothing in the pass reads the chunk back
+        uint64_t w = 0;
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-        const uint32_t i = i0 + e;
-        float y = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
-        if (HYB && hyb.n_add > 0) y = g[e] + y;
-        if (PLB) y = g[e] + y;
-        if (i < valid) {
-            if (F32OUT) ((float *)out)[(size_t)i * ostride] = y;
-            else ((int16_t *)out)[(size_t)i * ostride] = quantise(y);
+        for (int e = 0; e < PER; ++e) {
+            const uint32_t i = i0 + e;
+            const float y = g[e] + (((part[0][i] + part[1][i]) + part[2][i]) + part[3][i]);
+            w |= (uint64_t)(uint16_t)quantise(y) << (16 * e);
+        }
+        __builtin_nontemporal_store(w, (uint64_t *)o16);
+    } else {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const uint32_t i = i0 + e;
+            float y = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+            if (HYB && hyb.n_add > 0) y = g[e] + y;
+            if (PLB) y = g[e] + y;
+            if (i < valid) {
+                if (F32OUT) ((float *)out)[(size_t)i * ostride] = y;
+                else ((int16_t *)out)[(size_t)i * ostride] = quantise(y);
+            }
         }
     }
     __syncthreads();
