@@ -359,3 +359,40 @@ def test_static_plan_chirp_call_uses_matrix_cores():
     n0, c = p.stream_next(w.count)
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_line_buffer_output_at_unaligned_addresses():
+    """The line buffer writes a thread's four codes in one 8-byte store where the
+    destination allows it, else one code at a time: streams into an int16 view
+    two bytes off an 8-byte boundary and into one on it give the aligned
+    stream's codes chunk by chunk, and leave the elements around them alone."""
+    torch = need_gpu()
+    w = W.array_group_chirps(K=1000, seconds=0.012)
+    plans = [awg.Plan(w.tones, w.fs_hz, w.gain_lsb, w.period_log2, BF16) for _ in range(3)]
+    events = sorted(w.retunes, key=lambda e: e[1])
+    big = [torch.full((w.chunk + 8,), 7, dtype=torch.int16, device="cuda") for _ in range(2)]
+    views = [big[0][1:1 + w.chunk], big[1][4:4 + w.chunk]]
+    i = 0
+    for c in range(3):
+        end = (c + 1) * w.chunk
+        batch = []
+        while i < len(events) and events[i][1] < end:
+            k, a, n, shape, f = events[i]
+            batch.append((k, shape, a, n, f))
+            i += 1
+        for p in plans:
+            if batch:
+                p.retune(batch)
+        say("line buffer, chunk %d into offsets 0, 1 and 4 elements" % c)
+        _, q = plans[0].stream_next(w.chunk)
+        plans[1].stream_next(w.chunk, out=views[0])
+        plans[2].stream_next(w.chunk, out=views[1])
+        torch.cuda.synchronize()
+        ref = to_np(q)
+        for v in views:
+            assert np.array_equal(to_np(v), ref), c
+        b0, b1 = to_np(big[0]), to_np(big[1])
+        assert b0[0] == 7 and (b0[1 + w.chunk:] == 7).all()
+        assert (b1[:4] == 7).all() and (b1[4 + w.chunk:] == 7).all()
+    for p in plans:
+        p.close()
